@@ -1,0 +1,465 @@
+"""Plain CPU complex128 oracle for the QPINN circuit hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code with the HIP
+path (no kernels, tables, helpers or constants); the two meet only through the seeded inputs
+of ``workloads.py``.
+
+It follows the paper's definitions one step at a time, slowly and visibly:
+
+* angle embedding of each collocation point, with the five input scalings of eq. ``scale``
+  (section "QPINN architecture and ansatz designs") or random Fourier features
+  (section "PINN architecture and convergence enhancements", RFF item);
+* every gate is turned into its full 2^n x 2^n operator by an explicit Kronecker product
+  (dense ``np.kron`` for n <= 8, ``scipy.sparse.kron`` beyond) and applied, unfused and in
+  time order, to the state and to its three input-tangent states;
+* the Pauli-Z readout of each qubit (same section: each qubit acts as a neuron);
+* the TE_z Maxwell residuals and MSE losses (eqs. residual_1_vac, residual_1_diel,
+  residuals_2_and_3, phys_loss_vac, phys_loss_diel, mse, residual_1_intuitive);
+* parameter gradients of the loss by three independent routes: stored-state reverse mode,
+  the parameter-shift rule (section "QPINN architecture": the hardware-compatible method)
+  applied to the readouts, and central finite differences of the loss.
+
+Readings of the paper that it fixes (the paper does not define them):
+  R_P(theta) = exp(-i theta P / 2); qubit 0 is the leftmost Kronecker factor; the fields are
+  (E_z, H_x, H_y) = (<Z_{o0}>, <Z_{o1}>, <Z_{o2}>) for the first three output qubits.
+
+Precision: float64 / complex128 throughout; inputs given as float32 are upcast exactly.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+# gate / encoding / loss codes are data shared with the inputs module (numbers only)
+RX, RY, RZ, CNOT, CZ, CRZ = 0, 1, 2, 3, 4, 5
+ENC_CYCLE, ENC_ANGLES, ENC_RFF = 0, 1, 2
+ENC_RY, ENC_RX = 0, 1
+SCALE_NONE, SCALE_PI, SCALE_BIAS, SCALE_ASIN, SCALE_ACOS = 0, 1, 2, 3, 4
+LOSS_VACUUM, LOSS_DIEL_SPLIT, LOSS_DIEL_INTUITIVE = 0, 1, 2
+
+I2 = np.eye(2, dtype=np.complex128)
+PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+P0 = np.array([[1, 0], [0, 0]], dtype=np.complex128)
+P1 = np.array([[0, 0], [0, 1]], dtype=np.complex128)
+PAULI = {RX: PX, RY: PY, RZ: PZ}
+
+DENSE_MAX_N = 8
+
+
+# ---------------------------------------------------------------- gates -----------------------
+
+def rotation(kind: int, theta: float) -> np.ndarray:
+    """R_P(theta) = exp(-i theta P/2) = cos(theta/2) I - i sin(theta/2) P."""
+    return math.cos(theta / 2) * I2 - 1j * math.sin(theta / 2) * PAULI[kind]
+
+
+def rotation_derivative(kind: int, theta: float) -> np.ndarray:
+    """d/dtheta R_P(theta) = -(i/2) P R_P(theta)."""
+    return -0.5j * PAULI[kind] @ rotation(kind, theta)
+
+
+def _kron_list(factors, sparse: bool):
+    out = factors[0]
+    if sparse:
+        out = sp.csr_matrix(out)
+        for f in factors[1:]:
+            out = sp.kron(out, sp.csr_matrix(f), format="csr")
+        return out
+    for f in factors[1:]:
+        out = np.kron(out, f)
+    return out
+
+
+def full_operator(n: int, kind: int, q0: int, q1: int, theta: float | None,
+                  derivative: bool = False):
+    """The gate as a full 2^n x 2^n operator, built by an explicit Kronecker product.
+
+    Single-qubit: I (x) ... (x) U (x) ... (x) I with U in slot q0.
+    CNOT(c,t) = P0^(c) (x) I + P1^(c) (x) X^(t);  CZ(a,b) = P0^(a) (x) I + P1^(a) (x) Z^(b);
+    CRZ(c,t)  = P0^(c) (x) I + P1^(c) (x) RZ(theta)^(t).
+    With derivative=True the operator is d(gate)/d(theta) (parametrised gates only).
+    """
+    sparse = n > DENSE_MAX_N
+    if kind in (RX, RY, RZ):
+        U = rotation_derivative(kind, theta) if derivative else rotation(kind, theta)
+        return _kron_list([U if q == q0 else I2 for q in range(n)], sparse)
+    if kind in (CNOT, CZ, CRZ):
+        if kind == CNOT:
+            T = PX
+        elif kind == CZ:
+            T = PZ
+        else:
+            T = rotation_derivative(RZ, theta) if derivative else rotation(RZ, theta)
+        zero_branch = [P0 if q == q0 else I2 for q in range(n)]
+        one_branch = [P1 if q == q0 else (T if q == q1 else I2) for q in range(n)]
+        if derivative:      # only the controlled branch depends on theta
+            return _kron_list(one_branch, sparse)
+        return _kron_list(zero_branch, sparse) + _kron_list(one_branch, sparse)
+    raise ValueError(f"unknown gate kind {kind}")
+
+
+def z_diagonal(n: int, i: int) -> np.ndarray:
+    """Diagonal of Z_i^full = I (x) .. (x) Z (slot i) (x) .. (x) I, by explicit Kronecker product."""
+    d = np.ones(1)
+    for q in range(n):
+        d = np.kron(d, np.array([1.0, -1.0]) if q == i else np.ones(2))
+    return d
+
+
+# ------------------------------------------------------------- encoding -----------------------
+
+def scale_value(kind: int, a):
+    """Input scalings, eq. scale: none, pi, bias, asin, acos."""
+    if kind == SCALE_NONE:
+        return a
+    if kind == SCALE_PI:
+        return math.pi * a
+    if kind == SCALE_BIAS:
+        return (a + 1.0) * math.pi / 2.0
+    if kind == SCALE_ASIN:
+        return np.arcsin(a) + math.pi / 2.0
+    if kind == SCALE_ACOS:
+        return np.arccos(a)
+    raise ValueError(kind)
+
+
+def scale_derivative(kind: int, a):
+    if kind == SCALE_NONE:
+        return np.ones_like(a)
+    if kind == SCALE_PI:
+        return np.full_like(a, math.pi)
+    if kind == SCALE_BIAS:
+        return np.full_like(a, math.pi / 2.0)
+    if kind == SCALE_ASIN:
+        return 1.0 / np.sqrt(1.0 - a * a)
+    if kind == SCALE_ACOS:
+        return -1.0 / np.sqrt(1.0 - a * a)
+    raise ValueError(kind)
+
+
+def encoding_angles(circ, points, angles=None, jac=None):
+    """theta [P,n] and J = d theta / d(t,x,y) [P,n,3] for every point (float64)."""
+    pts = np.asarray(points, dtype=np.float64)
+    P, n, enc = pts.shape[0], circ.n, circ.enc
+    if enc.kind == ENC_ANGLES:
+        return np.asarray(angles, np.float64).copy(), np.asarray(jac, np.float64).copy()
+    if enc.kind == ENC_CYCLE:
+        coords = enc.coords(n)
+        theta = np.empty((P, n))
+        J = np.zeros((P, n, 3))
+        for q in range(n):
+            a = pts[:, coords[q]]
+            theta[:, q] = scale_value(enc.scale, a)
+            J[:, q, coords[q]] = scale_derivative(enc.scale, a)
+        return theta, J
+    if enc.kind == ENC_RFF:
+        # phi = [cos(B p); sin(B p)] (fixed Gaussian B), theta = W phi
+        B = np.asarray(enc.rff_B, np.float64)          # [F,3]
+        W = np.asarray(enc.rff_W, np.float64)          # [n,2F]
+        proj = pts @ B.T                               # [P,F]
+        phi = np.concatenate([np.cos(proj), np.sin(proj)], axis=1)
+        theta = phi @ W.T
+        # d phi / d p: [P,2F,3]
+        dphi = np.concatenate([-np.sin(proj)[:, :, None] * B[None],
+                               np.cos(proj)[:, :, None] * B[None]], axis=1)
+        J = np.einsum("qf,pfc->pqc", W, dphi)
+        return theta, J
+    raise ValueError(enc.kind)
+
+
+def _embed_vectors(gate: int, theta):
+    """Single-qubit embedded state G(theta)|0> and its theta-derivative, for an array of angles."""
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    if gate == ENC_RY:
+        v = np.stack([c, s], -1).astype(np.complex128)
+        dv = np.stack([-0.5 * s, 0.5 * c], -1).astype(np.complex128)
+    else:   # RX: (cos, -i sin)
+        v = np.stack([c + 0j, -1j * s], -1)
+        dv = np.stack([-0.5 * s + 0j, -0.5j * c], -1)
+    return v, dv
+
+
+def initial_states(circ, theta, J):
+    """psi0 = kron_q G(theta_q)|0> and the tangents dpsi0_c = sum_q J_qc kron(.., dG_q|0>, ..).
+
+    Returns psi [2^n, P] and dpsi [3, 2^n, P] (one column per point)."""
+    P, n = theta.shape
+    v, dv = _embed_vectors(circ.enc.gate, theta)          # [P,n,2]
+    psi = np.zeros((2 ** n, P), np.complex128)
+    dpsi = np.zeros((3, 2 ** n, P), np.complex128)
+    for p in range(P):
+        factors = [v[p, q] for q in range(n)]
+        psi[:, p] = _kron_list(factors, False)
+        for q in range(n):
+            if not np.any(J[p, q] != 0.0):
+                continue
+            term = _kron_list([dv[p, q] if qq == q else v[p, qq] for qq in range(n)], False)
+            for c in range(3):
+                if J[p, q, c] != 0.0:
+                    dpsi[c, :, p] += J[p, q, c] * term
+    return psi, dpsi
+
+
+# ------------------------------------------------------------ simulation ----------------------
+
+def _param_angle(params, g):
+    kind, q0, q1, pi = g
+    return float(params[pi]) if pi >= 0 else None
+
+
+def operators(circ, params, derivative=False):
+    """Full operators for every gate, in time order (cached per call)."""
+    out = []
+    for g in circ.gates:
+        kind, q0, q1, pi = g
+        th = _param_angle(params, g)
+        if derivative and pi < 0:
+            out.append(None)
+        else:
+            out.append(full_operator(circ.n, kind, q0, q1, th, derivative))
+    return out
+
+
+def readout(circ, psi, dpsi):
+    """f_i = Re psi^H Z_i psi, g_ic = 2 Re psi^H Z_i dpsi_c for the output qubits."""
+    outs = circ.out_qubits
+    P = psi.shape[1]
+    f = np.zeros((P, len(outs)))
+    g = np.zeros((P, len(outs), 3))
+    for k, i in enumerate(outs):
+        z = z_diagonal(circ.n, i)[:, None]
+        f[:, k] = np.real(np.sum(np.conj(psi) * z * psi, axis=0))
+        for c in range(3):
+            g[:, k, c] = 2.0 * np.real(np.sum(np.conj(psi) * z * dpsi[c], axis=0))
+    return f, g
+
+
+def simulate(circ, params, points, angles=None, jac=None, chunk=256):
+    """Outputs f [P,m] and input tangents g [P,m,3] (float64)."""
+    params = np.asarray(params, np.float64)
+    theta, J = encoding_angles(circ, points, angles, jac)
+    ops = operators(circ, params)
+    P = theta.shape[0]
+    f = np.zeros((P, len(circ.out_qubits)))
+    g = np.zeros((P, len(circ.out_qubits), 3))
+    for s in range(0, P, chunk):
+        e = min(P, s + chunk)
+        psi, dpsi = initial_states(circ, theta[s:e], J[s:e])
+        for U in ops:
+            psi = U @ psi
+            for c in range(3):
+                dpsi[c] = U @ dpsi[c]
+        f[s:e], g[s:e] = readout(circ, psi, dpsi)
+    return f, g
+
+
+def final_states(circ, params, points, angles=None, jac=None):
+    params = np.asarray(params, np.float64)
+    theta, J = encoding_angles(circ, points, angles, jac)
+    psi, dpsi = initial_states(circ, theta, J)
+    for U in operators(circ, params):
+        psi = U @ psi
+        for c in range(3):
+            dpsi[c] = U @ dpsi[c]
+    return psi, dpsi
+
+
+# ------------------------------------------------------------------ loss ----------------------
+
+def maxwell_terms(g, points, desc):
+    """Residuals and per-point weights of the TE_z Maxwell loss.
+
+    With (E_z, H_x, H_y) the first three outputs and g[:, i, c] = d field_i / d coordinate c
+    (c = 0:t, 1:x, 2:y):
+      r1 = dE/dt - (1/eps)(dHy/dx - dHx/dy)   (eqs. residual_1_vac / residual_1_diel / intuitive)
+      r2 = dHx/dt + dE/dy,  r3 = dHy/dt - dE/dx  (eq. residuals_2_and_3)
+    Loss = sum_p w1_p r1_p^2 + (1/P) sum_p (r2_p^2 + r3_p^2), with
+      vacuum:      eps = 1, w1 = 1/P                                   (eq. phys_loss_vac)
+      split:       eps = 1, w1 = 1/N_vac for x < x_if;  eps = eps_r, w1 = 1/N_diel otherwise
+                   (eq. phys_loss_diel with eq. mse; an empty region contributes nothing)
+      intuitive:   eps(x) as above, w1 = 1/P                           (eq. phys_loss_intuitive)
+    """
+    pts = np.asarray(points, np.float64)
+    P = pts.shape[0]
+    diel = pts[:, 1] >= desc.x_interface
+    if desc.kind == LOSS_VACUUM:
+        eps = np.ones(P)
+        w1 = np.full(P, 1.0 / P)
+    else:
+        eps = np.where(diel, desc.eps_r, 1.0)
+        if desc.kind == LOSS_DIEL_SPLIT:
+            n_d = int(diel.sum())
+            n_v = P - n_d
+            w1 = np.where(diel, 1.0 / max(n_d, 1), 1.0 / max(n_v, 1))
+        else:
+            w1 = np.full(P, 1.0 / P)
+    w = np.full(P, 1.0 / P)
+    dE, dHx, dHy = g[:, 0, :], g[:, 1, :], g[:, 2, :]
+    r1 = dE[:, 0] - (dHy[:, 1] - dHx[:, 2]) / eps
+    r2 = dHx[:, 0] + dE[:, 2]
+    r3 = dHy[:, 0] - dE[:, 1]
+    return r1, r2, r3, eps, w1, w
+
+
+def maxwell_loss(g, points, desc):
+    r1, r2, r3, eps, w1, w = maxwell_terms(g, points, desc)
+    return float(np.sum(w1 * r1 ** 2) + np.sum(w * (r2 ** 2 + r3 ** 2)))
+
+
+def maxwell_seeds(g, points, desc):
+    """W[p, i, c] = d Loss / d g[p, i, c] (the loss is a quadratic form in g)."""
+    r1, r2, r3, eps, w1, w = maxwell_terms(g, points, desc)
+    W = np.zeros_like(g)
+    a = 2.0 * w1 * r1
+    W[:, 0, 0] += a
+    W[:, 2, 1] += -a / eps
+    W[:, 1, 2] += a / eps
+    b = 2.0 * w * r2
+    W[:, 1, 0] += b
+    W[:, 0, 2] += b
+    c = 2.0 * w * r3
+    W[:, 2, 0] += c
+    W[:, 0, 1] += -c
+    return W
+
+
+# --------------------------------------------------------------- gradients --------------------
+
+def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, chunk=None):
+    """d/dparams of  sum_p [ sum_i seeds_f[p,i] f_i + sum_ic seeds_g[p,i,c] g_ic ]  by plain
+    stored-state reverse mode: every intermediate state is kept, the adjoints are pulled back
+    through U^H, and each parametrised gate contributes
+        2 Re [ <dU psi_in, lam_out> + sum_c <dU dpsi_c,in, mu_c,out> ].
+    For the Maxwell loss pass seeds_f = 0 and seeds_g = maxwell_seeds(g)."""
+    params = np.asarray(params, np.float64)
+    theta, J = encoding_angles(circ, points, angles, jac)
+    ops = operators(circ, params)
+    dops = operators(circ, params, derivative=True)
+    n, P = circ.n, theta.shape[0]
+    if chunk is None:   # bound the stored history to about 1 GB
+        chunk = max(1, int(1e9 // (max(len(ops), 1) * 4 * 2 ** n * 16)))
+    zd = [z_diagonal(n, i)[:, None] for i in circ.out_qubits]
+    grad = np.zeros(circ.n_params)
+    for s in range(0, P, chunk):
+        e = min(P, s + chunk)
+        psi, dpsi = initial_states(circ, theta[s:e], J[s:e])
+        hist = []
+        for U in ops:
+            hist.append((psi, dpsi.copy()))
+            psi = U @ psi
+            dpsi = np.stack([U @ dpsi[c] for c in range(3)])
+        Wf = np.asarray(seeds_f[s:e]) if seeds_f is not None else np.zeros((e - s, len(zd)))
+        Wg = np.asarray(seeds_g[s:e])
+        lam = np.zeros_like(psi)
+        mu = np.zeros_like(dpsi)
+        for k, z in enumerate(zd):
+            lam += z * psi * Wf[None, :, k]
+            for c in range(3):
+                lam += z * dpsi[c] * Wg[None, :, k, c]
+                mu[c] += z * psi * Wg[None, :, k, c]
+        for idx in range(len(ops) - 1, -1, -1):
+            psi_in, dpsi_in = hist[idx]
+            kind, q0, q1, pi = circ.gates[idx]
+            if pi >= 0:
+                dU = dops[idx]
+                acc = np.sum(np.conj(dU @ psi_in) * lam)
+                for c in range(3):
+                    acc += np.sum(np.conj(dU @ dpsi_in[c]) * mu[c])
+                grad[pi] += 2.0 * np.real(acc)
+            UH = ops[idx].conj().T
+            lam = UH @ lam
+            mu = np.stack([UH @ mu[c] for c in range(3)])
+    return grad
+
+
+def maxwell_eval(circ, params, points, desc, angles=None, jac=None):
+    """Everything the fused hot path returns: f, g, loss and d loss / d params (reverse mode)."""
+    f, g = simulate(circ, params, points, angles, jac)
+    loss = maxwell_loss(g, points, desc)
+    W = maxwell_seeds(g, points, desc)
+    grad = grad_reverse(circ, params, points, None, W, angles, jac)
+    return f, g, loss, grad
+
+
+def grad_param_shift(circ, params, points, seeds_f, seeds_g, angles=None, jac=None):
+    """Same quantity as grad_reverse, by the parameter-shift rule applied to f and g:
+    d f / d theta_k = [f(theta_k + pi/2) - f(theta_k - pi/2)] / 2 (exact for exp(-i theta P/2)),
+    then contracted with the (fixed) seeds.  Valid when each parameter drives one gate."""
+    params = np.asarray(params, np.float64)
+    grad = np.zeros(circ.n_params)
+    for k in range(circ.n_params):
+        pp, pm = params.copy(), params.copy()
+        pp[k] += math.pi / 2
+        pm[k] -= math.pi / 2
+        fp, gp = simulate(circ, pp, points, angles, jac)
+        fm, gm = simulate(circ, pm, points, angles, jac)
+        df, dg = (fp - fm) / 2.0, (gp - gm) / 2.0
+        grad[k] = np.sum(dg * seeds_g)
+        if seeds_f is not None:
+            grad[k] += np.sum(df * seeds_f)
+    return grad
+
+
+def grad_fd_loss(circ, params, points, desc, h=1e-6, idx=None, angles=None, jac=None):
+    """Central finite differences of the Maxwell loss itself."""
+    params = np.asarray(params, np.float64)
+    idx = range(circ.n_params) if idx is None else idx
+    out = {}
+    for k in idx:
+        pp, pm = params.copy(), params.copy()
+        pp[k] += h
+        pm[k] -= h
+        _, gp = simulate(circ, pp, points, angles, jac)
+        _, gm = simulate(circ, pm, points, angles, jac)
+        out[k] = (maxwell_loss(gp, points, desc) - maxwell_loss(gm, points, desc)) / (2 * h)
+    return out
+
+
+def fd_tangents(circ, params, points, h=1e-5):
+    """Central finite differences of f in each input coordinate (the plain method's tangents)."""
+    pts = np.asarray(points, np.float64)
+    out = np.zeros((pts.shape[0], len(circ.out_qubits), 3))
+    for c in range(3):
+        pp, pm = pts.copy(), pts.copy()
+        pp[:, c] += h
+        pm[:, c] -= h
+        fp, _ = simulate(circ, params, pp)
+        fm, _ = simulate(circ, params, pm)
+        out[:, :, c] = (fp - fm) / (2 * h)
+    return out
+
+
+def encoding_shift_tangents(circ, params, points):
+    """Input tangents through the encoding's own parameter-shift rule: each embedded angle
+    theta_q enters one rotation, so d f / d theta_q = [f(theta_q + pi/2) - f(theta_q - pi/2)]/2
+    exactly, and d f / d c = sum_q J_qc d f / d theta_q."""
+    theta, J = encoding_angles(circ, points)
+    P, n = theta.shape
+    zeros = np.zeros((P, n, 3))
+    out = np.zeros((P, len(circ.out_qubits), 3))
+    from copy import copy
+    c_ang = copy(circ)
+    c_ang.enc = copy(circ.enc)
+    c_ang.enc.kind = ENC_ANGLES
+    for q in range(n):
+        tp, tm = theta.copy(), theta.copy()
+        tp[:, q] += math.pi / 2
+        tm[:, q] -= math.pi / 2
+        fp, _ = simulate(c_ang, params, points, tp, zeros)
+        fm, _ = simulate(c_ang, params, points, tm, zeros)
+        d = (fp - fm) / 2.0
+        out += d[:, :, None] * J[:, q, None, :]
+    return out
+
+
+def unitary(circ, params):
+    """Dense product V = U_F ... U_1 of the full operators (brute force; small n only)."""
+    V = np.eye(2 ** circ.n, dtype=np.complex128)
+    for U in operators(circ, np.asarray(params, np.float64)):
+        V = (U @ V) if not sp.issparse(U) else U @ V
+    return V

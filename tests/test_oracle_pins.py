@@ -1,0 +1,450 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms, Bloch-sphere
+geometry, Bell/GHZ states, an independent bit-level simulator built on scipy's expm, the trace
+identity of the Z readout, the parameter-shift rule, finite differences, an exact plane-wave
+solution of the TE_z system, and the parameter counts printed in the paper's Table 1.
+"""
+import json
+import math
+import os
+from copy import deepcopy
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import qpinn_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _circ(n, gates, n_params, enc=None, out=None):
+    return W.Circuit(n=n, gates=gates, n_params=n_params, enc=enc or W.Encoding(),
+                     out_qubits=out if out is not None else list(range(min(n, 3))))
+
+
+# ------------------------------------------------------------------ closed forms --------------
+
+def test_ry_embedding_closed_form():
+    """<Z> = cos(theta) after RY(theta)|0>; cycled pi-scaling gives theta = pi*c, so
+    <Z_q> = cos(pi c) and d<Z_q>/dc = -pi sin(pi c) on the qubit's own coordinate only."""
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(-1, 1, (17, 3))
+    c = _circ(5, [], 0, out=[0, 1, 2, 3, 4])
+    f, g = O.simulate(c, [], pts)
+    for q in range(5):
+        col = q % 3
+        np.testing.assert_allclose(f[:, q], np.cos(math.pi * pts[:, col]), atol=1e-14)
+        for cc in range(3):
+            exp = -math.pi * np.sin(math.pi * pts[:, col]) if cc == col else 0.0
+            np.testing.assert_allclose(g[:, q, cc], exp, atol=1e-13)
+
+
+def test_rx_scaling_identities_golden():
+    """Caption of the input-scaling figure: RX(arccos a) gives <Z> = a, RX(arcsin a + pi/2)
+    gives <Z> = -a."""
+    gold = json.load(open(os.path.join(GOLDEN, "scaling_identities.json")))
+    a = np.array(gold["a"])
+    pts = np.stack([a, np.zeros_like(a), np.zeros_like(a)], 1)
+    for scale, key in ((W.SCALE_ACOS, "acos_expect_z"), (W.SCALE_ASIN, "asin_expect_z")):
+        enc = W.Encoding(kind=W.ENC_CYCLE, gate=W.ENC_RX, scale=scale, coord_of_qubit=[0])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f, _ = O.simulate(_circ(1, [], 0, enc=enc, out=[0]), [], pts)
+        np.testing.assert_allclose(f[:, 0], gold[key], atol=1e-12)
+
+
+def test_scale_derivatives_match_finite_differences():
+    a = np.linspace(-0.9, 0.9, 11)
+    h = 1e-6
+    for s in range(5):
+        fd = (O.scale_value(s, a + h) - O.scale_value(s, a - h)) / (2 * h)
+        np.testing.assert_allclose(O.scale_derivative(s, a), fd, rtol=1e-8, atol=1e-9)
+
+
+# ------------------------------------------------------------- Bloch-sphere pin ---------------
+
+def _so3(kind, phi):
+    c, s = math.cos(phi), math.sin(phi)
+    if kind == W.RX:
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    if kind == W.RY:
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def _so3_d(kind, phi):
+    c, s = math.cos(phi), math.sin(phi)
+    if kind == W.RX:
+        return np.array([[0, 0, 0], [0, -s, -c], [0, c, -s]])
+    if kind == W.RY:
+        return np.array([[-s, 0, c], [0, 0, 0], [-c, 0, -s]])
+    return np.array([[-s, -c, 0], [c, -s, 0], [0, 0, 0]])
+
+
+@pytest.mark.parametrize("rot,n,L", [("xyz", 3, 3), ("rot", 4, 2), ("xyz", 12, 2)])
+def test_product_state_matches_bloch_rotations(rot, n, L):
+    """With no entangler (the No-Entanglement ansatz) every qubit stays a product factor whose
+    Bloch vector is turned by the SO(3) rotation of each gate; <Z> is its z component.  This
+    pins outputs, input tangents and reverse-mode gradients at any n (here up to 12) without a
+    statevector."""
+    rng = np.random.default_rng(1)
+    circ = W.no_entanglement(n, L, rot)
+    circ.out_qubits = list(range(n))
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    pts = rng.uniform(-1, 1, (4, 3))
+    f, g = O.simulate(circ, params, pts)
+    seeds = rng.standard_normal(g.shape)
+    seeds_f = rng.standard_normal(f.shape)
+    grad = O.grad_reverse(circ, params, pts, seeds_f, seeds)
+    exp_grad = np.zeros(circ.n_params)
+    for p in range(pts.shape[0]):
+        for q in range(n):
+            th = math.pi * pts[p, q % 3]
+            b0 = np.array([math.sin(th), 0.0, math.cos(th)])
+            db0 = np.array([math.cos(th), 0.0, -math.sin(th)]) * math.pi
+            ops = [(k, prm) for (k, qq, _, prm) in circ.gates if qq == q]
+            Rs = [_so3(k, params[prm]) for k, prm in ops]
+            b, db = b0.copy(), db0.copy()
+            for R in Rs:
+                b, db = R @ b, R @ db
+            assert abs(f[p, q] - b[2]) < 1e-12
+            for cc in range(3):
+                exp = db[2] if cc == q % 3 else 0.0
+                assert abs(g[p, q, cc] - exp) < 1e-12
+            for i, (k, prm) in enumerate(ops):
+                before = np.eye(3)
+                for R in Rs[:i]:
+                    before = R @ before
+                after = np.eye(3)
+                for R in Rs[i + 1:]:
+                    after = R @ after
+                D = after @ _so3_d(k, params[prm]) @ before
+                exp_grad[prm] += seeds_f[p, q] * (D @ b0)[2]
+                exp_grad[prm] += seeds[p, q, q % 3] * (D @ db0)[2]
+    np.testing.assert_allclose(grad, exp_grad, atol=1e-11)
+
+
+# ------------------------------------------------------------- entanglers ---------------------
+
+def _zero_enc():
+    return W.Encoding(kind=W.ENC_CYCLE, gate=W.ENC_RY, scale=W.SCALE_NONE)
+
+
+def test_bell_state():
+    """RY(pi/2) on qubit 0 then CNOT(0,1): amplitudes 1/sqrt2 on |00> and |11>, <Z0>=<Z1>=0."""
+    circ = _circ(2, [(W.RY, 0, -1, 0), (W.CNOT, 0, 1, -1)], 1, enc=_zero_enc(), out=[0, 1])
+    psi, _ = O.final_states(circ, [math.pi / 2], np.zeros((1, 3)))
+    np.testing.assert_allclose(psi[:, 0], [2 ** -0.5, 0, 0, 2 ** -0.5], atol=1e-15)
+    f, _ = O.simulate(circ, [math.pi / 2], np.zeros((1, 3)))
+    np.testing.assert_allclose(f, 0.0, atol=1e-15)
+
+
+def test_ghz_state_and_cnot_direction():
+    n = 5
+    gates = [(W.RY, 0, -1, 0)] + [(W.CNOT, q, q + 1, -1) for q in range(n - 1)]
+    circ = _circ(n, gates, 1, enc=_zero_enc())
+    psi, _ = O.final_states(circ, [math.pi / 2], np.zeros((1, 3)))
+    exp = np.zeros(2 ** n)
+    exp[0] = exp[-1] = 2 ** -0.5
+    np.testing.assert_allclose(psi[:, 0], exp, atol=1e-15)
+    # direction: control 0 (most significant bit), target 1.  |10> -> |11>, |01> -> |01>.
+    circ = _circ(2, [(W.RY, 0, -1, 0), (W.CNOT, 0, 1, -1)], 1, enc=_zero_enc(), out=[0, 1])
+    psi, _ = O.final_states(circ, [math.pi], np.zeros((1, 3)))
+    np.testing.assert_allclose(np.abs(psi[:, 0]), [0, 0, 0, 1], atol=1e-15)
+    circ = _circ(2, [(W.RY, 1, -1, 0), (W.CNOT, 0, 1, -1)], 1, enc=_zero_enc(), out=[0, 1])
+    psi, _ = O.final_states(circ, [math.pi], np.zeros((1, 3)))
+    np.testing.assert_allclose(np.abs(psi[:, 0]), [0, 1, 0, 0], atol=1e-15)
+
+
+def _expm_rot(kind, th):
+    P = {W.RX: np.array([[0, 1], [1, 0]]), W.RY: np.array([[0, -1j], [1j, 0]]),
+         W.RZ: np.diag([1, -1])}[kind]
+    return sla.expm(-0.5j * th * P)
+
+
+def _bitwise_simulate(circ, params, psi0):
+    """Independent simulator: loops over basis indices and flips bits (qubit 0 = MSB)."""
+    n = circ.n
+    s = np.array(psi0, dtype=np.complex128)
+    for kind, q0, q1, pi in circ.gates:
+        m0 = 1 << (n - 1 - q0)
+        new = s.copy()
+        if kind in (W.RX, W.RY, W.RZ):
+            U = _expm_rot(kind, params[pi])
+            for j in range(2 ** n):
+                if j & m0:
+                    continue
+                a, b = s[j], s[j | m0]
+                new[j] = U[0, 0] * a + U[0, 1] * b
+                new[j | m0] = U[1, 0] * a + U[1, 1] * b
+        else:
+            m1 = 1 << (n - 1 - q1)
+            for j in range(2 ** n):
+                if not j & m0:
+                    continue
+                if kind == W.CNOT:
+                    new[j] = s[j ^ m1]
+                elif kind == W.CZ:
+                    new[j] = -s[j] if j & m1 else s[j]
+                elif kind == W.CRZ:
+                    ph = np.exp(0.5j * params[pi]) if j & m1 else np.exp(-0.5j * params[pi])
+                    new[j] = ph * s[j]
+        s = new
+    return s
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kron_oracle_matches_bitwise_simulator(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 5))
+    gates, K = [], 0
+    for _ in range(14):
+        k = int(rng.integers(0, 6))
+        if k <= 2:
+            gates.append((k, int(rng.integers(0, n)), -1, K))
+            K += 1
+        else:
+            a, b = rng.choice(n, 2, replace=False)
+            if k == W.CRZ:
+                gates.append((k, int(a), int(b), K))
+                K += 1
+            else:
+                gates.append((k, int(a), int(b), -1))
+    params = rng.uniform(0, 2 * math.pi, K)
+    circ = _circ(n, gates, K, out=list(range(n)))
+    pts = rng.uniform(-1, 1, (3, 3))
+    psi, dpsi = O.final_states(circ, params, pts)
+    psi0, _ = O.initial_states(circ, *O.encoding_angles(circ, pts))
+    for p in range(3):
+        np.testing.assert_allclose(psi[:, p], _bitwise_simulate(circ, params, psi0[:, p]),
+                                   atol=1e-13)
+    # brute-force dense product of the full operators: unitary, and the same final state
+    V = O.unitary(circ, params)
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(2 ** n), atol=1e-12)
+    np.testing.assert_allclose(V @ psi0, psi, atol=1e-13)
+
+
+def test_cz_stride_ring_sign_function():
+    """A CZ ring of stride r is the diagonal sign (-1)^(sum_q b_q b_(q+r mod n))."""
+    for n, r in ((4, 1), (5, 2), (6, 3), (4, 2)):
+        gates = W.ring(n, W.CZ, r)
+        V = O.unitary(_circ(n, gates, 0), [])
+        for j in range(2 ** n):
+            bits = [(j >> (n - 1 - q)) & 1 for q in range(n)]
+            e = sum(bits[q] * bits[(q + r) % n] for q in range(n) if (q + r) % n != q)
+            assert V[j, j] == pytest.approx((-1) ** e)
+        assert np.count_nonzero(V - np.diag(np.diag(V))) == 0
+
+
+def test_operators_unitary_and_norm_preserved():
+    w = W.config(1, P=8)
+    ops = O.operators(w.circuit, w.params)
+    for U in ops:
+        np.testing.assert_allclose(U.conj().T @ U, np.eye(U.shape[0]), atol=1e-13)
+    psi, _ = O.final_states(w.circuit, w.params, w.points)
+    np.testing.assert_allclose(np.linalg.norm(psi, axis=0), 1.0, atol=1e-13)
+
+
+def test_init_zeros_gives_unit_outputs():
+    """Section on parameter initialisation: all-zero parameters without an embedding rotation
+    give every output equal to 1 (here the embedding angle is 0 at the origin)."""
+    for circ in (W.config(1, P=1).circuit, W.strongly_entangling(5, 3, ent=W.CZ)):
+        circ = deepcopy(circ)
+        circ.out_qubits = list(range(circ.n))
+        f, g = O.simulate(circ, np.zeros(circ.n_params), np.zeros((2, 3)))
+        np.testing.assert_allclose(f, 1.0, atol=1e-14)
+        np.testing.assert_allclose(g, 0.0, atol=1e-14)
+
+
+def test_trace_identity_over_basis_encodings():
+    """Summing <Z_i> over all 2^n basis-state inputs gives Tr(V^H Z_i V) = Tr(Z_i) = 0, the
+    discrete form of the zero-mean statement in the initialisation section."""
+    rng = np.random.default_rng(3)
+    for circ in (W.basic_entangling(4, 3, "xyz"), W.strongly_entangling(5, 2, ent=W.CZ)):
+        circ = deepcopy(circ)
+        circ.out_qubits = list(range(circ.n))
+        circ.enc = W.Encoding(kind=W.ENC_ANGLES)
+        n = circ.n
+        theta = np.array([[math.pi * ((j >> (n - 1 - q)) & 1) for q in range(n)]
+                          for j in range(2 ** n)])
+        params = rng.uniform(0, 2 * math.pi, circ.n_params)
+        f, _ = O.simulate(circ, params, np.zeros((2 ** n, 3)), theta, np.zeros((2 ** n, n, 3)))
+        np.testing.assert_allclose(f.sum(0), 0.0, atol=1e-12)
+        assert np.abs(f).max() > 0.05
+
+
+# ------------------------------------------------------------ derivatives ---------------------
+
+def _small(k, P):
+    w = W.config(k, P=P)
+    if k == 0:
+        w.loss = W.MaxwellDesc(W.LOSS_VACUUM)
+    return w
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_tangents_match_fd_and_encoding_shift(k):
+    w = _small(k, 6)
+    _, g = O.simulate(w.circuit, w.params, w.points)
+    fd = O.fd_tangents(w.circuit, w.params, w.points, h=1e-5)
+    np.testing.assert_allclose(g, fd, atol=2e-8 if k == 1 else 5e-8)
+    if w.circuit.enc.kind == W.ENC_CYCLE:
+        sh = O.encoding_shift_tangents(w.circuit, w.params, w.points)
+        np.testing.assert_allclose(g, sh, atol=1e-12)
+
+
+def test_rff_jacobian_matches_fd():
+    w = W.config(2, P=5)
+    th, J = O.encoding_angles(w.circuit, w.points)
+    h = 1e-6
+    for c in range(3):
+        pp, pm = w.points.astype(np.float64), w.points.astype(np.float64)
+        pp = pp.copy(); pm = pm.copy()
+        pp[:, c] += h
+        pm[:, c] -= h
+        fd = (O.encoding_angles(w.circuit, pp)[0] - O.encoding_angles(w.circuit, pm)[0]) / (2 * h)
+        np.testing.assert_allclose(J[:, :, c], fd, atol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "mixed"])
+def test_reverse_mode_equals_parameter_shift(name):
+    if name == "c2":
+        w = _small(1, 5)
+    elif name == "c3":
+        w = W.config(2, P=6)
+        w.circuit = deepcopy(w.circuit)
+        w.circuit.gates = [g for g in w.circuit.gates if g[3] < 48 or g[3] < 0][:]
+        # keep the first two layers (48 params) and their rings
+        keep, K = [], 0
+        for g in W.config(2, P=1).circuit.gates:
+            if g[3] >= 48:
+                break
+            keep.append(g)
+        w.circuit.gates, w.circuit.n_params = keep, 48
+        w.params = w.params[:48]
+    else:
+        b = W.batch_config(P_cap=5)
+        w = min(b, key=lambda x: x.circuit.n_params)
+    f, g = O.simulate(w.circuit, w.params, w.points)
+    seeds = O.maxwell_seeds(g, w.points, w.loss)
+    rev = O.grad_reverse(w.circuit, w.params, w.points, None, seeds)
+    sh = O.grad_param_shift(w.circuit, w.params, w.points, None, seeds)
+    np.testing.assert_allclose(rev, sh, atol=1e-12 * max(1, np.abs(sh).max()))
+
+
+def test_reverse_mode_matches_fd_of_loss():
+    w = W.config(2, P=8)
+    f, g, L, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+    fd = O.grad_fd_loss(w.circuit, w.params, w.points, w.loss, h=1e-5, idx=[0, 7, 100, 233])
+    for k, v in fd.items():
+        assert abs(v - grad[k]) <= 1e-7 * max(1.0, abs(grad[k])), (k, v, grad[k])
+
+
+def test_last_layer_diagonal_gradients_vanish():
+    """A trailing Z rotation followed only by entangling permutations/diagonals cannot change
+    Z-basis probabilities: its gradient is exactly zero (last-layer RZ; last-layer Rot omega)."""
+    for k in (1, 2):
+        w = W.config(k, P=4)
+        _, _, _, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+        n = w.circuit.n
+        K = w.circuit.n_params
+        last = [K - 3 * n + 3 * q + 2 for q in range(n)]
+        assert np.abs(grad[last]).max() < 1e-14
+        assert np.abs(grad).max() > 1e-3
+
+
+def test_two_pi_periodicity():
+    """theta -> theta + 2 pi flips the sign of the state: outputs, tangents, gradients unchanged."""
+    w = _small(1, 4)
+    f, g, L, gr = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+    p2 = w.params.astype(np.float64).copy()
+    p2[[3, 17, 50]] += 2 * math.pi
+    f2, g2, L2, gr2 = O.maxwell_eval(w.circuit, p2, w.points, w.loss)
+    np.testing.assert_allclose(f2, f, atol=1e-13)
+    np.testing.assert_allclose(g2, g, atol=1e-12)
+    np.testing.assert_allclose(gr2, gr, atol=1e-12)
+
+
+# ------------------------------------------------------------------ loss ----------------------
+
+def _wave(points, eps_of_point, sign=-1.0):
+    """g for E = F(x - v t), Hx = 0, Hy = sign * sqrt(eps) F(x - v t), v = 1/sqrt(eps),
+    with F(s) = exp(-s^2) sin(3 s)."""
+    t, x = points[:, 0], points[:, 1]
+    v = 1.0 / np.sqrt(eps_of_point)
+    s = x - v * t
+    Fp = np.exp(-s * s) * (3 * np.cos(3 * s) - 2 * s * np.sin(3 * s))
+    g = np.zeros((points.shape[0], 3, 3))
+    g[:, 0, 0] = -v * Fp
+    g[:, 0, 1] = Fp
+    a = sign * np.sqrt(eps_of_point)
+    g[:, 2, 0] = -a * v * Fp
+    g[:, 2, 1] = a * Fp
+    return g, Fp
+
+
+def test_plane_wave_is_an_exact_zero_of_every_residual():
+    """E_z = F(x - t/sqrt(eps)), H_y = -sqrt(eps) F(...), H_x = 0 solves the TE_z system with
+    permittivity eps, so every residual, the loss and all seeds vanish; flipping H_y gives
+    r1 = r3 = -2F' (vacuum): loss = 8 mean(F'^2)."""
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-1, 1, (64, 3))
+    g, _ = _wave(pts, np.ones(64))
+    d = W.MaxwellDesc(W.LOSS_VACUUM)
+    assert O.maxwell_loss(g, pts, d) < 1e-28
+    assert np.abs(O.maxwell_seeds(g, pts, d)).max() < 1e-14
+    for kind in (W.LOSS_DIEL_SPLIT, W.LOSS_DIEL_INTUITIVE):
+        d = W.MaxwellDesc(kind, eps_r=4.0)
+        eps = np.where(pts[:, 1] >= 0, 4.0, 1.0)
+        g, _ = _wave(pts, eps)
+        assert O.maxwell_loss(g, pts, d) < 1e-28
+    g, Fp = _wave(pts, np.ones(64), sign=+1.0)
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_VACUUM)) == pytest.approx(
+        8 * np.mean(Fp ** 2), rel=1e-12)
+
+
+def test_dielectric_split_weights():
+    """Split loss (eq. phys_loss_diel): MSE over the vacuum half plus MSE over the dielectric
+    half.  dE/dt = 1 everywhere gives r1 = 1: split = 2, intuitive = vacuum = 1.  dHy/dx = 1
+    gives r1 = -1/eps: split = 1 + 1/16, intuitive = (N_vac + N_diel/16)/P."""
+    rng = np.random.default_rng(6)
+    pts = rng.uniform(-1, 1, (50, 3))
+    nd = int((pts[:, 1] >= 0).sum())
+    nv = 50 - nd
+    g = np.zeros((50, 3, 3))
+    g[:, 0, 0] = 1.0
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT)) == pytest.approx(2.0)
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_INTUITIVE)) == pytest.approx(1.0)
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_VACUUM)) == pytest.approx(1.0)
+    g = np.zeros((50, 3, 3))
+    g[:, 2, 1] = 1.0
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT)) == pytest.approx(1 + 1 / 16)
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_INTUITIVE)) == pytest.approx(
+        (nv + nd / 16) / 50)
+
+
+def test_seeds_are_the_gradient_of_the_loss_in_g():
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(-1, 1, (9, 3))
+    g = rng.standard_normal((9, 3, 3))
+    for kind in (W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT, W.LOSS_DIEL_INTUITIVE):
+        d = W.MaxwellDesc(kind)
+        S = O.maxwell_seeds(g, pts, d)
+        h = 1e-6
+        for idx in [(0, 0, 0), (3, 2, 1), (5, 1, 2), (8, 0, 2), (2, 0, 1), (4, 1, 0)]:
+            gp, gm = g.copy(), g.copy()
+            gp[idx] += h
+            gm[idx] -= h
+            fd = (O.maxwell_loss(gp, pts, d) - O.maxwell_loss(gm, pts, d)) / (2 * h)
+            assert fd == pytest.approx(S[idx], abs=1e-8)
+
+
+# ------------------------------------------------------------------ Table 1 -------------------
+
+def test_table1_parameter_counts_golden():
+    gold = json.load(open(os.path.join(GOLDEN, "table1_param_counts.json")))
+    for name, count in gold["quantum_params"].items():
+        c = W.paper_context_circuit(name, gold["n_qubits"], gold["n_layers"])
+        assert c.n_params == count, name
