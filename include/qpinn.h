@@ -1,0 +1,216 @@
+/*
+ * qpinn.h - C ABI of the MI355X (gfx950) QPINN circuit engine.
+ *
+ * The library evaluates, for every collocation point p = (t, x, y), a parametrised quantum
+ * circuit as a statevector and returns
+ *   - the readouts  f_i(p) = <Z_i>            (section "QPINN architecture and ansatz designs":
+ *                                              one Pauli-Z expectation per output qubit),
+ *   - the input tangents g_ic(p) = d f_i / d c for c in (t, x, y), by forward-mode tangent
+ *     statevectors (the derivatives the Maxwell residuals need),
+ *   - the gradient of a loss with respect to the circuit parameters, by an adjoint sweep that
+ *     walks the circuit backwards and uncomputes each gate with its inverse instead of storing
+ *     intermediate states.
+ * The fused entry point evaluates the TE_z Maxwell residual loss (section "PINN architecture
+ * and convergence enhancements": eqs. residual_1_vac, residual_1_diel, residuals_2_and_3,
+ * phys_loss_vac, phys_loss_diel, mse; section "Stabilizing the dielectric test case":
+ * eq. residual_1_intuitive) and its parameter gradient in one call.
+ *
+ * Conventions (fixed by this library; the paper leaves them open):
+ *   - R_P(theta) = exp(-i theta P / 2) for P in {X, Y, Z};
+ *   - qubit 0 is the most significant bit of a basis index (leftmost Kronecker factor);
+ *   - points are row-major float32 [P][3] with columns (t, x, y);
+ *   - outputs are float32 [P][m], tangents float32 [P][m][3] (m = number of output qubits);
+ *     the first three outputs are the fields (E_z, H_x, H_y) for the Maxwell loss.
+ *
+ * Memory and ownership:
+ *   - every device pointer argument is caller-owned device memory on the context's device;
+ *   - descriptors are copied during the call; the caller may free them afterwards;
+ *   - per-call scratch lives in a caller-provided workspace (size from the *_workspace_bytes
+ *     query, 256-byte aligned).  Compiling a circuit or a batch uploads its execution plan
+ *     once into a small device buffer owned by the returned object; evaluation calls allocate
+ *     no device memory.
+ *
+ * Execution: calls are asynchronous and ordered on the context's HIP stream.  Errors found on
+ * the host are returned as status codes (no exceptions or aborts cross this boundary) with a
+ * message from qp_last_error(); asynchronous device errors surface at a later call or at
+ * qp_sync().  Reductions run in a fixed order, so repeated calls give bitwise equal results.
+ * Arithmetic: complex64 state, FP32 accumulation per point and per workgroup; the final
+ * cross-workgroup loss and gradient reductions run in FP64.
+ */
+#ifndef QPINN_H
+#define QPINN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum qp_status {
+  QP_OK = 0,
+  QP_EINVAL = 1,        /* null pointer, bad enum, bad gate operand, P < 0 */
+  QP_ESHAPE = 2,        /* sizes inconsistent with the circuit (e.g. fewer than 3 outputs for Maxwell) */
+  QP_EUNSUPPORTED = 3,  /* valid request outside this build's range (qubit count, gate kind) */
+  QP_EWORKSPACE = 4,    /* workspace missing, too small or misaligned */
+  QP_EDEVICE = 5        /* HIP runtime error */
+} qp_status;
+
+/* Gate kinds.  Rotations take one parameter (param = index into the parameter vector). */
+enum { QP_RX = 0, QP_RY = 1, QP_RZ = 2, QP_CNOT = 3, QP_CZ = 4, QP_CRZ = 5 };
+/* Encodings (section "QPINN architecture": angle embedding; section "PINN architecture":
+ * random Fourier features). */
+enum { QP_ENC_CYCLE = 0, QP_ENC_ANGLES = 1, QP_ENC_RFF = 2 };
+enum { QP_ENC_RY = 0, QP_ENC_RX = 1 };
+/* Input scalings of eq. scale: a, pi a, (a+1) pi/2, asin(a) + pi/2, acos(a). */
+enum { QP_SCALE_NONE = 0, QP_SCALE_PI = 1, QP_SCALE_BIAS = 2, QP_SCALE_ASIN = 3, QP_SCALE_ACOS = 4 };
+/* Maxwell residual losses: vacuum (eq. phys_loss_vac), split dielectric (eq. phys_loss_diel),
+ * intuitive dielectric (eq. phys_loss_intuitive). */
+enum { QP_LOSS_VACUUM = 0, QP_LOSS_DIEL_SPLIT = 1, QP_LOSS_DIEL_INTUITIVE = 2 };
+
+/* Flags (bitwise or). */
+#define QP_FLAG_NO_TANGENTS 0x1u  /* qp_simulate: tangents not needed (tan may be NULL)      */
+#define QP_FLAG_LOSS_SUM    0x2u  /* Maxwell: sum of squared residuals instead of MSE means  */
+#define QP_FLAG_TUNE        0x4u  /* time the candidate launch shapes on first use and cache  */
+#define QP_FLAG_DENSE_MFMA  0x8u  /* force the dense-block MFMA path (where the plan has one) */
+
+typedef struct qp_ctx qp_ctx;
+typedef struct qp_circuit qp_circuit;
+typedef struct qp_batch qp_batch;
+
+typedef struct qp_gate {
+  int32_t kind;   /* QP_RX..QP_CRZ                                          */
+  int32_t q0;     /* rotation target, or control of CNOT/CRZ, first qubit of CZ */
+  int32_t q1;     /* target of CNOT/CRZ, second qubit of CZ; ignored otherwise */
+  int32_t param;  /* parameter index for rotations (and CRZ); ignored otherwise */
+} qp_gate;
+
+typedef struct qp_encoding {
+  int32_t kind;                   /* QP_ENC_*                                             */
+  int32_t gate;                   /* QP_ENC_RY or QP_ENC_RX: rotation applied to |0>       */
+  int32_t scale;                  /* QP_SCALE_* (QP_ENC_CYCLE only)                       */
+  int32_t n_features;             /* QP_ENC_RFF: number of frequencies F                  */
+  const int32_t* coord_of_qubit;  /* QP_ENC_CYCLE: host [n] in {0,1,2}, or NULL for q mod 3 */
+  const float* rff_B;             /* QP_ENC_RFF: host [F][3] frequencies                  */
+  const float* rff_W;             /* QP_ENC_RFF: host [n][2F] map [cos(Bp); sin(Bp)] -> angles */
+} qp_encoding;
+
+typedef struct qp_circuit_desc {
+  int32_t n_qubits;               /* 3..12 for the fused paths, 1..14 for the plain path  */
+  int32_t n_params;               /* K                                                    */
+  int32_t n_gates;
+  const qp_gate* gates;           /* host [n_gates], time order                          */
+  qp_encoding enc;
+  int32_t n_out;                  /* m, 1..8                                              */
+  const int32_t* out_qubits;      /* host [m]                                             */
+} qp_circuit_desc;
+
+typedef struct qp_maxwell_desc {
+  int32_t kind;                   /* QP_LOSS_*                                            */
+  float eps_r;                    /* relative permittivity of the dielectric half (4)     */
+  float x_interface;              /* eps = eps_r where x >= x_interface                   */
+} qp_maxwell_desc;
+
+/* ---- context ---------------------------------------------------------------------------
+ * qp_ctx_create: binds the calling thread's work to `device` and the HIP stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  One context per stream; not thread-safe.        */
+qp_status qp_ctx_create(int device, void* hip_stream, qp_ctx** out);
+qp_status qp_ctx_set_stream(qp_ctx* ctx, void* hip_stream);
+void qp_ctx_destroy(qp_ctx* ctx);
+const char* qp_last_error(const qp_ctx* ctx);
+qp_status qp_sync(qp_ctx* ctx);   /* waits for the stream; reports asynchronous device errors */
+int32_t qp_device_cu_count(const qp_ctx* ctx);
+
+/* ---- circuits --------------------------------------------------------------------------
+ * qp_circuit_compile validates the descriptor, fuses consecutive rotations on a qubit into
+ * one 2x2 gate, turns runs of CNOT/CZ gates into index permutations with sign functions,
+ * schedules the register/LDS rounds and uploads the plan.  Errors: QP_EINVAL (bad operand),
+ * QP_EUNSUPPORTED (n outside 3..12 for fused evaluation is reported at evaluation time).     */
+qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* desc, qp_circuit** out);
+void qp_circuit_destroy(qp_circuit* c);
+/* what: 0 n_qubits, 1 n_params, 2 n_out, 3 fused gates, 4 rounds, 5 register-exchange count,
+ *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile            */
+int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
+
+/* Workspace bytes for qp_simulate / qp_vjp / qp_maxwell_fused with P points. */
+size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags);
+
+/* ---- evaluation ------------------------------------------------------------------------
+ * points [P][3] (read for QP_ENC_CYCLE and QP_ENC_RFF; may be NULL for QP_ENC_ANGLES unless a
+ * dielectric loss needs x), angles [P][n] and jac [P][n][3] (QP_ENC_ANGLES only, else NULL).
+ * P = 0 is valid and does nothing except zeroing reduced outputs.                          */
+
+/* Forward: out [P][m]; tan [P][m][3] unless QP_FLAG_NO_TANGENTS.                           */
+qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params,
+                      const float* points, const float* angles, const float* jac, int64_t P,
+                      float* out, float* tan, void* ws, size_t ws_bytes, uint32_t flags);
+
+/* Vector-Jacobian product with respect to the parameters:
+ *   d_params[k] = sum_p sum_i d_out[p,i] df_i/dtheta_k + sum_ic d_tan[p,i,c] dg_ic/dtheta_k.
+ * d_out or d_tan may be NULL (treated as zero).  Recomputes the forward internally.         */
+qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                 const float* angles, const float* jac, int64_t P, const float* d_out,
+                 const float* d_tan, float* d_params, void* ws, size_t ws_bytes,
+                 uint32_t flags);
+
+/* Fused Maxwell evaluation: forward + tangents + residual loss + adjoint gradient in one
+ * stream-ordered call.  out/tan may be NULL.  loss: one double (device); d_params: [K].     */
+qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params,
+                           const float* points, const float* angles, const float* jac,
+                           int64_t P, const qp_maxwell_desc* loss_desc, float* out, float* tan,
+                           double* loss, float* d_params, void* ws, size_t ws_bytes,
+                           uint32_t flags);
+
+/* ---- uneven batch: many circuits in one persistent launch ------------------------------
+ * qp_batch_compile plans `count` circuits with their point counts P[count] (host), orders the
+ * (circuit, point-tile) work items longest first and uploads the work list.  qp_batch_run
+ * evaluates the fused Maxwell step for every circuit in one persistent kernel followed by one
+ * reduction kernel; with QP_FLAG_TUNE the grid size is chosen by timing.  io is a host array
+ * [count] of per-circuit device pointers.  qp_batch_graph_launch captures the whole step into
+ * a hipGraph on first use (per batch, io and workspace) and replays it afterwards; parameters
+ * and points may change between replays, the pointers may not.                           */
+typedef struct qp_batch_io {
+  const float* params;    /* [K_c]          */
+  const float* points;    /* [P_c][3]       */
+  float* out;             /* [P_c][m] or NULL */
+  float* tan;             /* [P_c][m][3] or NULL */
+  double* loss;           /* [1]            */
+  float* d_params;        /* [K_c]          */
+} qp_batch_io;
+
+qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circuit_desc* descs,
+                           const int64_t* P, qp_batch** out);
+void qp_batch_destroy(qp_batch* b);
+size_t qp_batch_workspace_bytes(const qp_batch* b);
+qp_status qp_batch_run(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
+                       const qp_maxwell_desc* loss_desc, void* ws, size_t ws_bytes,
+                       uint32_t flags);
+qp_status qp_batch_graph_launch(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
+                                const qp_maxwell_desc* loss_desc, void* ws, size_t ws_bytes,
+                                uint32_t flags);
+/* what: 0 circuits, 1 work items, 2 grid size in use, 3 graph captured (0/1) */
+int64_t qp_batch_info(const qp_batch* b, int32_t what);
+
+/* ---- plain baseline (the speedup denominator) -----------------------------------------
+ * One kernel launch per gate on a statevector batch held in HBM, a readout kernel, input
+ * tangents by central finite differences (6 extra forwards with step fd_h) - the evaluation
+ * count of the paper's hardware-derivative cost model (section 2.1, cost per point).
+ * precision 32: complex64 state; 64: complex128 state.  params [K], points [P][3] and the
+ * outputs use the matching real type (float or double).  tan may be NULL (forward only).   */
+size_t qp_plain_workspace_bytes(const qp_circuit* c, int64_t P, int32_t precision);
+qp_status qp_plain_eval(qp_ctx* ctx, const qp_circuit* c, int32_t precision,
+                        const void* params, const void* points, int64_t P, double fd_h,
+                        void* out, void* tan, void* ws, size_t ws_bytes);
+/* Plain Maxwell step: FD tangents, then the loss (FP64 reduction), then central finite
+ * differences of the loss for parameters k_begin..k_end-1 (step fd_h_param).  loss: device
+ * double [1]; d_params: device [K] (entries outside the range are left untouched).         */
+qp_status qp_plain_maxwell_fd(qp_ctx* ctx, const qp_circuit* c, int32_t precision,
+                              const void* params, const void* points, int64_t P,
+                              const qp_maxwell_desc* loss_desc, double fd_h,
+                              double fd_h_param, int32_t k_begin, int32_t k_end,
+                              double* loss, void* d_params, void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPINN_H */

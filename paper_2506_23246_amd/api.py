@@ -1,0 +1,286 @@
+"""Torch-facing wrapper of the C ABI: contexts, compiled circuits and batches.
+
+PyTorch supplies device memory (tensors) and the stream; the wrapper only marshals pointers
+and sizes into the library, which runs every step in its own HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _f32(t, dev):
+    if t is None:
+        return None
+    t = torch.as_tensor(t)
+    return t.to(device=dev, dtype=torch.float32).contiguous()
+
+
+def _aligned_bytes(nbytes, dev):
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, int(nbytes)
+
+
+class Context:
+    """One library context bound to a device and a HIP stream (default: torch's current one)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        L.check(L.qp_ctx_create(device, self.stream.cuda_stream, C.byref(h)))
+        self.h = h
+        self.dev = torch.device("cuda", device)
+
+    def use_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        L.check(L.qp_ctx_set_stream(self.h, stream.cuda_stream), self.h)
+
+    def sync(self):
+        L.check(L.qp_sync(self.h), self.h)
+
+    @property
+    def cu_count(self):
+        return L.qp_device_cu_count(self.h)
+
+    def close(self):
+        if self.h:
+            L.qp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_desc(circ):
+    """qp_circuit_desc from any object with n, gates [(kind,q0,q1,param)], n_params, enc, out_qubits.
+    Returns (desc, keepalive)."""
+    n = int(circ.n)
+    gates = (L.qp_gate * max(1, len(circ.gates)))()
+    for i, (k, q0, q1, p) in enumerate(circ.gates):
+        gates[i] = L.qp_gate(int(k), int(q0), int(q1), int(p))
+    outs = (C.c_int32 * len(circ.out_qubits))(*[int(q) for q in circ.out_qubits])
+    enc = circ.enc
+    keep = [gates, outs]
+    e = L.qp_encoding()
+    e.kind, e.gate, e.scale = int(enc.kind), int(enc.gate), int(enc.scale)
+    coords = getattr(enc, "coord_of_qubit", None)
+    if coords is not None:
+        ca = (C.c_int32 * n)(*[int(c) for c in coords])
+        keep.append(ca)
+        e.coord_of_qubit = ca
+    if getattr(enc, "rff_B", None) is not None:
+        B = np.ascontiguousarray(enc.rff_B, dtype=np.float32)
+        W = np.ascontiguousarray(enc.rff_W, dtype=np.float32)
+        keep += [B, W]
+        e.n_features = B.shape[0]
+        e.rff_B = B.ctypes.data_as(C.POINTER(C.c_float))
+        e.rff_W = W.ctypes.data_as(C.POINTER(C.c_float))
+    d = L.qp_circuit_desc()
+    d.n_qubits, d.n_params, d.n_gates = n, int(circ.n_params), len(circ.gates)
+    d.gates = gates
+    d.enc = e
+    d.n_out = len(circ.out_qubits)
+    d.out_qubits = outs
+    return d, keep
+
+
+def maxwell_desc(loss):
+    kind = int(getattr(loss, "kind", 0))
+    return L.qp_maxwell_desc(kind, float(getattr(loss, "eps_r", 4.0)), float(getattr(loss, "x_interface", 0.0)))
+
+
+class Circuit:
+    """A compiled circuit (plan uploaded once)."""
+
+    def __init__(self, ctx: Context, circ):
+        self.ctx = ctx
+        self.src = circ
+        d, keep = make_desc(circ)
+        h = C.c_void_p()
+        L.check(L.qp_circuit_compile(ctx.h, C.byref(d), C.byref(h)), ctx.h)
+        self.h = h
+        self.n = int(circ.n)
+        self.K = int(circ.n_params)
+        self.m = len(circ.out_qubits)
+        self._ws = {}
+
+    def info(self, what: int) -> int:
+        return int(L.qp_circuit_info(self.h, what))
+
+    def workspace(self, P: int):
+        nb = int(L.qp_workspace_bytes(self.h, int(P), 0))
+        key = ("fused", nb)
+        if key not in self._ws:
+            self._ws = {key: _aligned_bytes(nb, self.ctx.dev)}
+        return self._ws[key]
+
+    def _inputs(self, params, points, angles, jac):
+        dev = self.ctx.dev
+        return _f32(params, dev), _f32(points, dev), _f32(angles, dev), _f32(jac, dev)
+
+    def simulate(self, params, points=None, angles=None, jac=None, tangents=True, out=None, tan=None):
+        prm, pts, ang, jc = self._inputs(params, points, angles, jac)
+        P = int((pts if pts is not None else ang).shape[0])
+        dev = self.ctx.dev
+        out = out if out is not None else torch.empty((P, self.m), dtype=torch.float32, device=dev)
+        if tangents and tan is None:
+            tan = torch.empty((P, self.m, 3), dtype=torch.float32, device=dev)
+        _, wp, nb = self.workspace(P)
+        flags = 0 if tangents else L.QP_FLAG_NO_TANGENTS
+        L.check(L.qp_simulate(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, _ptr(out),
+                              _ptr(tan) if tangents else None, wp, nb, flags), self.ctx.h)
+        return out, (tan if tangents else None)
+
+    def vjp(self, params, points=None, d_out=None, d_tan=None, angles=None, jac=None, d_params=None):
+        prm, pts, ang, jc = self._inputs(params, points, angles, jac)
+        P = int((pts if pts is not None else ang).shape[0])
+        dev = self.ctx.dev
+        d_out = _f32(d_out, dev)
+        d_tan = _f32(d_tan, dev)
+        d_params = d_params if d_params is not None else torch.empty(self.K, dtype=torch.float32, device=dev)
+        _, wp, nb = self.workspace(P)
+        L.check(L.qp_vjp(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, _ptr(d_out), _ptr(d_tan),
+                         _ptr(d_params), wp, nb, 0), self.ctx.h)
+        return d_params
+
+    def maxwell(self, params, points, loss, angles=None, jac=None, outputs=True, flags=0, bufs=None):
+        """Fused forward + tangents + Maxwell loss + adjoint gradient.  Returns
+        dict(out, tan, loss (float64 [1]), grad (float32 [K]))."""
+        prm, pts, ang, jc = self._inputs(params, points, angles, jac)
+        P = int((pts if pts is not None else ang).shape[0])
+        dev = self.ctx.dev
+        if bufs is None:
+            bufs = {
+                "out": torch.empty((P, self.m), dtype=torch.float32, device=dev) if outputs else None,
+                "tan": torch.empty((P, self.m, 3), dtype=torch.float32, device=dev) if outputs else None,
+                "loss": torch.empty(1, dtype=torch.float64, device=dev),
+                "grad": torch.empty(self.K, dtype=torch.float32, device=dev),
+            }
+        _, wp, nb = self.workspace(P)
+        md = maxwell_desc(loss)
+        L.check(L.qp_maxwell_fused(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, C.byref(md),
+                                   _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]), _ptr(bufs["grad"]),
+                                   wp, nb, flags), self.ctx.h)
+        return bufs
+
+    # ---- plain baseline -------------------------------------------------------------------
+    def plain_workspace(self, P, precision):
+        nb = int(L.qp_plain_workspace_bytes(self.h, int(P), int(precision)))
+        key = ("plain", nb)
+        if key not in self._ws:
+            self._ws[key] = _aligned_bytes(nb, self.ctx.dev)
+        return self._ws[key]
+
+    def plain_eval(self, params, points, precision=32, h=None, tangents=True):
+        dt = torch.float64 if precision == 64 else torch.float32
+        dev = self.ctx.dev
+        prm = torch.as_tensor(params).to(dev, dt).contiguous()
+        pts = torch.as_tensor(points).to(dev, dt).contiguous()
+        P = int(pts.shape[0])
+        h = h if h is not None else (1e-5 if precision == 64 else 2.0 ** -7)
+        out = torch.empty((P, self.m), dtype=dt, device=dev)
+        tan = torch.empty((P, self.m, 3), dtype=dt, device=dev) if tangents else None
+        _, wp, nb = self.plain_workspace(P, precision)
+        L.check(L.qp_plain_eval(self.ctx.h, self.h, precision, _ptr(prm), _ptr(pts), P, float(h), _ptr(out),
+                                _ptr(tan), wp, nb), self.ctx.h)
+        return out, tan
+
+    def plain_maxwell_fd(self, params, points, loss, precision=32, h=None, h_param=None, k_begin=0, k_end=None):
+        dt = torch.float64 if precision == 64 else torch.float32
+        dev = self.ctx.dev
+        prm = torch.as_tensor(params).to(dev, dt).contiguous()
+        pts = torch.as_tensor(points).to(dev, dt).contiguous()
+        P = int(pts.shape[0])
+        h = h if h is not None else (1e-5 if precision == 64 else 2.0 ** -7)
+        h_param = h_param if h_param is not None else (1e-5 if precision == 64 else 2.0 ** -7)
+        k_end = self.K if k_end is None else k_end
+        lo = torch.empty(1, dtype=torch.float64, device=dev)
+        dp = torch.zeros(self.K, dtype=dt, device=dev)
+        _, wp, nb = self.plain_workspace(P, precision)
+        md = maxwell_desc(loss)
+        L.check(L.qp_plain_maxwell_fd(self.ctx.h, self.h, precision, _ptr(prm), _ptr(pts), P, C.byref(md), float(h),
+                                      float(h_param), int(k_begin), int(k_end), _ptr(lo), _ptr(dp), wp, nb),
+                self.ctx.h)
+        return lo, dp
+
+    def close(self):
+        if self.h:
+            L.qp_circuit_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many circuits with their own point sets, evaluated by one persistent launch."""
+
+    def __init__(self, ctx: Context, circuits, P):
+        self.ctx = ctx
+        descs = (L.qp_circuit_desc * len(circuits))()
+        self._keep = []
+        for i, c in enumerate(circuits):
+            d, keep = make_desc(c)
+            descs[i] = d
+            self._keep.append(keep)
+        Ps = (C.c_int64 * len(P))(*[int(p) for p in P])
+        h = C.c_void_p()
+        L.check(L.qp_batch_compile(ctx.h, len(circuits), descs, Ps, C.byref(h)), ctx.h)
+        self.h = h
+        self.circuits = circuits
+        self.P = [int(p) for p in P]
+        nb = int(L.qp_batch_workspace_bytes(h))
+        self._ws = _aligned_bytes(nb, ctx.dev)
+
+    def info(self, what):
+        return int(L.qp_batch_info(self.h, what))
+
+    def io(self, params_list, points_list, outputs=True):
+        dev = self.ctx.dev
+        bufs = []
+        arr = (L.qp_batch_io * len(self.circuits))()
+        for i, c in enumerate(self.circuits):
+            m = len(c.out_qubits)
+            P = self.P[i]
+            b = {"params": _f32(params_list[i], dev), "points": _f32(points_list[i], dev),
+                 "out": torch.empty((P, m), dtype=torch.float32, device=dev) if outputs else None,
+                 "tan": torch.empty((P, m, 3), dtype=torch.float32, device=dev) if outputs else None,
+                 "loss": torch.empty(1, dtype=torch.float64, device=dev),
+                 "grad": torch.empty(int(c.n_params), dtype=torch.float32, device=dev)}
+            arr[i] = L.qp_batch_io(_ptr(b["params"]), _ptr(b["points"]), _ptr(b["out"]), _ptr(b["tan"]),
+                                   _ptr(b["loss"]), _ptr(b["grad"]))
+            bufs.append(b)
+        return arr, bufs
+
+    def run(self, arr, loss, flags=0, graph=False):
+        md = maxwell_desc(loss)
+        _, wp, nb = self._ws
+        fn = L.qp_batch_graph_launch if graph else L.qp_batch_run
+        L.check(fn(self.ctx.h, self.h, arr, C.byref(md), wp, nb, flags), self.ctx.h)
+
+    def close(self):
+        if self.h:
+            L.qp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,186 @@
+// Uneven batch: many circuits (different qubit counts, depths and point counts) evaluated by
+// ONE persistent kernel.  The host splits every circuit into work items of whole point tiles,
+// sized so that items cost about the same, and orders them longest-processing-time first.
+// Workgroups pull items from an atomic counter (reset by the preceding gate-table kernel, so
+// the sequence replays inside a hipGraph without memset nodes).  Each item writes its own M and
+// loss partials, so the final fixed-order FP64 reduction per circuit is deterministic no matter
+// which workgroup ran which item.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "fused_kernel.hpp"
+#include "grads_dev.hpp"
+
+namespace qp {
+
+constexpr int kBT = 256;   // threads per workgroup (all batch circuits have n <= 11)
+constexpr int kBEXS = 4;
+
+__global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGate* __restrict__ gates, int ngates,
+                              int* __restrict__ counter) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *counter = 0;
+  if (g >= ngates) return;
+  const BatchGate G = gates[g];
+  const BatchCirc& C = circs[G.circ];
+  const QPlanDev* plan = C.a.plan;
+  const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + G.idx;
+  float ur[2][2] = {{1.f, 0.f}, {0.f, 1.f}}, ui[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+  for (int c = 0; c < fu->ncomp; ++c) {
+    float s, co;
+    sincosf(0.5f * C.params[fu->param[c]], &s, &co);
+    float rr[2][2], ri[2][2];
+    const int kd = fu->kind[c];
+    if (kd == QP_RX) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = 0; ri[0][1] = -s; rr[1][0] = 0; ri[1][0] = -s; rr[1][1] = co; ri[1][1] = 0; }
+    else if (kd == QP_RY) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = -s; ri[0][1] = 0; rr[1][0] = s; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = 0; }
+    else { rr[0][0] = co; ri[0][0] = -s; rr[0][1] = 0; ri[0][1] = 0; rr[1][0] = 0; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = s; }
+    float nr[2][2], ni[2][2];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        nr[i][j] = rr[i][0] * ur[0][j] - ri[i][0] * ui[0][j] + rr[i][1] * ur[1][j] - ri[i][1] * ui[1][j];
+        ni[i][j] = rr[i][0] * ui[0][j] + ri[i][0] * ur[0][j] + rr[i][1] * ui[1][j] + ri[i][1] * ur[1][j];
+      }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) { ur[i][j] = nr[i][j]; ui[i][j] = ni[i][j]; }
+  }
+  float* o = const_cast<float*>(C.a.gtab) + G.idx * 8;
+  o[0] = ur[0][0]; o[1] = ui[0][0]; o[2] = ur[0][1]; o[3] = ui[0][1];
+  o[4] = ur[1][0]; o[5] = ui[1][0]; o[6] = ur[1][1]; o[7] = ui[1][1];
+}
+
+// Dielectric point counts per circuit (one workgroup per circuit).
+__global__ void k_batch_counts(const BatchCirc* __restrict__ circs) {
+  const BatchCirc& C = circs[blockIdx.x];
+  if (C.a.loss_kind != QP_LOSS_DIEL_SPLIT) return;
+  __shared__ int sh[4];
+  int c = 0;
+  for (long long p = threadIdx.x; p < C.a.P; p += blockDim.x) c += C.a.points[p * 3 + 1] >= C.a.x_if ? 1 : 0;
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int s = sh[0] + sh[1] + sh[2] + sh[3];
+    int* cnt = const_cast<int*>(C.a.counts);
+    cnt[0] = (int)(C.a.P - s);
+    cnt[1] = s;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void batch_tiles(const BatchCirc& C, const BatchItem& it, float2* buf, float* slots,
+                                            float* red, float& lacc) {
+  for (int t = it.tile0; t < it.tile0 + it.ntile; ++t)
+    fused_tile<N, kBT, kBEXS, kModeMaxwell>(C.a, t, buf, slots, red, lacc);
+}
+
+__global__ __launch_bounds__(kBT) void k_batch(const BatchCirc* __restrict__ circs, const BatchItem* __restrict__ items,
+                                               int nitems, int* __restrict__ counter, float* __restrict__ mpart,
+                                               float* __restrict__ lpart) {
+  constexpr int WAVES = kBT / 64;
+  constexpr int PLANE = kBT * 8;
+  extern __shared__ float4 smem4[];
+  float2* buf = reinterpret_cast<float2*>(smem4);
+  float* slots = reinterpret_cast<float*>(buf + kBEXS * PLANE);
+  __shared__ int s_item;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int id = s_item;
+    __syncthreads();
+    if (id >= nitems) break;
+    const BatchItem it = items[id];
+    const BatchCirc& C = circs[it.circ];
+    const int F = C.F;
+    float* red = slots + WAVES * F * 8;
+    for (int i = tid; i < WAVES * F * 8; i += kBT) slots[i] = 0.f;
+    __syncthreads();
+    float lacc = 0.f;
+    switch (C.n) {
+      case 3: batch_tiles<3>(C, it, buf, slots, red, lacc); break;
+      case 4: batch_tiles<4>(C, it, buf, slots, red, lacc); break;
+      case 5: batch_tiles<5>(C, it, buf, slots, red, lacc); break;
+      case 6: batch_tiles<6>(C, it, buf, slots, red, lacc); break;
+      case 7: batch_tiles<7>(C, it, buf, slots, red, lacc); break;
+      case 8: batch_tiles<8>(C, it, buf, slots, red, lacc); break;
+      case 9: batch_tiles<9>(C, it, buf, slots, red, lacc); break;
+      case 10: batch_tiles<10>(C, it, buf, slots, red, lacc); break;
+      case 11: batch_tiles<11>(C, it, buf, slots, red, lacc); break;
+      default: break;
+    }
+    __syncthreads();
+    float* mp = mpart + C.mpart_off + (long long)it.slot * F * 8;
+    for (int i = tid; i < F * 8; i += kBT) {
+      float s = 0.f;
+      for (int w = 0; w < WAVES; ++w) s += slots[w * F * 8 + i];
+      mp[i] = s;
+    }
+    for (int off = 32; off >= 1; off >>= 1) lacc += __shfl_xor(lacc, off);
+    if (lane == 0) red[wave * 40] = lacc;
+    __syncthreads();
+    if (tid == 0) {
+      float s = 0.f;
+      for (int w = 0; w < WAVES; ++w) s += red[w * 40];
+      lpart[C.item_lp0 + it.slot] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// One wave per (circuit, column): fixed-order FP64 sum over the circuit's items.
+__global__ void k_batch_reduce(const BatchCirc* __restrict__ circs, const BatchCol* __restrict__ cols, int ncols,
+                               const float* __restrict__ mpart, const float* __restrict__ lpart) {
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= ncols) return;
+  const BatchCol col = cols[w];
+  const BatchCirc& C = circs[col.circ];
+  const int ncol = C.F * 8;
+  double s = 0.0;
+  if (col.col < ncol) {
+    for (int b = lane; b < C.nitems; b += 64) s += (double)mpart[C.mpart_off + (long long)b * ncol + col.col];
+  } else {
+    for (int b = lane; b < C.nitems; b += 64) s += (double)lpart[C.item_lp0 + b];
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) {
+    if (col.col < ncol) C.m64[col.col] = s;
+    else *C.loss = s;
+  }
+}
+
+__global__ void k_batch_grads(const BatchCirc* __restrict__ circs, const BatchGate* __restrict__ pars, int npars) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npars) return;
+  const BatchGate g = pars[i];
+  const BatchCirc& C = circs[g.circ];
+  C.d_params[g.idx] = (float)param_grad_one(C.a.plan, C.params, C.m64, g.idx);
+}
+
+size_t batch_lds_bytes(int max_fused) {
+  return (size_t)kBEXS * kBT * 8 * sizeof(float2) + (size_t)(kBT / 64) * max_fused * 8 * sizeof(float) +
+         (size_t)(kBT / 64) * 40 * sizeof(float);
+}
+
+hipError_t batch_prepare(int max_fused) {
+  const size_t lds = batch_lds_bytes(max_fused);
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* items, int nitems,
+                        const BatchGate* gates, int ngates, const BatchCol* cols, int ncols,
+                        const BatchGate* pars, int npars, int* counter, float* mpart, float* lpart,
+                        int grid, int max_fused, int count_needed, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_gates, dim3(ngates > 0 ? (ngates + 127) / 128 : 1), dim3(128), 0, st,
+                     circs, gates, ngates, counter);
+  if (count_needed) hipLaunchKernelGGL(k_batch_counts, dim3(ncirc), dim3(256), 0, st, circs);
+  if (grid > 0 && nitems > 0)
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), batch_lds_bytes(max_fused), st, circs, items, nitems,
+                       counter, mpart, lpart);
+  hipLaunchKernelGGL(k_batch_reduce, dim3((ncols + 3) / 4), dim3(256), 0, st, circs, cols, ncols, mpart, lpart);
+  if (npars > 0) hipLaunchKernelGGL(k_batch_grads, dim3((npars + 127) / 128), dim3(128), 0, st, circs, pars, npars);
+  return hipGetLastError();
+}
+
+}  // namespace qp

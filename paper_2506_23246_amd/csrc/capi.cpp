@@ -1,0 +1,379 @@
+// C ABI of the QPINN circuit engine: contexts, circuit compilation, workspace layout and the
+// stream-ordered launch sequences of the fused, plain and batch paths.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qpinn.h"
+#include "batch.hpp"
+#include "capi_internal.hpp"
+#include "fused.hpp"
+#include "plain.hpp"
+#include "plan.hpp"
+#include "tune.hpp"
+
+using namespace qp;
+
+qp_status qp::fail(qp_ctx* c, qp_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+qp_status qp::hipcheck(qp_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QP_OK;
+  return fail(c, QP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- context -------------------
+extern "C" qp_status qp_ctx_create(int device, void* stream, qp_ctx** out) {
+  if (!out) return QP_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return QP_EDEVICE;
+  if (device < 0 || device >= ndev) return QP_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return QP_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return QP_EDEVICE;
+  auto* c = new qp_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->cu_count = prop.multiProcessorCount;
+  c->max_lds = prop.sharedMemPerBlock;
+  c->arch = prop.gcnArchName;
+  *out = c;
+  return QP_OK;
+}
+
+extern "C" qp_status qp_ctx_set_stream(qp_ctx* c, void* stream) {
+  if (!c) return QP_EINVAL;
+  c->stream = static_cast<hipStream_t>(stream);
+  return QP_OK;
+}
+
+extern "C" void qp_ctx_destroy(qp_ctx* c) { delete c; }
+
+extern "C" const char* qp_last_error(const qp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" qp_status qp_sync(qp_ctx* c) {
+  if (!c) return QP_EINVAL;
+  hipSetDevice(c->device);
+  return hipcheck(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+extern "C" int32_t qp_device_cu_count(const qp_ctx* c) { return c ? c->cu_count : 0; }
+
+// ---------------------------------------------------------------- circuits ------------------
+extern "C" qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* d, qp_circuit** out) {
+  if (!ctx || !d || !out) return fail(ctx, QP_EINVAL, "qp_circuit_compile: null argument");
+  *out = nullptr;
+  auto* c = new qp_circuit();
+  c->ctx = ctx;
+  int status = QP_OK;
+  std::string msg = build_plan(d, &c->hp, &status);
+  if (!msg.empty() || status != QP_OK) {
+    delete c;
+    return fail(ctx, (qp_status)status, "qp_circuit_compile: %s", msg.c_str());
+  }
+  hipSetDevice(ctx->device);
+  // plain-path gate list (device copy for the gate-table kernel)
+  c->pgates.resize(c->hp.gates.size());
+  for (size_t i = 0; i < c->hp.gates.size(); ++i)
+    c->pgates[i] = PlainGate{c->hp.gates[i].kind, c->hp.gates[i].q0, c->hp.gates[i].q1, c->hp.gates[i].param};
+  size_t bytes = c->hp.blob.size() + sizeof(PlainGate) * std::max<size_t>(1, c->pgates.size()) + 256;
+  if (hipMalloc(&c->dplan_raw, bytes) != hipSuccess) {
+    delete c;
+    return fail(ctx, QP_EDEVICE, "qp_circuit_compile: hipMalloc of %zu plan bytes failed", bytes);
+  }
+  c->dplan = static_cast<QPlanDev*>(c->dplan_raw);
+  c->dpgates = reinterpret_cast<PlainGate*>(static_cast<char*>(c->dplan_raw) + ((c->hp.blob.size() + 255) & ~size_t(255)));
+  hipError_t e = hipMemcpy(c->dplan_raw, c->hp.blob.data(), c->hp.blob.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !c->pgates.empty())
+    e = hipMemcpy(c->dpgates, c->pgates.data(), sizeof(PlainGate) * c->pgates.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(c->dplan_raw);
+    delete c;
+    return fail(ctx, QP_EDEVICE, "qp_circuit_compile: upload failed: %s", hipGetErrorString(e));
+  }
+  if (c->hp.fused_ok) choose_launch(ctx, c);
+  *out = c;
+  return QP_OK;
+}
+
+extern "C" void qp_circuit_destroy(qp_circuit* c) {
+  if (!c) return;
+  if (c->dplan_raw) hipFree(c->dplan_raw);
+  delete c;
+}
+
+extern "C" int64_t qp_circuit_info(const qp_circuit* c, int32_t what) {
+  if (!c) return -1;
+  switch (what) {
+    case 0: return c->hp.n;
+    case 1: return c->hp.K;
+    case 2: return c->hp.m;
+    case 3: return (int64_t)c->hp.fused.size();
+    case 4: return (int64_t)c->hp.rounds.size();
+    case 5: return c->hp.n_exchanges;
+    case 6: return c->hp.fused_ok ? fused_threads(c->hp.n) : 0;
+    case 7: return c->hp.fused_ok ? fused_points_per_tile(c->hp.n) : 0;
+    case 8: return c->exs;
+    case 9: return c->wg_per_cu;
+    default: return -1;
+  }
+}
+
+// Launch shape: points per tile are fixed by n; the LDS exchange depth (EXS statevector
+// planes per phase) and the persistent grid (workgroups per CU) come from the LDS budget,
+// optionally refined by the autotuner.
+void qp::choose_launch(qp_ctx* ctx, qp_circuit* c) {
+  const int n = c->hp.n;
+  const int F = (int)c->hp.fused.size();
+  const size_t lds_cap = 160 * 1024;
+  const int T = fused_threads(n);
+  const int max_wg_vgpr = (T == 512) ? 1 : 2;   // ~256 VGPRs per lane: 2 waves per SIMD
+  c->exs = 4;
+  size_t lds = fused_lds_bytes(n, 4, F);
+  if (lds * max_wg_vgpr > lds_cap) {
+    c->exs = 2;
+    lds = fused_lds_bytes(n, 2, F);
+  }
+  int wg = (int)std::min<size_t>(max_wg_vgpr, lds_cap / std::max<size_t>(lds, 1));
+  c->wg_per_cu = std::max(wg, 1);
+  const TuneEntry* te = tune_lookup(ctx, c);
+  if (te) { c->exs = te->exs; c->wg_per_cu = te->wg_per_cu; }
+}
+
+int qp::fused_grid(const qp_ctx* ctx, const qp_circuit* c, int64_t P) {
+  const int ppw = fused_points_per_tile(c->hp.n);
+  const int64_t ntiles = (P + ppw - 1) / ppw;
+  const int64_t cap = (int64_t)ctx->cu_count * c->wg_per_cu;
+  return (int)std::min<int64_t>(ntiles, cap);
+}
+
+WsLayout qp::fused_layout(const qp_circuit* c, int64_t P, int grid_cap) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  WsLayout L{};
+  const int F = (int)c->hp.fused.size();
+  size_t off = 0;
+  L.gtab = off; off = al(off + sizeof(float) * 8 * std::max(F, 1));
+  L.counts = off; off = al(off + 2 * sizeof(int));
+  if (c->hp.enc_kind == QP_ENC_RFF) {
+    L.angles = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n);
+    L.jac = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n * 3);
+  }
+  L.mpart = off; off = al(off + sizeof(float) * (size_t)grid_cap * F * 8);
+  L.lpart = off; off = al(off + sizeof(float) * (size_t)std::max(grid_cap, 1));
+  L.m64 = off; off = al(off + sizeof(double) * (size_t)std::max(F, 1) * 8);
+  L.total = off;
+  return L;
+}
+
+extern "C" size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags) {
+  (void)flags;
+  if (!c || P < 0) return 0;
+  const int cap = c->ctx->cu_count * 4;   // covers every launch shape the tuner may pick
+  return fused_layout(c, P, cap).total;
+}
+
+static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                              const float* angles, const float* jac, int64_t P, void* ws, size_t ws_bytes,
+                              const char* who) {
+  if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
+  if (P < 0) return fail(ctx, QP_EINVAL, "%s: P < 0", who);
+  if (!c->hp.fused_ok) return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
+  if (c->hp.K > 0 && !params) return fail(ctx, QP_EINVAL, "%s: params is null", who);
+  if (P > 0) {
+    if (c->hp.enc_kind == QP_ENC_ANGLES) {
+      if (!angles || !jac) return fail(ctx, QP_EINVAL, "%s: angle-given encoding needs angles and jac", who);
+    } else if (!points) {
+      return fail(ctx, QP_EINVAL, "%s: points is null", who);
+    }
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or not 256-byte aligned", who);
+  if (ws_bytes < qp_workspace_bytes(c, P, 0)) return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, qp_workspace_bytes(c, P, 0));
+  if (P > (int64_t)1 << 40) return fail(ctx, QP_EUNSUPPORTED, "%s: P too large", who);
+  return QP_OK;
+}
+
+// Shared launch sequence of the three fused entry points.
+qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
+                        const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
+                        float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
+                        uint32_t flags, int exs_override, int grid_override) {
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int n = c->hp.n;
+  const int F = (int)c->hp.fused.size();
+  const int cap = ctx->cu_count * 4;
+  const WsLayout L = fused_layout(c, P, cap);
+  char* w = static_cast<char*>(ws);
+  float* gtab = reinterpret_cast<float*>(w + L.gtab);
+  int* counts = reinterpret_cast<int*>(w + L.counts);
+  hipError_t e = launch_gate_table(c->dplan, F, params, gtab, st);
+  if (e != hipSuccess) return hipcheck(ctx, e, "gate table");
+  const float* ang = angles;
+  const float* jc = jac;
+  if (c->hp.enc_kind == QP_ENC_RFF) {
+    ang = reinterpret_cast<float*>(w + L.angles);
+    jc = reinterpret_cast<float*>(w + L.jac);
+    if ((e = launch_rff(c->dplan, points, P, const_cast<float*>(ang), const_cast<float*>(jc), st)) != hipSuccess)
+      return hipcheck(ctx, e, "rff angles");
+  }
+  if (mode == kModeMaxwell && ld->kind == QP_LOSS_DIEL_SPLIT) {
+    if ((e = launch_count(points, P, ld->x_interface, counts, st)) != hipSuccess) return hipcheck(ctx, e, "count");
+  }
+  int grid = fused_grid(ctx, c, P);
+  if (grid_override > 0) grid = (int)std::min<int64_t>(grid_override, (P + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
+  grid = std::min(grid, cap);
+  const int exs = exs_override > 0 ? exs_override : c->exs;
+  const size_t lds = fused_lds_bytes(n, exs, F);
+  FusedArgs a{};
+  a.plan = c->dplan;
+  a.gtab = gtab;
+  a.points = points;
+  a.angles = ang;
+  a.jac = jc;
+  a.P = P;
+  a.ntiles = (int)((P + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
+  a.n_fused = F;
+  a.out = out;
+  a.tan = tan;
+  a.d_out = d_out;
+  a.d_tan = d_tan;
+  a.loss_kind = ld ? ld->kind : QP_LOSS_VACUUM;
+  a.loss_sum = (flags & QP_FLAG_LOSS_SUM) ? 1 : 0;
+  a.eps_r = ld ? ld->eps_r : 1.f;
+  a.x_if = ld ? ld->x_interface : 0.f;
+  a.counts = counts;
+  a.mpart = reinterpret_cast<float*>(w + L.mpart);
+  a.lpart = reinterpret_cast<float*>(w + L.lpart);
+  if (grid > 0) {
+    if ((e = launch_fused(n, mode, a, grid, exs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
+  }
+  if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
+  double* m64 = reinterpret_cast<double*>(w + L.m64);
+  if ((e = launch_reduce(a.mpart, grid, F * 8, mode == kModeMaxwell ? a.lpart : nullptr, m64,
+                         mode == kModeMaxwell ? loss : nullptr, st)) != hipSuccess)
+    return hipcheck(ctx, e, "reduce");
+  if (d_params && (e = launch_param_grads(c->dplan, c->hp.K, params, m64, d_params, st)) != hipSuccess)
+    return hipcheck(ctx, e, "param grads");
+  return QP_OK;
+}
+
+extern "C" qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                                 const float* angles, const float* jac, int64_t P, float* out, float* tan, void* ws,
+                                 size_t ws_bytes, uint32_t flags) {
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_simulate");
+  if (s != QP_OK) return s;
+  if (P > 0 && !out) return fail(ctx, QP_EINVAL, "qp_simulate: out is null");
+  if (P > 0 && !tan && !(flags & QP_FLAG_NO_TANGENTS)) return fail(ctx, QP_EINVAL, "qp_simulate: tan is null");
+  return run_fused(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
+                   (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags, 0, 0);
+}
+
+extern "C" qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                            const float* angles, const float* jac, int64_t P, const float* d_out, const float* d_tan,
+                            float* d_params, void* ws, size_t ws_bytes, uint32_t flags) {
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_vjp");
+  if (s != QP_OK) return s;
+  if (c->hp.K > 0 && !d_params) return fail(ctx, QP_EINVAL, "qp_vjp: d_params is null");
+  return run_fused(ctx, c, kModeVjp, params, points, angles, jac, P, nullptr, nullptr, nullptr, d_out, d_tan, nullptr,
+                   d_params, ws, flags, 0, 0);
+}
+
+extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                                      const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld,
+                                      float* out, float* tan, double* loss, float* d_params, void* ws,
+                                      size_t ws_bytes, uint32_t flags) {
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_maxwell_fused");
+  if (s != QP_OK) return s;
+  if (!ld) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss descriptor is null");
+  if (ld->kind < QP_LOSS_VACUUM || ld->kind > QP_LOSS_DIEL_INTUITIVE) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: unknown loss kind");
+  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "qp_maxwell_fused: the Maxwell loss needs 3 outputs (E_z, H_x, H_y)");
+  if (ld->kind != QP_LOSS_VACUUM && P > 0 && !points) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: dielectric loss needs points");
+  if (!loss || (c->hp.K > 0 && !d_params)) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss/d_params null");
+  if ((flags & QP_FLAG_TUNE) && P > 0) tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws);
+  return run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
+                   ws, flags, 0, 0);
+}
+
+// ---------------------------------------------------------------- plain ---------------------
+static PlainProblem plain_problem(const qp_circuit* c, int64_t P) {
+  PlainProblem pr{};
+  pr.enc.n = c->hp.n;
+  pr.enc.kind = c->hp.enc_kind;
+  pr.enc.gate = c->hp.enc_gate;
+  pr.enc.scale = c->hp.enc_scale;
+  pr.enc.nf = c->hp.n_feat;
+  for (int q = 0; q < 16; ++q) pr.enc.coord[q] = c->hp.coord[q];
+  const char* pb = reinterpret_cast<const char*>(c->dplan_raw);
+  const QPlanDev* h = reinterpret_cast<const QPlanDev*>(c->hp.blob.data());
+  pr.enc.B = reinterpret_cast<const float*>(pb + h->off_rff_B);
+  pr.enc.W = reinterpret_cast<const float*>(pb + h->off_rff_W);
+  pr.m = c->hp.m;
+  pr.K = c->hp.K;
+  pr.n_gates = (int)c->pgates.size();
+  for (int i = 0; i < 8; ++i) pr.oq.q[i] = i < c->hp.m ? c->hp.out_qubits[i] : 0;
+  pr.gates_dev = c->dpgates;
+  pr.gates_host = c->pgates.data();
+  pr.P = P;
+  return pr;
+}
+
+extern "C" size_t qp_plain_workspace_bytes(const qp_circuit* c, int64_t P, int32_t precision) {
+  if (!c || P < 0 || (precision != 32 && precision != 64)) return 0;
+  return plain_layout(plain_problem(c, P), precision == 64 ? 8 : 4).total;
+}
+
+static qp_status plain_checks(qp_ctx* ctx, const qp_circuit* c, int precision, const void* params, const void* points,
+                              int64_t P, void* ws, size_t ws_bytes, const char* who) {
+  if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
+  if (precision != 32 && precision != 64) return fail(ctx, QP_EINVAL, "%s: precision must be 32 or 64", who);
+  if (P < 0) return fail(ctx, QP_EINVAL, "%s: P < 0", who);
+  if (c->hp.enc_kind == QP_ENC_ANGLES) return fail(ctx, QP_EUNSUPPORTED, "%s: the plain path needs a point encoding", who);
+  if ((c->hp.K > 0 && !params) || (P > 0 && !points)) return fail(ctx, QP_EINVAL, "%s: null params/points", who);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or misaligned", who);
+  if (ws_bytes < qp_plain_workspace_bytes(c, P, precision)) return fail(ctx, QP_EWORKSPACE, "%s: workspace too small", who);
+  return QP_OK;
+}
+
+extern "C" qp_status qp_plain_eval(qp_ctx* ctx, const qp_circuit* c, int32_t precision, const void* params,
+                                   const void* points, int64_t P, double fd_h, void* out, void* tan, void* ws,
+                                   size_t ws_bytes) {
+  qp_status s = plain_checks(ctx, c, precision, params, points, P, ws, ws_bytes, "qp_plain_eval");
+  if (s != QP_OK) return s;
+  if (P > 0 && !out) return fail(ctx, QP_EINVAL, "qp_plain_eval: out is null");
+  if (tan && !(fd_h > 0)) return fail(ctx, QP_EINVAL, "qp_plain_eval: fd_h must be > 0");
+  hipSetDevice(ctx->device);
+  return hipcheck(ctx, plain_eval(plain_problem(c, P), precision, params, points, fd_h, out, tan, ws, ctx->stream),
+                  "plain eval");
+}
+
+extern "C" qp_status qp_plain_maxwell_fd(qp_ctx* ctx, const qp_circuit* c, int32_t precision, const void* params,
+                                         const void* points, int64_t P, const qp_maxwell_desc* ld, double fd_h,
+                                         double fd_h_param, int32_t k_begin, int32_t k_end, double* loss,
+                                         void* d_params, void* ws, size_t ws_bytes) {
+  qp_status s = plain_checks(ctx, c, precision, params, points, P, ws, ws_bytes, "qp_plain_maxwell_fd");
+  if (s != QP_OK) return s;
+  if (!ld || !loss) return fail(ctx, QP_EINVAL, "qp_plain_maxwell_fd: null loss descriptor or loss");
+  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "qp_plain_maxwell_fd: needs 3 outputs");
+  if (k_begin < 0 || k_end > c->hp.K || k_begin > k_end) return fail(ctx, QP_EINVAL, "qp_plain_maxwell_fd: bad parameter range");
+  if (k_end > k_begin && !d_params) return fail(ctx, QP_EINVAL, "qp_plain_maxwell_fd: d_params is null");
+  if (!(fd_h > 0) || (k_end > k_begin && !(fd_h_param > 0))) return fail(ctx, QP_EINVAL, "qp_plain_maxwell_fd: steps must be > 0");
+  hipSetDevice(ctx->device);
+  return hipcheck(ctx, plain_maxwell(plain_problem(c, P), precision, params, points, *ld, 0, fd_h, fd_h_param, k_begin,
+                                     k_end, loss, d_params, ws, ctx->stream),
+                  "plain maxwell");
+}

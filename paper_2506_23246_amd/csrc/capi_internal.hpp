@@ -1,0 +1,47 @@
+// Internal definitions behind the opaque C handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qpinn.h"
+#include "plain.hpp"
+#include "plan.hpp"
+
+struct qp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+  size_t max_lds = 0;
+  std::string arch;
+  std::string err;
+};
+
+struct qp_circuit {
+  qp_ctx* ctx = nullptr;
+  qp::HostPlan hp;
+  void* dplan_raw = nullptr;
+  qp::QPlanDev* dplan = nullptr;
+  std::vector<qp::PlainGate> pgates;
+  qp::PlainGate* dpgates = nullptr;
+  int exs = 4;         // exchange planes per LDS phase
+  int wg_per_cu = 1;   // persistent workgroups per CU
+};
+
+namespace qp {
+
+struct WsLayout { size_t gtab, counts, angles, jac, mpart, lpart, m64, total; };
+
+qp_status fail(qp_ctx* c, qp_status s, const char* fmt, ...);
+qp_status hipcheck(qp_ctx* c, hipError_t e, const char* what);
+void choose_launch(qp_ctx* ctx, qp_circuit* c);
+int fused_grid(const qp_ctx* ctx, const qp_circuit* c, int64_t P);
+WsLayout fused_layout(const qp_circuit* c, int64_t P, int grid_cap);
+qp_status run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
+                    const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
+                    float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
+                    uint32_t flags, int exs_override, int grid_override);
+
+}  // namespace qp

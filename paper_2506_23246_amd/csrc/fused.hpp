@@ -1,0 +1,44 @@
+// Launch interface of the fused register/LDS kernels (fused.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/qpinn.h"
+#include "qp_internal.hpp"
+
+namespace qp {
+
+struct FusedArgs {
+  const QPlanDev* plan;
+  const float* gtab;      // [F][8] fused gate matrices
+  const float* points;    // [P][3]
+  const float* angles;    // [P][n]   (angle-given or RFF encodings)
+  const float* jac;       // [P][n][3]
+  long long P;
+  int ntiles;
+  int n_fused;
+  float* out;             // [P][m] or null
+  float* tan;             // [P][m][3] or null
+  const float* d_out;     // VJP seeds [P][m] or null
+  const float* d_tan;     // VJP seeds [P][m][3] or null
+  int loss_kind;
+  int loss_sum;           // 1: plain sums (weights 1) instead of means
+  float eps_r, x_if;
+  const int* counts;      // [2]: points with x < x_if, points with x >= x_if
+  float* mpart;           // [grid][F][8]
+  float* lpart;           // [grid]
+};
+
+int fused_threads(int n);
+int fused_points_per_tile(int n);
+size_t fused_lds_bytes(int n, int exs, int n_fused);
+hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
+hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, hipStream_t st);
+hipError_t launch_rff(const QPlanDev* plan, const float* points, long long P, float* angles, float* jac, hipStream_t st);
+hipError_t launch_count(const float* points, long long P, float x_if, int* counts, hipStream_t st);
+hipError_t launch_reduce(const float* mpart, int nblk, int ncol, const float* lpart, double* m64, double* loss, hipStream_t st);
+hipError_t launch_param_grads(const QPlanDev* plan, int K, const float* params, const double* m64, float* grads, hipStream_t st);
+
+}  // namespace qp

@@ -1,0 +1,570 @@
+// Templates of the fused register/LDS kernel (included by the per-qubit-count units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qp_internal.hpp"
+#include "fused.hpp"
+
+namespace qp {
+
+__device__ __forceinline__ uint32_t parity(uint32_t x) { return __popc(x) & 1u; }
+
+// LDS index swizzle: XOR the low nibble with the fold of all higher nibbles (a bijection).
+__device__ __forceinline__ uint32_t swz(uint32_t idx) {
+  uint32_t h = idx >> 4;
+  h ^= h >> 4;
+  h ^= h >> 8;
+  return idx ^ (h & 15u);
+}
+
+template <int N>
+__device__ __forceinline__ uint32_t deposit_thread(uint32_t u, const uint8_t* __restrict__ tpos) {
+  uint32_t j = 0;
+#pragma unroll
+  for (int k = 3; k < N; ++k) j |= ((u >> (k - 3)) & 1u) << tpos[k];
+  return j;
+}
+
+__device__ __forceinline__ uint32_t reg_off(int r, uint32_t p0, uint32_t p1, uint32_t p2) {
+  return ((uint32_t)(r & 1) << p0) | ((uint32_t)((r >> 1) & 1) << p1) |
+         ((uint32_t)((r >> 2) & 1) << p2);
+}
+
+// ---- single-qubit gate on register bit B for statevectors [S0, S0+NS) ----------------------
+// u: u00r,u00i,u01r,u01i,u10r,u10i,u11r,u11i
+template <int B, int S0, int NS>
+__device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8], const float* u) {
+  const float a0r = u[0], a0i = u[1], a1r = u[2], a1i = u[3];
+  const float b0r = u[4], b0i = u[5], b1r = u[6], b1i = u[7];
+#pragma unroll
+  for (int s = S0; s < S0 + NS; ++s) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r & (1 << B)) continue;
+      const int r1 = r | (1 << B);
+      const float xr = sr[s][r], xi = si[s][r], yr = sr[s][r1], yi = si[s][r1];
+      sr[s][r] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
+      si[s][r] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
+      sr[s][r1] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
+      si[s][r1] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
+    }
+  }
+}
+
+// conj-transpose of a gate table entry
+__device__ __forceinline__ void dagger(const float* u, float* d) {
+  d[0] = u[0]; d[1] = -u[1];   // (0,0) <- conj u00
+  d[2] = u[4]; d[3] = -u[5];   // (0,1) <- conj u10
+  d[4] = u[2]; d[5] = -u[3];   // (1,0) <- conj u01
+  d[6] = u[6]; d[7] = -u[7];   // (1,1) <- conj u11
+}
+
+// M_ab += conj(x_a) y_b over register pairs of bit B; x = statevector XS+s, y = statevector s.
+template <int B>
+__device__ __forceinline__ void accum_m(const float (&sr)[8][8], const float (&si)[8][8], float* m) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r & (1 << B)) continue;
+      const int r1 = r | (1 << B);
+      const float x0r = sr[4 + s][r], x0i = si[4 + s][r], x1r = sr[4 + s][r1], x1i = si[4 + s][r1];
+      const float y0r = sr[s][r], y0i = si[s][r], y1r = sr[s][r1], y1i = si[s][r1];
+      // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
+      m[0] += x0r * y0r + x0i * y0i;  m[1] += x0r * y0i - x0i * y0r;
+      m[2] += x0r * y1r + x0i * y1i;  m[3] += x0r * y1i - x0i * y1r;
+      m[4] += x1r * y0r + x1i * y0i;  m[5] += x1r * y0i - x1i * y0r;
+      m[6] += x1r * y1r + x1i * y1i;  m[7] += x1r * y1i - x1i * y1r;
+    }
+  }
+}
+
+// Reduce 8 floats over the 64 lanes of a wave; afterwards lane 8*e holds the sum of entry e.
+__device__ __forceinline__ float wave_reduce_scatter8(const float* v, int lane) {
+  const bool h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1;
+  float a[4], b[2], c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float send = h5 ? v[i] : v[4 + i];
+    const float keep = h5 ? v[4 + i] : v[i];
+    a[i] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = h4 ? a[i] : a[2 + i];
+    const float keep = h4 ? a[2 + i] : a[i];
+    b[i] = keep + __shfl_xor(send, 16);
+  }
+  {
+    const float send = h3 ? b[0] : b[1];
+    const float keep = h3 ? b[1] : b[0];
+    c = keep + __shfl_xor(send, 8);
+  }
+  c += __shfl_xor(c, 4);
+  c += __shfl_xor(c, 2);
+  c += __shfl_xor(c, 1);
+  return c;   // entry index (h5*4 + h4*2 + h3) on every lane of the octet
+}
+
+// ---- register exchange through LDS ----------------------------------------------------------
+// Writes statevectors [0, NSV) in the writer mapping `wr`, reads them back in mapping `rd`
+// through the exchange descriptor X (index map and sign), in groups of EXS planes.
+template <int N, int T, int NSV, int EXS>
+__device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
+                                         const QRound* __restrict__ wr, const QRound* __restrict__ rd,
+                                         const QXchg* __restrict__ X, uint32_t u, uint32_t pbase) {
+  constexpr int PLANE = T * 8;
+  const uint32_t jw = deposit_thread<N>(u, wr->tpos);
+  const uint32_t w0 = wr->tpos[0], w1 = wr->tpos[1], w2 = wr->tpos[2];
+  const uint32_t jn = deposit_thread<N>(u, rd->tpos);
+  uint32_t sb;
+  uint32_t sgn = 0;   // bit r set: negate amplitude r
+  if (X->identity) {
+    sb = jn;
+  } else {
+    sb = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      if ((jn >> k) & 1u) sb ^= X->acol[k];
+    const int nt = X->nterms;
+    if (nt > 0) {
+      const uint32_t xb = X->sign_at_src ? sb : jn;
+      uint32_t pu = 0, pv = 0;
+      for (int t = 0; t < nt; ++t) {
+        pu |= parity(X->qu[t] & xb) << t;
+        pv |= parity(X->qv[t] & xb) << t;
+      }
+      const uint32_t q0 = parity(pu & pv);
+      const uint32_t b0 = parity((pu & X->ve[0]) ^ (X->ue[0] & pv));
+      const uint32_t b1 = parity((pu & X->ve[1]) ^ (X->ue[1] & pv));
+      const uint32_t b2 = parity((pu & X->ve[2]) ^ (X->ue[2] & pv));
+      const uint32_t qs = X->qsign_r;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        uint32_t s = q0 ^ ((qs >> r) & 1u);
+        if (r & 1) s ^= b0;
+        if (r & 2) s ^= b1;
+        if (r & 4) s ^= b2;
+        sgn |= s << r;
+      }
+    }
+  }
+  uint32_t srcr[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) srcr[r] = X->identity ? reg_off(r, rd->tpos[0], rd->tpos[1], rd->tpos[2]) : X->src_r[r];
+#pragma unroll
+  for (int g = 0; g < NSV; g += EXS) {
+#pragma unroll
+    for (int s = 0; s < EXS; ++s)
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        buf[s * PLANE + swz(pbase + (jw ^ reg_off(r, w0, w1, w2)))] = make_float2(sr[g + s][r], si[g + s][r]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EXS; ++s)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const float2 v = buf[s * PLANE + swz(pbase + (sb ^ srcr[r]))];
+        const bool neg = (sgn >> r) & 1u;
+        sr[g + s][r] = neg ? -v.x : v.x;
+        si[g + s][r] = neg ? -v.y : v.y;
+      }
+    __syncthreads();
+  }
+}
+
+// ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
+// buf: EXS exchange planes; slots: per-wave M accumulators [WAVES][F][8]; red: [WAVES][40].
+template <int N, int T, int EXS, int MODE>
+__device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
+                                           float* __restrict__ slots, float* __restrict__ red, float& lacc) {
+  constexpr int TP = 1 << (N - 3);         // threads per point
+  constexpr int PPW = T / TP;              // points per workgroup tile
+  constexpr int DIM = 1 << N;
+  static_assert(PPW >= 1, "tile too small");
+  const QPlanDev* __restrict__ plan = a.plan;
+  const char* pb = reinterpret_cast<const char*>(plan);
+  const QRound* __restrict__ rounds = reinterpret_cast<const QRound*>(pb + plan->off_rounds);
+  const QXchg* __restrict__ xf = reinterpret_cast<const QXchg*>(pb + plan->off_xf);
+  const QXchg* __restrict__ xb = reinterpret_cast<const QXchg*>(pb + plan->off_xb);
+  const int R = plan->n_rounds;
+  const int m = plan->n_out;
+  const int F = a.n_fused;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int ps = tid / TP;
+  const uint32_t u = (uint32_t)(tid % TP);
+  const uint32_t pbase = (uint32_t)ps * DIM;
+  // loss weights: 1/P for the mean over all points, 1/N_vac and 1/N_diel for the split loss
+  float w_all = 1.f, w_vac = 1.f, w_diel = 1.f;
+  if (MODE == kModeMaxwell && !a.loss_sum) {
+    w_all = a.P > 0 ? 1.f / (float)a.P : 0.f;
+    if (a.loss_kind == QP_LOSS_DIEL_SPLIT) {
+      const int nv = a.counts[0], nd = a.counts[1];
+      w_vac = nv > 0 ? 1.f / (float)nv : 0.f;
+      w_diel = nd > 0 ? 1.f / (float)nd : 0.f;
+    }
+  }
+  float sr[8][8], si[8][8];
+  {
+    const long long pt = (long long)tile * PPW + ps;
+    const bool valid = pt < a.P;
+
+    // ---------------- encoding: per-qubit embedded amplitudes and derivatives -------------
+    float e0r[N], e1r[N], e1i[N], d0r[N], d1r[N], d1i[N], jq[N][3];
+    {
+      float p3[3] = {0.f, 0.f, 0.f};
+      if (valid && a.points && plan->enc_kind != QP_ENC_ANGLES) {
+        p3[0] = a.points[pt * 3 + 0];
+        p3[1] = a.points[pt * 3 + 1];
+        p3[2] = a.points[pt * 3 + 2];
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        float c, s, j0 = 0.f, j1 = 0.f, j2 = 0.f;
+        if (plan->enc_kind == QP_ENC_CYCLE) {
+          const int cc = plan->coord_of_qubit[q];
+          const float x = cc == 0 ? p3[0] : (cc == 1 ? p3[1] : p3[2]);
+          float jv;
+          const int sc = plan->enc_scale;
+          if (sc == QP_SCALE_PI) {           // theta/2 = pi x/2
+            sincospif(0.5f * x, &s, &c);
+            jv = 3.14159265358979323846f;
+          } else if (sc == QP_SCALE_BIAS) {  // theta/2 = pi (x+1)/4
+            sincospif(0.25f * (x + 1.f), &s, &c);
+            jv = 1.57079632679489661923f;
+          } else if (sc == QP_SCALE_NONE) {
+            sincosf(0.5f * x, &s, &c);
+            jv = 1.f;
+          } else {
+            const float xx = fminf(fmaxf(x, -1.f), 1.f);
+            const float th = (sc == QP_SCALE_ASIN) ? asinf(xx) + 1.57079632679489661923f : acosf(xx);
+            sincosf(0.5f * th, &s, &c);
+            const float rs = 1.f / sqrtf(fmaxf(1.f - xx * xx, 0.f));
+            jv = (sc == QP_SCALE_ASIN) ? rs : -rs;
+          }
+          j0 = cc == 0 ? jv : 0.f;
+          j1 = cc == 1 ? jv : 0.f;
+          j2 = cc == 2 ? jv : 0.f;
+        } else {
+          float th = 0.f;
+          if (valid) {
+            th = a.angles[pt * N + q];
+            j0 = a.jac[(pt * N + q) * 3 + 0];
+            j1 = a.jac[(pt * N + q) * 3 + 1];
+            j2 = a.jac[(pt * N + q) * 3 + 2];
+          }
+          sincosf(0.5f * th, &s, &c);
+        }
+        e0r[q] = c;
+        d0r[q] = -0.5f * s;
+        if (plan->enc_gate == QP_ENC_RY) {
+          e1r[q] = s; e1i[q] = 0.f; d1r[q] = 0.5f * c; d1i[q] = 0.f;
+        } else {   // RX|0> = (cos, -i sin)
+          e1r[q] = 0.f; e1i[q] = -s; d1r[q] = 0.f; d1i[q] = -0.5f * c;
+        }
+        jq[q][0] = j0; jq[q][1] = j1; jq[q][2] = j2;
+      }
+    }
+    // ---------------- product state and tangent seeds in round 0's mapping ---------------
+    {
+      const QRound* r0 = rounds;
+      // thread part: (P, D_c) by the product rule over the thread qubits
+      float Pr = valid ? 1.f : 0.f, Pi = 0.f;
+      float Dr[3] = {0.f, 0.f, 0.f}, Di[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 3; k < N; ++k) {
+        const int q = N - 1 - r0->tpos[k];
+        const bool bit = (u >> (k - 3)) & 1u;
+        float er = 0.f, ei = 0.f, dr = 0.f, di = 0.f, jj[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq)
+          if (qq == q) {
+            er = bit ? e1r[qq] : e0r[qq];
+            ei = bit ? e1i[qq] : 0.f;
+            dr = bit ? d1r[qq] : d0r[qq];
+            di = bit ? d1i[qq] : 0.f;
+            jj[0] = jq[qq][0]; jj[1] = jq[qq][1]; jj[2] = jq[qq][2];
+          }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float nr = Dr[c] * er - Di[c] * ei + jj[c] * (Pr * dr - Pi * di);
+          const float ni = Dr[c] * ei + Di[c] * er + jj[c] * (Pr * di + Pi * dr);
+          Dr[c] = nr; Di[c] = ni;
+        }
+        const float npr = Pr * er - Pi * ei, npi = Pr * ei + Pi * er;
+        Pr = npr; Pi = npi;
+      }
+      float qer[3][2], qei[3][2], qdr[3][2], qdi[3][2], qj[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int q = N - 1 - r0->tpos[i];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq)
+          if (qq == q) {
+            qer[i][0] = e0r[qq]; qei[i][0] = 0.f; qer[i][1] = e1r[qq]; qei[i][1] = e1i[qq];
+            qdr[i][0] = d0r[qq]; qdi[i][0] = 0.f; qdr[i][1] = d1r[qq]; qdi[i][1] = d1i[qq];
+            qj[i][0] = jq[qq][0]; qj[i][1] = jq[qq][1]; qj[i][2] = jq[qq][2];
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        float pr = Pr, pi = Pi, dr[3] = {Dr[0], Dr[1], Dr[2]}, di[3] = {Di[0], Di[1], Di[2]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int b = (r >> i) & 1;
+          const float er = qer[i][b], ei = qei[i][b], ddr = qdr[i][b], ddi = qdi[i][b];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float nr = dr[c] * er - di[c] * ei + qj[i][c] * (pr * ddr - pi * ddi);
+            const float ni = dr[c] * ei + di[c] * er + qj[i][c] * (pr * ddi + pi * ddr);
+            dr[c] = nr; di[c] = ni;
+          }
+          const float npr = pr * er - pi * ei, npi = pr * ei + pi * er;
+          pr = npr; pi = npi;
+        }
+        sr[0][r] = pr; si[0][r] = pi;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { sr[1 + c][r] = dr[c]; si[1 + c][r] = di[c]; }
+      }
+    }
+    // ---------------- forward rounds -------------------------------------------------------
+    for (int k = 0; k < R; ++k) {
+      const QRound* rk = rounds + k;
+      if (k > 0) exchange<N, T, 4, (EXS < 4 ? EXS : 4)>(sr, si, buf, rk - 1, rk, xf + k, u, pbase);
+      float g[8];
+      if (rk->gate[0] >= 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[0] * 8 + e];
+        apply_gate<0, 0, 4>(sr, si, g);
+      }
+      if (rk->gate[1] >= 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[1] * 8 + e];
+        apply_gate<1, 0, 4>(sr, si, g);
+      }
+      if (rk->gate[2] >= 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[2] * 8 + e];
+        apply_gate<2, 0, 4>(sr, si, g);
+      }
+    }
+    // ---------------- readout ----------------------------------------------------------------
+    const QRound* rl = rounds + (R - 1);
+    const uint32_t jl = deposit_thread<N>(u, rl->tpos);
+    const uint32_t l0 = rl->tpos[0], l1 = rl->tpos[1], l2 = rl->tpos[2];
+    float acc[kMaxOut * 4];
+#pragma unroll
+    for (int i = 0; i < kMaxOut * 4; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t j = jl ^ reg_off(r, l0, l1, l2);
+      const float p2 = sr[0][r] * sr[0][r] + si[0][r] * si[0][r];
+      float gc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gc[c] = 2.f * (sr[0][r] * sr[1 + c][r] + si[0][r] * si[1 + c][r]);
+#pragma unroll
+      for (int i = 0; i < kMaxOut; ++i) {
+        if (i < m) {
+          const float z = parity(plan->zmask[i] & j) ? -1.f : 1.f;
+          acc[i * 4 + 0] += z * p2;
+          acc[i * 4 + 1] += z * gc[0];
+          acc[i * 4 + 2] += z * gc[1];
+          acc[i * 4 + 3] += z * gc[2];
+        }
+      }
+    }
+    // all-reduce over the point's thread group
+    if (TP <= 64) {
+#pragma unroll
+      for (int off = 1; off < (TP < 64 ? TP : 64); off <<= 1)
+#pragma unroll
+        for (int i = 0; i < kMaxOut * 4; ++i)
+          if (i < 4 * m) acc[i] += __shfl_xor(acc[i], off);
+    } else {
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < kMaxOut * 4; ++i)
+          if (i < 4 * m) acc[i] += __shfl_xor(acc[i], off);
+      if (lane == 0)
+        for (int i = 0; i < 4 * m; ++i) red[wave * 40 + i] = acc[i];
+      __syncthreads();
+      constexpr int WPP = TP / 64;   // waves per point
+      const int w0 = (wave / WPP) * WPP;
+#pragma unroll
+      for (int i = 0; i < kMaxOut * 4; ++i) {
+        if (i < 4 * m) {
+          float s = 0.f;
+          for (int w = 0; w < WPP; ++w) s += red[(w0 + w) * 40 + i];
+          acc[i] = s;
+        }
+      }
+      __syncthreads();
+    }
+    if (valid && u == 0) {
+      for (int i = 0; i < m; ++i) {
+        if (a.out) a.out[pt * m + i] = acc[i * 4];
+        if (a.tan) {
+          a.tan[(pt * m + i) * 3 + 0] = acc[i * 4 + 1];
+          a.tan[(pt * m + i) * 3 + 1] = acc[i * 4 + 2];
+          a.tan[(pt * m + i) * 3 + 2] = acc[i * 4 + 3];
+        }
+      }
+    }
+    if (MODE == kModeFwd) return;
+
+    // ---------------- seeds -----------------------------------------------------------------
+    float Wv[kMaxOut][3], Vv[kMaxOut];
+#pragma unroll
+    for (int i = 0; i < kMaxOut; ++i) { Vv[i] = 0.f; Wv[i][0] = Wv[i][1] = Wv[i][2] = 0.f; }
+    if (MODE == kModeMaxwell) {
+      if (valid) {
+        const float gEt = acc[1], gEx = acc[2], gEy = acc[3];
+        const float gXt = acc[5], gXy = acc[7];
+        const float gYt = acc[9], gYx = acc[10];
+        float eps = 1.f, w1 = w_all;
+        if (a.loss_kind != QP_LOSS_VACUUM) {
+          const float x = a.points[pt * 3 + 1];
+          const bool diel = x >= a.x_if;
+          eps = diel ? a.eps_r : 1.f;
+          if (a.loss_kind == QP_LOSS_DIEL_SPLIT) w1 = diel ? w_diel : w_vac;
+        }
+        const float ie = 1.f / eps;
+        const float r1 = gEt - (gYx - gXy) * ie;
+        const float r2 = gXt + gEy;
+        const float r3 = gYt - gEx;
+        const float w = w_all;
+        lacc += (u == 0) ? (w1 * r1 * r1 + w * (r2 * r2 + r3 * r3)) : 0.f;
+        const float A = 2.f * w1 * r1, Bq = 2.f * w * r2, C = 2.f * w * r3;
+        Wv[0][0] = A;  Wv[2][1] = -A * ie;  Wv[1][2] = A * ie;
+        Wv[1][0] = Bq; Wv[0][2] += Bq;
+        Wv[2][0] = C;  Wv[0][1] += -C;
+      }
+    } else {   // VJP seeds
+      if (valid) {
+        for (int i = 0; i < m; ++i) {
+          if (a.d_out) Vv[i] = a.d_out[pt * m + i];
+          if (a.d_tan) {
+            Wv[i][0] = a.d_tan[(pt * m + i) * 3 + 0];
+            Wv[i][1] = a.d_tan[(pt * m + i) * 3 + 1];
+            Wv[i][2] = a.d_tan[(pt * m + i) * 3 + 2];
+          }
+        }
+      }
+    }
+    // lambda = Df psi + sum_c D_c dpsi_c, mu_c = D_c psi (D real diagonal in the final basis)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t j = jl ^ reg_off(r, l0, l1, l2);
+      float Df = 0.f, D0 = 0.f, D1 = 0.f, D2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < kMaxOut; ++i) {
+        if (i < m) {
+          const float z = parity(plan->zmask[i] & j) ? -1.f : 1.f;
+          Df += z * Vv[i];
+          D0 += z * Wv[i][0];
+          D1 += z * Wv[i][1];
+          D2 += z * Wv[i][2];
+        }
+      }
+      sr[4][r] = Df * sr[0][r] + D0 * sr[1][r] + D1 * sr[2][r] + D2 * sr[3][r];
+      si[4][r] = Df * si[0][r] + D0 * si[1][r] + D1 * si[2][r] + D2 * si[3][r];
+      sr[5][r] = D0 * sr[0][r]; si[5][r] = D0 * si[0][r];
+      sr[6][r] = D1 * sr[0][r]; si[6][r] = D1 * si[0][r];
+      sr[7][r] = D2 * sr[0][r]; si[7][r] = D2 * si[0][r];
+    }
+    // ---------------- adjoint sweep with uncompute -----------------------------------------
+    for (int k = R - 1; k >= 0; --k) {
+      const QRound* rk = rounds + k;
+#pragma unroll
+      for (int bb = 2; bb >= 0; --bb) {
+        const int gid = rk->gate[bb];
+        if (gid < 0) continue;
+        float g[8], d[8], mm[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) { g[e] = a.gtab[gid * 8 + e]; mm[e] = 0.f; }
+        dagger(g, d);
+        if (bb == 0) { apply_gate<0, 0, 4>(sr, si, d); accum_m<0>(sr, si, mm); apply_gate<0, 4, 4>(sr, si, d); }
+        if (bb == 1) { apply_gate<1, 0, 4>(sr, si, d); accum_m<1>(sr, si, mm); apply_gate<1, 4, 4>(sr, si, d); }
+        if (bb == 2) { apply_gate<2, 0, 4>(sr, si, d); accum_m<2>(sr, si, mm); apply_gate<2, 4, 4>(sr, si, d); }
+        const float v = wave_reduce_scatter8(mm, lane);
+        if ((lane & 7) == 0) {
+          const int e = (((lane >> 5) & 1) << 2) | (((lane >> 4) & 1) << 1) | ((lane >> 3) & 1);
+          slots[(wave * F + gid) * 8 + e] += v;
+        }
+      }
+      if (k > 0) exchange<N, T, 8, EXS>(sr, si, buf, rk, rk - 1, xb + k, u, pbase);
+    }
+  }
+}
+
+// ---- the fused kernel: a persistent grid walks the tiles ------------------------------------
+template <int N, int T, int EXS, int MODE>
+__global__ __launch_bounds__(T) void k_fused(FusedArgs a) {
+  constexpr int WAVES = T / 64;
+  constexpr int PLANE = T * 8;
+  extern __shared__ float4 smem4[];
+  float2* buf = reinterpret_cast<float2*>(smem4);
+  float* slots = reinterpret_cast<float*>(buf + EXS * PLANE);      // [WAVES][F][8]
+  float* red = slots + WAVES * a.n_fused * 8;                        // [WAVES][40]
+  const int F = a.n_fused;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  if (MODE != kModeFwd) {
+    for (int i = tid; i < WAVES * F * 8; i += T) slots[i] = 0.f;
+  }
+  __syncthreads();
+  float lacc = 0.f;
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+    fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+  if (MODE == kModeFwd) return;
+  // ---------------- per-workgroup partials (fixed order) -----------------------------------
+  __syncthreads();
+  for (int i = tid; i < F * 8; i += T) {
+    float s = 0.f;
+    for (int w = 0; w < WAVES; ++w) s += slots[w * F * 8 + i];
+    a.mpart[(long long)blockIdx.x * F * 8 + i] = s;
+  }
+  if (MODE == kModeMaxwell) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) lacc += __shfl_xor(lacc, off);
+    __syncthreads();
+    if (lane == 0) red[wave * 40] = lacc;
+    __syncthreads();
+    if (tid == 0) {
+      float s = 0.f;
+      for (int w = 0; w < WAVES; ++w) s += red[w * 40];
+      a.lpart[blockIdx.x] = s;
+    }
+  }
+}
+
+
+template <int N, int EXS, int MODE>
+hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) {
+  constexpr int T = (N == 12) ? 512 : 256;
+  auto kern = k_fused<N, T, EXS, MODE>;
+  static size_t attr_bytes = 0;
+  if (lds > 64 * 1024 && lds > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_bytes = lds;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(T), lds, st, a);
+  return hipGetLastError();
+}
+
+// Entry point of one per-N unit.
+template <int N>
+hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
+  if (mode == kModeFwd) return exs == 2 ? launch_one<N, 2, kModeFwd>(a, grid, lds, st) : launch_one<N, 4, kModeFwd>(a, grid, lds, st);
+  if (mode == kModeMaxwell) return exs == 2 ? launch_one<N, 2, kModeMaxwell>(a, grid, lds, st) : launch_one<N, 4, kModeMaxwell>(a, grid, lds, st);
+  return exs == 2 ? launch_one<N, 2, kModeVjp>(a, grid, lds, st) : launch_one<N, 4, kModeVjp>(a, grid, lds, st);
+}
+
+}  // namespace qp

@@ -1,0 +1,8 @@
+// Instantiation of the fused kernel for 4 qubits.
+#include "fused_kernel.hpp"
+
+namespace qp {
+hipError_t launch_fused_4(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
+  return launch_fused_n<4>(mode, a, grid, exs, lds, st);
+}
+}  // namespace qp

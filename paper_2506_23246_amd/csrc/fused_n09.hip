@@ -1,0 +1,8 @@
+// Instantiation of the fused kernel for 9 qubits.
+#include "fused_kernel.hpp"
+
+namespace qp {
+hipError_t launch_fused_9(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
+  return launch_fused_n<9>(mode, a, grid, exs, lds, st);
+}
+}  // namespace qp

@@ -1,0 +1,429 @@
+// Circuit planner for the fused register/LDS kernels.
+//
+// A circuit is a time-ordered list of rotations (RX/RY/RZ) and entanglers (CNOT/CZ).  The
+// planner
+//   1. fuses consecutive rotations on one qubit into one 2x2 gate (up to three components,
+//      e.g. RZ(omega) RY(theta) RZ(phi) of the Rot gate, eq. rot_gate);
+//   2. turns every maximal run of CNOT/CZ gates into one affine stage
+//         psi_out(j') = (-1)^Q(j') psi_in(A j'),
+//      with A an invertible GF(2) matrix on index bits and Q a quadratic form (a CNOT ring is a
+//      pure index permutation, a CZ ring a pure sign function);
+//   3. groups the fused gates of every rotation stage into rounds of three qubits (the three
+//      register bits of a thread) and attaches each entangler stage to the register exchange
+//      that precedes the next round; a trailing stage is folded into the readout masks.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+namespace qp {
+
+namespace {
+
+inline int popc(uint32_t x) { return __builtin_popcount(x); }
+inline uint32_t par(uint32_t x) { return popc(x) & 1u; }
+
+struct Affine {            // psi_out(j') = (-1)^Q(j') psi_in(A j')
+  int n = 0;
+  uint32_t acol[16];
+  std::vector<std::pair<uint32_t, uint32_t>> terms;
+  void init(int nn) {
+    n = nn;
+    for (int k = 0; k < 16; ++k) acol[k] = (k < n) ? (1u << k) : 0u;
+    terms.clear();
+  }
+  // Append CNOT(control bit bc, target bit bt): A <- A X, Q <- Q o X.
+  void cnot(int bc, int bt) {
+    acol[bc] ^= acol[bt];
+    for (auto& t : terms) {
+      if ((t.first >> bt) & 1u) t.first ^= (1u << bc);
+      if ((t.second >> bt) & 1u) t.second ^= (1u << bc);
+    }
+  }
+  void cz(int ba, int bb) { terms.emplace_back(1u << ba, 1u << bb); }
+  bool is_identity() const {
+    for (int k = 0; k < n; ++k)
+      if (acol[k] != (1u << k)) return false;
+    return terms.empty();
+  }
+};
+
+uint32_t apply_cols(const uint32_t* cols, int n, uint32_t x) {
+  uint32_t y = 0;
+  for (int k = 0; k < n; ++k)
+    if ((x >> k) & 1u) y ^= cols[k];
+  return y;
+}
+
+// Inverse of an invertible GF(2) matrix given by columns.
+bool gf2_inverse(const uint32_t* cols, int n, uint32_t* inv) {
+  // rows of [A | I]
+  uint32_t rowsA[16], rowsI[16];
+  for (int i = 0; i < n; ++i) {
+    rowsA[i] = 0;
+    for (int k = 0; k < n; ++k)
+      if ((cols[k] >> i) & 1u) rowsA[i] |= (1u << k);
+    rowsI[i] = 1u << i;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = -1;
+    for (int r = c; r < n; ++r)
+      if ((rowsA[r] >> c) & 1u) { piv = r; break; }
+    if (piv < 0) return false;
+    std::swap(rowsA[c], rowsA[piv]);
+    std::swap(rowsI[c], rowsI[piv]);
+    for (int r = 0; r < n; ++r)
+      if (r != c && ((rowsA[r] >> c) & 1u)) { rowsA[r] ^= rowsA[c]; rowsI[r] ^= rowsI[c]; }
+  }
+  for (int k = 0; k < n; ++k) {   // columns of the inverse from its rows
+    inv[k] = 0;
+    for (int i = 0; i < n; ++i)
+      if ((rowsI[i] >> k) & 1u) inv[k] |= (1u << i);
+  }
+  for (int k = n; k < 16; ++k) inv[k] = 0;
+  return true;
+}
+
+uint32_t qform(const std::vector<std::pair<uint32_t, uint32_t>>& terms, uint32_t x) {
+  uint32_t s = 0;
+  for (auto& t : terms) s ^= par(t.first & x) & par(t.second & x);
+  return s;
+}
+
+// Thread-bit order for a round: register bits first, then the remaining positions chosen so
+// that each group of four consecutive lane bits lands on distinct position residues mod 4
+// (the LDS swizzle folds higher nibbles into the low four bits).
+void make_tpos(int n, const int reg[3], uint8_t* tpos) {
+  bool used[16] = {false};
+  for (int i = 0; i < 3; ++i) { tpos[i] = (uint8_t)reg[i]; used[reg[i]] = true; }
+  int k = 3;
+  int group_mask = 0;
+  while (k < n) {
+    if (((k - 3) & 3) == 0) group_mask = 0;
+    int pick = -1;
+    for (int p = 0; p < n; ++p)
+      if (!used[p] && !((group_mask >> (p & 3)) & 1)) { pick = p; break; }
+    if (pick < 0)
+      for (int p = 0; p < n; ++p)
+        if (!used[p]) { pick = p; break; }
+    used[pick] = true;
+    group_mask |= 1 << (pick & 3);
+    tpos[k++] = (uint8_t)pick;
+  }
+  for (; k < 16; ++k) tpos[k] = 0;
+}
+
+uint32_t jr_of(const uint8_t* tpos, int r) {
+  return ((uint32_t)(r & 1) << tpos[0]) | ((uint32_t)((r >> 1) & 1) << tpos[1]) |
+         ((uint32_t)((r >> 2) & 1) << tpos[2]);
+}
+
+void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool sign_at_src,
+               const uint8_t* read_tpos) {
+  std::memset(X, 0, sizeof(QXchg));
+  for (int k = 0; k < 16; ++k) X->acol[k] = (uint16_t)(k < n ? Acols[k] : 0);
+  for (int r = 0; r < 8; ++r) X->src_r[r] = (uint16_t)apply_cols(Acols, n, jr_of(read_tpos, r));
+  X->nterms = (uint8_t)aff.terms.size();
+  for (size_t t = 0; t < aff.terms.size(); ++t) {
+    X->qu[t] = (uint16_t)aff.terms[t].first;
+    X->qv[t] = (uint16_t)aff.terms[t].second;
+  }
+  X->sign_at_src = sign_at_src ? 1 : 0;
+  for (int i = 0; i < 3; ++i) {
+    uint32_t xe = jr_of(read_tpos, 1 << i);
+    if (sign_at_src) xe = apply_cols(Acols, n, xe);
+    uint32_t ue = 0, ve = 0;
+    for (size_t t = 0; t < aff.terms.size(); ++t) {
+      ue |= par(aff.terms[t].first & xe) << t;
+      ve |= par(aff.terms[t].second & xe) << t;
+    }
+    X->ue[i] = ue;
+    X->ve[i] = ve;
+  }
+  uint8_t qs = 0;
+  for (int r = 0; r < 8; ++r) {
+    uint32_t xr = sign_at_src ? X->src_r[r] : jr_of(read_tpos, r);
+    qs |= (uint8_t)(qform(aff.terms, xr) << r);
+  }
+  X->qsign_r = qs;
+  bool ident = aff.terms.empty();
+  for (int k = 0; k < n; ++k) ident = ident && (Acols[k] == (1u << k));
+  X->identity = ident ? 1 : 0;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+}  // namespace
+
+uint32_t gf2_apply(const uint32_t* cols, int n, uint32_t x) { return apply_cols(cols, n, x); }
+
+std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
+  *status = QP_EINVAL;
+  if (!d) return "null circuit descriptor";
+  const int n = d->n_qubits;
+  if (n < 1 || n > kMaxQubitsPlain) { *status = QP_EUNSUPPORTED; return "n_qubits out of range 1..14"; }
+  if (d->n_params < 0) return "n_params < 0";
+  if (d->n_gates < 0 || (d->n_gates > 0 && !d->gates)) return "bad gate array";
+  if (d->n_out < 1 || d->n_out > kMaxOut || !d->out_qubits) { *status = QP_ESHAPE; return "n_out must be 1..8 with out_qubits"; }
+  hp->n = n;
+  hp->K = d->n_params;
+  hp->m = d->n_out;
+  hp->out_qubits.assign(d->out_qubits, d->out_qubits + d->n_out);
+  for (int q : hp->out_qubits)
+    if (q < 0 || q >= n) return "output qubit out of range";
+  hp->gates.assign(d->gates, d->gates + d->n_gates);
+  for (const auto& g : hp->gates) {
+    if (g.kind < QP_RX || g.kind > QP_CRZ) return "unknown gate kind";
+    if (g.q0 < 0 || g.q0 >= n) return "gate qubit out of range";
+    if (g.kind >= QP_CNOT) {
+      if (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0) return "two-qubit gate needs distinct qubits in range";
+    }
+    if (g.kind <= QP_RZ || g.kind == QP_CRZ) {
+      if (g.param < 0 || g.param >= d->n_params) return "parameter index out of range";
+    }
+  }
+  // encoding
+  const qp_encoding& e = d->enc;
+  hp->enc_kind = e.kind;
+  hp->enc_gate = e.gate;
+  hp->enc_scale = e.scale;
+  if (e.kind < QP_ENC_CYCLE || e.kind > QP_ENC_RFF) return "unknown encoding kind";
+  if (e.gate != QP_ENC_RY && e.gate != QP_ENC_RX) return "unknown encoding gate";
+  if (e.scale < QP_SCALE_NONE || e.scale > QP_SCALE_ACOS) return "unknown scaling";
+  for (int q = 0; q < 16; ++q) hp->coord[q] = q % 3;
+  if (e.kind == QP_ENC_CYCLE && e.coord_of_qubit) {
+    for (int q = 0; q < n; ++q) {
+      if (e.coord_of_qubit[q] < 0 || e.coord_of_qubit[q] > 2) return "coord_of_qubit must be 0..2";
+      hp->coord[q] = e.coord_of_qubit[q];
+    }
+  }
+  if (e.kind == QP_ENC_RFF) {
+    if (e.n_features < 1 || e.n_features > 4096 || !e.rff_B || !e.rff_W) return "RFF needs 1..4096 features and B, W";
+    hp->n_feat = e.n_features;
+    hp->rffB.assign(e.rff_B, e.rff_B + 3 * e.n_features);
+    hp->rffW.assign(e.rff_W, e.rff_W + (size_t)n * 2 * e.n_features);
+  }
+  *status = QP_OK;
+
+  // ---------------- fused plan ----------------
+  hp->fused_ok = true;
+  if (n < 3 || n > kMaxQubits) { hp->fused_ok = false; hp->fused_reason = "fused kernels support 3..12 qubits"; }
+  for (const auto& g : hp->gates)
+    if (g.kind == QP_CRZ) { hp->fused_ok = false; hp->fused_reason = "CRZ is supported by the plain path only"; }
+
+  struct Stage {
+    bool rot;
+    std::map<int, int> fused_of_qubit;   // qubit -> index into hp->fused
+    std::vector<int> order;              // fused ids in creation order
+    Affine aff;
+  };
+  std::vector<Stage> stages;
+  hp->fused.clear();
+  for (const auto& g : hp->gates) {
+    if (g.kind <= QP_RZ) {
+      bool need_new = stages.empty() || !stages.back().rot;
+      if (!need_new) {
+        auto it = stages.back().fused_of_qubit.find(g.q0);
+        if (it != stages.back().fused_of_qubit.end() && hp->fused[it->second].ncomp >= 3) need_new = true;
+      }
+      if (need_new) { stages.push_back(Stage{}); stages.back().rot = true; }
+      Stage& s = stages.back();
+      auto it = s.fused_of_qubit.find(g.q0);
+      int fid;
+      if (it == s.fused_of_qubit.end()) {
+        QFused f{};
+        f.qubit = g.q0;
+        f.ncomp = 0;
+        fid = (int)hp->fused.size();
+        hp->fused.push_back(f);
+        s.fused_of_qubit[g.q0] = fid;
+        s.order.push_back(fid);
+      } else {
+        fid = it->second;
+      }
+      QFused& f = hp->fused[fid];
+      f.kind[f.ncomp] = g.kind;
+      f.param[f.ncomp] = g.param;
+      f.ncomp++;
+    } else if (g.kind == QP_CNOT || g.kind == QP_CZ) {
+      if (stages.empty() || stages.back().rot) {
+        stages.push_back(Stage{});
+        stages.back().rot = false;
+        stages.back().aff.init(n);
+      }
+      Affine& a = stages.back().aff;
+      const int b0 = n - 1 - g.q0, b1 = n - 1 - g.q1;
+      if (g.kind == QP_CNOT) a.cnot(b0, b1);
+      else a.cz(b0, b1);
+      if ((int)a.terms.size() > kMaxTerms) { hp->fused_ok = false; hp->fused_reason = "too many CZ terms in one entangler stage"; }
+    }
+  }
+  // parameter -> (fused, component) lists
+  hp->csr_ptr.assign(hp->K + 1, 0);
+  for (const auto& f : hp->fused)
+    for (int c = 0; c < f.ncomp; ++c) hp->csr_ptr[f.param[c] + 1]++;
+  for (int k = 0; k < hp->K; ++k) hp->csr_ptr[k + 1] += hp->csr_ptr[k];
+  hp->csr_idx.assign(hp->csr_ptr[hp->K], 0);
+  {
+    std::vector<int> fill(hp->csr_ptr.begin(), hp->csr_ptr.end() - 1);
+    for (size_t fi = 0; fi < hp->fused.size(); ++fi)
+      for (int c = 0; c < hp->fused[fi].ncomp; ++c)
+        hp->csr_idx[fill[hp->fused[fi].param[c]]++] = (int)fi * 4 + c;
+  }
+  if (!hp->fused_ok) return "";
+
+  // rounds
+  hp->rounds.clear();
+  std::vector<Affine> round_ent;    // entangler applied in the exchange before round k
+  std::vector<bool> round_has_ent;
+  Affine pending;
+  pending.init(n);
+  bool have_pending = false;
+  auto push_round = [&](const int* gate_ids, const int* reg) {
+    QRound R{};
+    for (int i = 0; i < 3; ++i) R.gate[i] = (int16_t)gate_ids[i];
+    make_tpos(n, reg, R.tpos);
+    hp->rounds.push_back(R);
+    round_ent.push_back(pending);
+    round_has_ent.push_back(have_pending);
+    pending.init(n);
+    have_pending = false;
+  };
+  for (auto& s : stages) {
+    if (!s.rot) {
+      // compose: pending then s.aff  ->  psi(j) = sP(j') ... apply s after pending
+      if (!have_pending) { pending = s.aff; have_pending = true; continue; }
+      // composition of two affine stages: first P (A1, Q1) then S (A2, Q2):
+      // psi2(j) = (-1)^Q2(j) psi1(A2 j) = (-1)^{Q2(j)+Q1(A2 j)} psi0(A1 A2 j)
+      Affine c;
+      c.init(n);
+      for (int k = 0; k < n; ++k) c.acol[k] = apply_cols(pending.acol, n, s.aff.acol[k]);
+      c.terms = s.aff.terms;
+      for (auto& t : pending.terms) {   // Q1(A2 j): mask u -> A2^T u
+        uint32_t u2 = 0, v2 = 0;
+        for (int k = 0; k < n; ++k) {
+          u2 |= par(t.first & s.aff.acol[k]) << k;
+          v2 |= par(t.second & s.aff.acol[k]) << k;
+        }
+        c.terms.emplace_back(u2, v2);
+      }
+      pending = c;
+      if ((int)pending.terms.size() > kMaxTerms) { hp->fused_ok = false; hp->fused_reason = "too many CZ terms"; return ""; }
+      continue;
+    }
+    if (have_pending && hp->rounds.empty()) {   // leading entangler: empty round first
+      int none[3] = {-1, -1, -1};
+      int reg[3] = {0, 1, 2};
+      Affine keep = pending;
+      bool hk = have_pending;
+      pending.init(n);
+      have_pending = false;
+      push_round(none, reg);
+      pending = keep;
+      have_pending = hk;
+    }
+    // fused gates of the stage sorted by qubit, in chunks of three
+    std::vector<int> ids;
+    for (auto& kv : s.fused_of_qubit) ids.push_back(kv.second);
+    std::sort(ids.begin(), ids.end(), [&](int a, int b) { return hp->fused[a].qubit < hp->fused[b].qubit; });
+    for (size_t c0 = 0; c0 < ids.size(); c0 += 3) {
+      int gid[3] = {-1, -1, -1}, reg[3] = {-1, -1, -1};
+      bool used[16] = {false};
+      int cnt = 0;
+      for (size_t i = c0; i < ids.size() && i < c0 + 3; ++i) {
+        gid[cnt] = ids[i];
+        reg[cnt] = n - 1 - hp->fused[ids[i]].qubit;
+        used[reg[cnt]] = true;
+        cnt++;
+      }
+      for (int i = cnt; i < 3; ++i) {   // pad with unused positions near the used ones
+        int best = -1;
+        for (int p = 0; p < n && best < 0; ++p)
+          if (!used[p]) best = p;
+        reg[i] = best;
+        used[best] = true;
+      }
+      push_round(gid, reg);
+    }
+  }
+  if (hp->rounds.empty()) {   // no rotations at all: one empty round
+    int none[3] = {-1, -1, -1};
+    int reg[3] = {0, 1, 2};
+    Affine keep = pending;
+    bool hk = have_pending;
+    pending.init(n);
+    have_pending = false;
+    push_round(none, reg);
+    pending = keep;
+    have_pending = hk;
+  }
+  // trailing entangler -> readout masks: z_i(pi j), pi = A^{-1}
+  {
+    uint32_t pcols[16];
+    if (have_pending) {
+      if (!gf2_inverse(pending.acol, n, pcols)) { *status = QP_EINVAL; return "singular entangler map"; }
+    } else {
+      for (int k = 0; k < 16; ++k) pcols[k] = k < n ? (1u << k) : 0;
+    }
+    for (int i = 0; i < hp->m; ++i) {
+      const int b = n - 1 - hp->out_qubits[i];
+      uint32_t mask = 0;
+      for (int k = 0; k < n; ++k)
+        if ((pcols[k] >> b) & 1u) mask |= (1u << k);
+      hp->zmask[i] = mask;
+    }
+  }
+  // exchanges
+  const int R = (int)hp->rounds.size();
+  hp->xf.assign(R, QXchg{});
+  hp->xb.assign(R, QXchg{});
+  hp->n_exchanges = 0;
+  for (int k = 1; k < R; ++k) {
+    const Affine& a = round_ent[k];
+    fill_xchg(&hp->xf[k], n, a.acol, a, false, hp->rounds[k].tpos);
+    uint32_t inv[16];
+    if (!gf2_inverse(a.acol, n, inv)) { *status = QP_EINVAL; return "singular entangler map"; }
+    fill_xchg(&hp->xb[k], n, inv, a, true, hp->rounds[k - 1].tpos);
+    hp->n_exchanges++;
+  }
+
+  // device image
+  QPlanDev h{};
+  h.n = n;
+  h.n_params = hp->K;
+  h.n_out = hp->m;
+  h.n_fused = (int)hp->fused.size();
+  h.n_rounds = R;
+  h.enc_kind = hp->enc_kind;
+  h.enc_gate = hp->enc_gate;
+  h.enc_scale = hp->enc_scale;
+  h.n_feat = hp->n_feat;
+  for (int q = 0; q < 16; ++q) h.coord_of_qubit[q] = hp->coord[q];
+  for (int i = 0; i < kMaxOut; ++i) h.zmask[i] = hp->zmask[i];
+  size_t off = align16(sizeof(QPlanDev));
+  h.off_rounds = (int)off; off = align16(off + sizeof(QRound) * R);
+  h.off_xf = (int)off; off = align16(off + sizeof(QXchg) * R);
+  h.off_xb = (int)off; off = align16(off + sizeof(QXchg) * R);
+  h.off_fused = (int)off; off = align16(off + sizeof(QFused) * hp->fused.size());
+  h.off_csr_ptr = (int)off; off = align16(off + sizeof(int32_t) * hp->csr_ptr.size());
+  h.off_csr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->csr_idx.size()));
+  h.off_rff_B = (int)off; off = align16(off + sizeof(float) * hp->rffB.size());
+  h.off_rff_W = (int)off; off = align16(off + sizeof(float) * hp->rffW.size());
+  h.bytes = (int)off;
+  hp->blob.assign(off, 0);
+  std::memcpy(hp->blob.data(), &h, sizeof(h));
+  std::memcpy(hp->blob.data() + h.off_rounds, hp->rounds.data(), sizeof(QRound) * R);
+  std::memcpy(hp->blob.data() + h.off_xf, hp->xf.data(), sizeof(QXchg) * R);
+  std::memcpy(hp->blob.data() + h.off_xb, hp->xb.data(), sizeof(QXchg) * R);
+  if (!hp->fused.empty())
+    std::memcpy(hp->blob.data() + h.off_fused, hp->fused.data(), sizeof(QFused) * hp->fused.size());
+  std::memcpy(hp->blob.data() + h.off_csr_ptr, hp->csr_ptr.data(), sizeof(int32_t) * hp->csr_ptr.size());
+  if (!hp->csr_idx.empty())
+    std::memcpy(hp->blob.data() + h.off_csr_idx, hp->csr_idx.data(), sizeof(int32_t) * hp->csr_idx.size());
+  if (!hp->rffB.empty()) std::memcpy(hp->blob.data() + h.off_rff_B, hp->rffB.data(), sizeof(float) * hp->rffB.size());
+  if (!hp->rffW.empty()) std::memcpy(hp->blob.data() + h.off_rff_W, hp->rffW.data(), sizeof(float) * hp->rffW.size());
+  return "";
+}
+
+}  // namespace qp

@@ -1,0 +1,71 @@
+// Internal types shared by the planner (host C++) and the gfx950 kernels.
+//
+// Index conventions: a basis index j of an n-qubit state has qubit q in bit (n-1-q), so
+// qubit 0 is the most significant bit.  "Logical" index = the index of the state the circuit
+// defines.  In the fused kernels a thread owns 8 amplitudes of each statevector: its three
+// "register" bits r0,r1,r2 plus n-3 "thread" bits u.  A round's mapping tpos[k] gives the
+// logical index-bit position of physical bit k (k = 0..2 register bits, k >= 3 thread bit k-3).
+#pragma once
+#include <cstdint>
+
+namespace qp {
+
+constexpr int kMaxQubits = 12;     // fused register/LDS kernels
+constexpr int kMaxQubitsPlain = 14;
+constexpr int kMaxOut = 8;
+constexpr int kMaxTerms = 32;      // sign terms of one entangler stage
+constexpr int kRegBits = 3;        // 8 amplitudes per thread per statevector
+
+struct alignas(16) QRound {
+  int16_t gate[3];    // fused-gate id applied on register bit b (-1: none)
+  int16_t pad0;
+  uint8_t tpos[16];   // logical index-bit position of physical bit k
+};
+
+// One direction of the register exchange that precedes a round.  Reader thread (u, r) in the
+// read mapping holds logical index jn = base(u) ^ jr(r); it takes the amplitude stored at
+// src = A jn (A over GF(2), given by its columns), times (-1)^Q(x), where x = jn (sign in the
+// destination coordinates) or x = src (sign in the source coordinates) and
+// Q(x) = XOR_t parity(qu[t] & x) * parity(qv[t] & x).
+struct alignas(16) QXchg {
+  uint16_t acol[16];
+  uint16_t src_r[8];  // A jr(r): uniform part of the source index
+  uint16_t qu[kMaxTerms];
+  uint16_t qv[kMaxTerms];
+  uint32_t ue[3];     // bit t: parity(qu[t] & x_e(i)) for register basis i (uniform)
+  uint32_t ve[3];
+  uint8_t nterms;
+  uint8_t sign_at_src;
+  uint8_t qsign_r;    // bit r: Q(x_r) for the uniform part x_r
+  uint8_t identity;   // A = I and no sign terms
+  uint32_t pad1;
+};
+
+// Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).
+struct alignas(16) QFused {
+  int32_t qubit;
+  int32_t ncomp;
+  int32_t kind[3];
+  int32_t param[3];
+};
+
+enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2 };
+
+// Plan header uploaded to the device (followed by the arrays at the given byte offsets).
+struct alignas(16) QPlanDev {
+  int32_t n, n_params, n_out, n_fused, n_rounds;
+  int32_t enc_kind, enc_gate, enc_scale, n_feat;
+  int32_t coord_of_qubit[16];
+  uint32_t zmask[kMaxOut];          // readout parity mask of output i (trailing entangler folded)
+  int32_t off_rounds;               // QRound[n_rounds]
+  int32_t off_xf;                   // QXchg[n_rounds]  forward exchange before round k (k>=1)
+  int32_t off_xb;                   // QXchg[n_rounds]  inverse exchange after round k (k>=1)
+  int32_t off_fused;                // QFused[n_fused]
+  int32_t off_csr_ptr;              // int32[n_params+1]
+  int32_t off_csr_idx;              // int32[nnz]: fused*4 + component
+  int32_t off_rff_B;                // float[F][3]
+  int32_t off_rff_W;                // float[n][2F]
+  int32_t bytes;
+};
+
+}  // namespace qp
