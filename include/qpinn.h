@@ -73,6 +73,7 @@ enum { QP_LOSS_VACUUM = 0, QP_LOSS_DIEL_SPLIT = 1, QP_LOSS_DIEL_INTUITIVE = 2 };
 #define QP_FLAG_LOSS_SUM    0x2u  /* Maxwell: sum of squared residuals instead of MSE means  */
 #define QP_FLAG_TUNE        0x4u  /* time the candidate launch shapes on first use and cache  */
 #define QP_FLAG_DENSE_MFMA  0x8u  /* force the dense-block MFMA path (where the plan has one) */
+#define QP_FLAG_GATES_FP32  0x10u /* build the 2x2 gate table in FP32 instead of FP64-rounded  */
 
 typedef struct qp_ctx qp_ctx;
 typedef struct qp_circuit qp_circuit;
@@ -131,6 +132,11 @@ void qp_circuit_destroy(qp_circuit* c);
 /* what: 0 n_qubits, 1 n_params, 2 n_out, 3 fused gates, 4 rounds, 5 register-exchange count,
  *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile            */
 int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
+
+/* Host-only introspection: builds the execution plan of `desc` without a device and copies its
+ * device image (header, rounds, exchange descriptors, fused gates, gradient map) into host_buf
+ * (capacity cap bytes); *bytes receives the image size.  QP_EWORKSPACE if cap is too small.  */
+qp_status qp_plan_image(const qp_circuit_desc* desc, void* host_buf, size_t cap, size_t* bytes);
 
 /* Workspace bytes for qp_simulate / qp_vjp / qp_maxwell_fused with P points. */
 size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags);

@@ -144,10 +144,11 @@ def scale_derivative(kind: int, a):
 
 def encoding_angles(circ, points, angles=None, jac=None):
     """theta [P,n] and J = d theta / d(t,x,y) [P,n,3] for every point (float64)."""
-    pts = np.asarray(points, dtype=np.float64)
-    P, n, enc = pts.shape[0], circ.n, circ.enc
-    if enc.kind == ENC_ANGLES:
+    enc = circ.enc
+    if enc.kind == ENC_ANGLES:      # angles given per point; the points themselves are not read
         return np.asarray(angles, np.float64).copy(), np.asarray(jac, np.float64).copy()
+    pts = np.asarray(points, dtype=np.float64)
+    P, n = pts.shape[0], circ.n
     if enc.kind == ENC_CYCLE:
         coords = enc.coords(n)
         theta = np.empty((P, n))

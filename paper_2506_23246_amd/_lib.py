@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libqpinn.so")
 QP_OK, QP_EINVAL, QP_ESHAPE, QP_EUNSUPPORTED, QP_EWORKSPACE, QP_EDEVICE = range(6)
 STATUS_NAMES = {0: "QP_OK", 1: "QP_EINVAL", 2: "QP_ESHAPE", 3: "QP_EUNSUPPORTED", 4: "QP_EWORKSPACE",
                 5: "QP_EDEVICE"}
-QP_FLAG_NO_TANGENTS, QP_FLAG_LOSS_SUM, QP_FLAG_TUNE, QP_FLAG_DENSE_MFMA = 0x1, 0x2, 0x4, 0x8
+QP_FLAG_NO_TANGENTS, QP_FLAG_LOSS_SUM, QP_FLAG_TUNE, QP_FLAG_DENSE_MFMA, QP_FLAG_GATES_FP32 = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 class qp_gate(C.Structure):
@@ -55,6 +55,7 @@ _SIGS = {
     "qp_circuit_compile": (C.c_int, [_P, C.POINTER(qp_circuit_desc), C.POINTER(_P)]),
     "qp_circuit_destroy": (None, [_P]),
     "qp_circuit_info": (C.c_int64, [_P, C.c_int32]),
+    "qp_plan_image": (C.c_int, [C.POINTER(qp_circuit_desc), _P, C.c_size_t, C.POINTER(C.c_size_t)]),
     "qp_workspace_bytes": (C.c_size_t, [_P, C.c_int64, C.c_uint32]),
     "qp_simulate": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_size_t, C.c_uint32]),
     "qp_vjp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_size_t, C.c_uint32]),

@@ -10,6 +10,7 @@
 #include "batch.hpp"
 #include "fused_kernel.hpp"
 #include "grads_dev.hpp"
+#include "rot_dev.hpp"
 
 namespace qp {
 
@@ -25,27 +26,15 @@ __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGa
   const BatchCirc& C = circs[G.circ];
   const QPlanDev* plan = C.a.plan;
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + G.idx;
-  float ur[2][2] = {{1.f, 0.f}, {0.f, 1.f}}, ui[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+  double u[8];
+  set_identity(u);
   for (int c = 0; c < fu->ncomp; ++c) {
-    float s, co;
-    sincosf(0.5f * C.params[fu->param[c]], &s, &co);
-    float rr[2][2], ri[2][2];
-    const int kd = fu->kind[c];
-    if (kd == QP_RX) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = 0; ri[0][1] = -s; rr[1][0] = 0; ri[1][0] = -s; rr[1][1] = co; ri[1][1] = 0; }
-    else if (kd == QP_RY) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = -s; ri[0][1] = 0; rr[1][0] = s; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = 0; }
-    else { rr[0][0] = co; ri[0][0] = -s; rr[0][1] = 0; ri[0][1] = 0; rr[1][0] = 0; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = s; }
-    float nr[2][2], ni[2][2];
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        nr[i][j] = rr[i][0] * ur[0][j] - ri[i][0] * ui[0][j] + rr[i][1] * ur[1][j] - ri[i][1] * ui[1][j];
-        ni[i][j] = rr[i][0] * ui[0][j] + ri[i][0] * ur[0][j] + rr[i][1] * ui[1][j] + ri[i][1] * ur[1][j];
-      }
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) { ur[i][j] = nr[i][j]; ui[i][j] = ni[i][j]; }
+    double s, co;
+    sincos(0.5 * (double)C.params[fu->param[c]], &s, &co);
+    left_mul_rot<double>(fu->kind[c], co, s, u);
   }
   float* o = const_cast<float*>(C.a.gtab) + G.idx * 8;
-  o[0] = ur[0][0]; o[1] = ui[0][0]; o[2] = ur[0][1]; o[3] = ui[0][1];
-  o[4] = ur[1][0]; o[5] = ui[1][0]; o[6] = ur[1][1]; o[7] = ui[1][1];
+  for (int e = 0; e < 8; ++e) o[e] = (float)u[e];
 }
 
 // Dielectric point counts per circuit (one workgroup per circuit).

@@ -111,6 +111,19 @@ extern "C" qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* d, q
   return QP_OK;
 }
 
+extern "C" qp_status qp_plan_image(const qp_circuit_desc* d, void* host_buf, size_t cap, size_t* bytes) {
+  if (!d || !bytes) return QP_EINVAL;
+  HostPlan hp;
+  int status = QP_OK;
+  std::string msg = build_plan(d, &hp, &status);
+  if (!msg.empty() || status != QP_OK) return status != QP_OK ? (qp_status)status : QP_EINVAL;
+  if (!hp.fused_ok) return QP_EUNSUPPORTED;
+  *bytes = hp.blob.size();
+  if (!host_buf || cap < hp.blob.size()) return QP_EWORKSPACE;
+  std::memcpy(host_buf, hp.blob.data(), hp.blob.size());
+  return QP_OK;
+}
+
 extern "C" void qp_circuit_destroy(qp_circuit* c) {
   if (!c) return;
   if (c->dplan_raw) hipFree(c->dplan_raw);
@@ -221,7 +234,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   char* w = static_cast<char*>(ws);
   float* gtab = reinterpret_cast<float*>(w + L.gtab);
   int* counts = reinterpret_cast<int*>(w + L.counts);
-  hipError_t e = launch_gate_table(c->dplan, F, params, gtab, st);
+  hipError_t e = launch_gate_table(c->dplan, F, params, gtab, (flags & QP_FLAG_GATES_FP32) ? 1 : 0, st);
   if (e != hipSuccess) return hipcheck(ctx, e, "gate table");
   const float* ang = angles;
   const float* jc = jac;

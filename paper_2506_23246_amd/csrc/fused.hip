@@ -30,6 +30,7 @@
 #include "qp_internal.hpp"
 #include "fused.hpp"
 #include "grads_dev.hpp"
+#include "rot_dev.hpp"
 
 namespace qp {
 
@@ -46,37 +47,38 @@ hipError_t launch_fused_11(int mode, const FusedArgs& a, int grid, int exs, size
 hipError_t launch_fused_12(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------------
-// Gate table: U = R_{c-1} ... R_0 for every fused gate, R_P(theta) = exp(-i theta P/2), FP32.
+// Gate table: U = R_{c-1} ... R_0 for every fused gate, R_P(theta) = exp(-i theta P/2).  The table
+// is formed once per call from the K parameters (work independent of the point count) in FP64
+// and rounded once to complex64; every per-point operation then runs in FP32.  The FP32-built
+// variant (k_gate_table) is kept for comparison (QP_FLAG_GATES_FP32).
+__global__ void k_gate_table64(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
+                               float* __restrict__ gtab) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= plan->n_fused) return;
+  const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
+  double u[8];
+  set_identity(u);
+  for (int c = 0; c < fu->ncomp; ++c) {
+    double s, co;
+    sincos(0.5 * (double)params[fu->param[c]], &s, &co);
+    left_mul_rot<double>(fu->kind[c], co, s, u);
+  }
+  for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = (float)u[e];
+}
+
 __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
                              float* __restrict__ gtab) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= plan->n_fused) return;
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
-  float ur[2][2] = {{1.f, 0.f}, {0.f, 1.f}}, ui[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+  float u[8];
+  set_identity(u);
   for (int c = 0; c < fu->ncomp; ++c) {
     float s, co;
     sincosf(0.5f * params[fu->param[c]], &s, &co);
-    float rr[2][2], ri[2][2];
-    const int kd = fu->kind[c];
-    if (kd == QP_RX) {        // [[c, -is], [-is, c]]
-      rr[0][0] = co; ri[0][0] = 0; rr[0][1] = 0; ri[0][1] = -s; rr[1][0] = 0; ri[1][0] = -s; rr[1][1] = co; ri[1][1] = 0;
-    } else if (kd == QP_RY) { // [[c, -s], [s, c]]
-      rr[0][0] = co; ri[0][0] = 0; rr[0][1] = -s; ri[0][1] = 0; rr[1][0] = s; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = 0;
-    } else {                  // diag(e^{-i t/2}, e^{i t/2})
-      rr[0][0] = co; ri[0][0] = -s; rr[0][1] = 0; ri[0][1] = 0; rr[1][0] = 0; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = s;
-    }
-    float nr[2][2], ni[2][2];
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        nr[i][j] = rr[i][0] * ur[0][j] - ri[i][0] * ui[0][j] + rr[i][1] * ur[1][j] - ri[i][1] * ui[1][j];
-        ni[i][j] = rr[i][0] * ui[0][j] + ri[i][0] * ur[0][j] + rr[i][1] * ui[1][j] + ri[i][1] * ur[1][j];
-      }
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) { ur[i][j] = nr[i][j]; ui[i][j] = ni[i][j]; }
+    left_mul_rot<float>(fu->kind[c], co, s, u);
   }
-  float* o = gtab + f * 8;
-  o[0] = ur[0][0]; o[1] = ui[0][0]; o[2] = ur[0][1]; o[3] = ui[0][1];
-  o[4] = ur[1][0]; o[5] = ui[1][0]; o[6] = ur[1][1]; o[7] = ui[1][1];
+  for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
 }
 
 // Random-Fourier-feature angles: phi = [cos(Bp); sin(Bp)], theta = W phi, J = W dphi/dp.
@@ -179,9 +181,10 @@ hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, 
   }
 }
 
-hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, hipStream_t st) {
+hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, int fp32, hipStream_t st) {
   if (n_fused == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gate_table, dim3((n_fused + 127) / 128), dim3(128), 0, st, plan, params, gtab);
+  if (fp32) hipLaunchKernelGGL(k_gate_table, dim3((n_fused + 127) / 128), dim3(128), 0, st, plan, params, gtab);
+  else hipLaunchKernelGGL(k_gate_table64, dim3((n_fused + 127) / 128), dim3(128), 0, st, plan, params, gtab);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include "../../include/qpinn.h"
 #include "qp_internal.hpp"
+#include "rot_dev.hpp"
 
 namespace qp {
 
@@ -19,35 +20,17 @@ __device__ inline double param_grad_one(const QPlanDev* __restrict__ plan, const
   for (int e = ptr[k]; e < ptr[k + 1]; ++e) {
     const int fi = idx[e] >> 2, ci = idx[e] & 3;
     const QFused& fu = fused[fi];
-    double ur[2][2] = {{1, 0}, {0, 1}}, ui[2][2] = {{0, 0}, {0, 0}};
+    double u[8];
+    set_identity(u);
     for (int c = 0; c < fu.ncomp; ++c) {
       double s, co;
       sincos(0.5 * (double)params[fu.param[c]], &s, &co);
-      double rr[2][2], ri[2][2];
-      const int kd = fu.kind[c];
-      if (kd == QP_RX) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = 0; ri[0][1] = -s; rr[1][0] = 0; ri[1][0] = -s; rr[1][1] = co; ri[1][1] = 0; }
-      else if (kd == QP_RY) { rr[0][0] = co; ri[0][0] = 0; rr[0][1] = -s; ri[0][1] = 0; rr[1][0] = s; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = 0; }
-      else { rr[0][0] = co; ri[0][0] = -s; rr[0][1] = 0; ri[0][1] = 0; rr[1][0] = 0; ri[1][0] = 0; rr[1][1] = co; ri[1][1] = s; }
-      if (c == ci) {   // R -> -(i/2) P R
-        double pr[2][2], pi[2][2];
-        if (kd == QP_RX) { for (int j = 0; j < 2; ++j) { pr[0][j] = rr[1][j]; pi[0][j] = ri[1][j]; pr[1][j] = rr[0][j]; pi[1][j] = ri[0][j]; } }
-        else if (kd == QP_RY) { for (int j = 0; j < 2; ++j) { pr[0][j] = ri[1][j]; pi[0][j] = -rr[1][j]; pr[1][j] = -ri[0][j]; pi[1][j] = rr[0][j]; } }
-        else { for (int j = 0; j < 2; ++j) { pr[0][j] = rr[0][j]; pi[0][j] = ri[0][j]; pr[1][j] = -rr[1][j]; pi[1][j] = -ri[1][j]; } }
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) { rr[i][j] = 0.5 * pi[i][j]; ri[i][j] = -0.5 * pr[i][j]; }
-      }
-      double nr[2][2], ni[2][2];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
-          nr[i][j] = rr[i][0] * ur[0][j] - ri[i][0] * ui[0][j] + rr[i][1] * ur[1][j] - ri[i][1] * ui[1][j];
-          ni[i][j] = rr[i][0] * ui[0][j] + ri[i][0] * ur[0][j] + rr[i][1] * ui[1][j] + ri[i][1] * ur[1][j];
-        }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) { ur[i][j] = nr[i][j]; ui[i][j] = ni[i][j]; }
+      left_mul_rot<double>(fu.kind[c], co, s, u);
+      if (c == ci) left_mul_mhalf_i_pauli<double>(fu.kind[c], u);
     }
     const double* M = m64 + fi * 8;
     double re = 0.0;
-    for (int ab = 0; ab < 4; ++ab) re += ur[ab >> 1][ab & 1] * M[2 * ab] - ui[ab >> 1][ab & 1] * M[2 * ab + 1];
+    for (int ab = 0; ab < 4; ++ab) re += u[2 * ab] * M[2 * ab] - u[2 * ab + 1] * M[2 * ab + 1];
     gsum += 2.0 * re;
   }
   return gsum;

@@ -1,0 +1,232 @@
+"""CPU emulation of the fused kernel's register/LDS algorithm, driven by the planner's own
+device image (qp_plan_image).  complex128, one point at a time, every thread of the point's
+thread group emulated explicitly: registers [thread][8], exchanges through a logical-index
+buffer with the descriptor's index map and signs, readout with the plan's parity masks, and
+the adjoint sweep with uncompute and per-gate M accumulation.
+
+This checks the planner (fusion, GF(2) entangler maps, sign forms, round mappings, readout
+folding, gradient map) and the algorithm independently of the GPU; the oracle is the
+reference it is compared with.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused", "<i4"), ("n_rounds", "<i4"),
+                ("enc_kind", "<i4"), ("enc_gate", "<i4"), ("enc_scale", "<i4"), ("n_feat", "<i4"),
+                ("coord", "<i4", 16), ("zmask", "<u4", 8), ("off_rounds", "<i4"), ("off_xf", "<i4"),
+                ("off_xb", "<i4"), ("off_fused", "<i4"), ("off_csr_ptr", "<i4"), ("off_csr_idx", "<i4"),
+                ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4")])
+ROUND = np.dtype([("gate", "<i2", 3), ("pad0", "<i2"), ("tpos", "u1", 16), ("_pad", "u1", 8)])
+XCHG = np.dtype([("acol", "<u2", 16), ("src_r", "<u2", 8), ("qu", "<u2", 32), ("qv", "<u2", 32), ("ue", "<u4", 3),
+                 ("ve", "<u4", 3), ("nterms", "u1"), ("sign_at_src", "u1"), ("qsign_r", "u1"), ("identity", "u1"),
+                 ("pad1", "<u4")])
+FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3)])
+assert ROUND.itemsize == 32 and XCHG.itemsize == 208 and FUSED.itemsize == 32
+
+
+def plan_image(circ):
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import make_desc
+    d, keep = make_desc(circ)
+    nb = C.c_size_t(0)
+    st = L.qp_plan_image(C.byref(d), None, 0, C.byref(nb))
+    buf = (C.c_ubyte * nb.value)()
+    st = L.qp_plan_image(C.byref(d), buf, nb.value, C.byref(nb))
+    assert st == 0, st
+    raw = bytes(buf)
+    h = np.frombuffer(raw, HDR, 1)[0]
+    R = int(h["n_rounds"])
+    plan = {
+        "h": h,
+        "rounds": np.frombuffer(raw, ROUND, R, int(h["off_rounds"])),
+        "xf": np.frombuffer(raw, XCHG, R, int(h["off_xf"])),
+        "xb": np.frombuffer(raw, XCHG, R, int(h["off_xb"])),
+        "fused": np.frombuffer(raw, FUSED, int(h["n_fused"]), int(h["off_fused"])),
+        "csr_ptr": np.frombuffer(raw, "<i4", int(h["n_params"]) + 1, int(h["off_csr_ptr"])),
+    }
+    nnz = int(plan["csr_ptr"][-1])
+    plan["csr_idx"] = np.frombuffer(raw, "<i4", nnz, int(h["off_csr_idx"])) if nnz else np.zeros(0, np.int32)
+    return plan
+
+
+def _par(x):
+    return bin(int(x)).count("1") & 1
+
+
+def _deposit(u, tpos, n):
+    j = 0
+    for k in range(3, n):
+        j |= ((u >> (k - 3)) & 1) << int(tpos[k])
+    return j
+
+
+def _regoff(r, tpos):
+    return ((r & 1) << int(tpos[0])) | (((r >> 1) & 1) << int(tpos[1])) | (((r >> 2) & 1) << int(tpos[2]))
+
+
+def _rot(kind, th):
+    c, s = math.cos(th / 2), math.sin(th / 2)
+    if kind == 0:
+        return np.array([[c, -1j * s], [-1j * s, c]])
+    if kind == 1:
+        return np.array([[c, -s], [s, c]], dtype=complex)
+    return np.array([[c - 1j * s, 0], [0, c + 1j * s]])
+
+
+def _fused_matrix(f, params):
+    U = np.eye(2, dtype=complex)
+    for c in range(int(f["ncomp"])):
+        U = _rot(int(f["kind"][c]), float(params[int(f["param"][c])])) @ U
+    return U
+
+
+def _exchange(regs, wr, rd, X, n, TP):
+    """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point)."""
+    S = regs.shape[0]
+    buf = np.zeros((S, 1 << n), complex)
+    for u in range(TP):
+        jw = _deposit(u, wr["tpos"], n)
+        for r in range(8):
+            buf[:, jw ^ _regoff(r, wr["tpos"])] = regs[:, u, r]
+    out = np.zeros_like(regs)
+    for u in range(TP):
+        jn = _deposit(u, rd["tpos"], n)
+        if X["identity"]:
+            sb = jn
+            srcr = [_regoff(r, rd["tpos"]) for r in range(8)]
+            sg = [0] * 8
+        else:
+            sb = 0
+            for k in range(n):
+                if (jn >> k) & 1:
+                    sb ^= int(X["acol"][k])
+            srcr = [int(v) for v in X["src_r"]]
+            sg = [0] * 8
+            nt = int(X["nterms"])
+            if nt:
+                xb = sb if X["sign_at_src"] else jn
+                pu = sum(_par(int(X["qu"][t]) & xb) << t for t in range(nt))
+                pv = sum(_par(int(X["qv"][t]) & xb) << t for t in range(nt))
+                q0 = _par(pu & pv)
+                bs = [_par((pu & int(X["ve"][i])) ^ (int(X["ue"][i]) & pv)) for i in range(3)]
+                for r in range(8):
+                    s = q0 ^ ((int(X["qsign_r"]) >> r) & 1)
+                    for i in range(3):
+                        if (r >> i) & 1:
+                            s ^= bs[i]
+                    sg[r] = s
+        for r in range(8):
+            v = buf[:, sb ^ srcr[r]]
+            out[:, u, r] = -v if sg[r] else v
+    return out
+
+
+def _apply(regs, svs, bit, U):
+    for r in range(8):
+        if r & (1 << bit):
+            continue
+        r1 = r | (1 << bit)
+        x, y = regs[svs, :, r].copy(), regs[svs, :, r1].copy()
+        regs[svs, :, r] = U[0, 0] * x + U[0, 1] * y
+        regs[svs, :, r1] = U[1, 0] * x + U[1, 1] * y
+
+
+def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
+    """One point: returns f [m], g [m,3] and (if seeds given) M [F,2,2] contributions."""
+    h = plan["h"]
+    n, m, R = int(h["n"]), int(h["n_out"]), int(h["n_rounds"])
+    TP = 1 << (n - 3)
+    rounds, xf, xb, fused = plan["rounds"], plan["xf"], plan["xb"], plan["fused"]
+    Us = [_fused_matrix(f, params) for f in fused]
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    e0, e1 = c.astype(complex), (-1j * s if gate_rx else s.astype(complex))
+    d0, d1 = -0.5 * s + 0j, (-0.5j * c if gate_rx else 0.5 * c + 0j)
+    regs = np.zeros((8, TP, 8), complex)
+    t0 = rounds[0]["tpos"]
+    for u in range(TP):
+        for r in range(8):
+            j = _deposit(u, t0, n) | _regoff(r, t0)
+            amp = 1 + 0j
+            der = np.zeros(3, complex)
+            for q in range(n):
+                b = (j >> (n - 1 - q)) & 1
+                e = e1[q] if b else e0[q]
+                d = d1[q] if b else d0[q]
+                der = der * e + amp * J[q] * d
+                amp = amp * e
+            regs[0, u, r] = amp
+            regs[1:4, u, r] = der
+    for k in range(R):
+        if k > 0:
+            regs[:4] = _exchange(regs[:4], rounds[k - 1], rounds[k], xf[k], n, TP)
+        for b in range(3):
+            g = int(rounds[k]["gate"][b])
+            if g >= 0:
+                _apply(regs, slice(0, 4), b, Us[g])
+    tl = rounds[R - 1]["tpos"]
+    f = np.zeros(m)
+    gg = np.zeros((m, 3))
+    z = np.zeros((m, TP, 8))
+    for u in range(TP):
+        for r in range(8):
+            j = _deposit(u, tl, n) ^ _regoff(r, tl)
+            for i in range(m):
+                z[i, u, r] = -1.0 if _par(int(h["zmask"][i]) & j) else 1.0
+    psi = regs[0]
+    for i in range(m):
+        f[i] = np.sum(z[i] * np.abs(psi) ** 2)
+        for cc in range(3):
+            gg[i, cc] = 2 * np.sum(z[i] * np.real(np.conj(psi) * regs[1 + cc]))
+    if seeds_g is None:
+        return f, gg, None
+    Df = sum(seeds_f[i] * z[i] for i in range(m)) if seeds_f is not None else 0.0
+    D = [sum(seeds_g[i, cc] * z[i] for i in range(m)) for cc in range(3)]
+    regs[4] = Df * regs[0] + D[0] * regs[1] + D[1] * regs[2] + D[2] * regs[3]
+    for cc in range(3):
+        regs[5 + cc] = D[cc] * regs[0]
+    M = np.zeros((len(fused), 2, 2), complex)
+    for k in range(R - 1, -1, -1):
+        for b in (2, 1, 0):
+            g = int(rounds[k]["gate"][b])
+            if g < 0:
+                continue
+            Ud = Us[g].conj().T
+            _apply(regs, slice(0, 4), b, Ud)
+            for r in range(8):
+                if r & (1 << b):
+                    continue
+                r1 = r | (1 << b)
+                for sv in range(4):
+                    x0, x1 = regs[4 + sv, :, r], regs[4 + sv, :, r1]
+                    y0, y1 = regs[sv, :, r], regs[sv, :, r1]
+                    M[g, 0, 0] += np.sum(np.conj(x0) * y0)
+                    M[g, 0, 1] += np.sum(np.conj(x0) * y1)
+                    M[g, 1, 0] += np.sum(np.conj(x1) * y0)
+                    M[g, 1, 1] += np.sum(np.conj(x1) * y1)
+            _apply(regs, slice(4, 8), b, Ud)
+        if k > 0:
+            regs = _exchange(regs, rounds[k], rounds[k - 1], xb[k], n, TP)
+    return f, gg, M
+
+
+def grads_from_m(plan, params, M):
+    """d L / d theta_k = sum over components driven by theta_k of 2 Re sum_ab dU_ab M_ab."""
+    K = int(plan["h"]["n_params"])
+    out = np.zeros(K)
+    P = {0: np.array([[0, 1], [1, 0]]), 1: np.array([[0, -1j], [1j, 0]]), 2: np.diag([1, -1])}
+    for k in range(K):
+        for e in range(int(plan["csr_ptr"][k]), int(plan["csr_ptr"][k + 1])):
+            fi, ci = int(plan["csr_idx"][e]) >> 2, int(plan["csr_idx"][e]) & 3
+            f = plan["fused"][fi]
+            U = np.eye(2, dtype=complex)
+            for c in range(int(f["ncomp"])):
+                Rm = _rot(int(f["kind"][c]), float(params[int(f["param"][c])]))
+                if c == ci:
+                    Rm = -0.5j * P[int(f["kind"][c])] @ Rm
+                U = Rm @ U
+            out[k] += 2 * np.real(np.sum(U * M[fi]))
+    return out

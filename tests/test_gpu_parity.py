@@ -35,7 +35,7 @@ def _check_forward(ctx, circ, params, points, angles=None, jac=None, tol=TOL, na
     out, tan = c.simulate(params, points, angles, jac)
     f, g = O.simulate(circ, params, points, angles, jac)
     e_f, e_g = rel(t2n(out), f), rel(t2n(tan), g)
-    report(f"forward {name} n={circ.n} P={len(points)}", f=e_f, g=e_g)
+    report(f"forward {name} n={circ.n} P={len(f)}", f=e_f, g=e_g)
     assert e_f < tol and e_g < tol
     return c
 

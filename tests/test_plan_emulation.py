@@ -1,0 +1,52 @@
+"""Host logic: the planner's device image, executed by a CPU emulation of the fused kernel's
+register/LDS algorithm, reproduces the oracle (outputs, tangents and parameter gradients)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import qpinn_oracle as O
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2506_23246_amd",
+                   "libqpinn.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def _run(circ, params, pts, seeds=True):
+    from tests.plan_emulator import emulate_point, grads_from_m, plan_image
+    plan = plan_image(circ)
+    theta, J = O.encoding_angles(circ, pts)
+    f, g = O.simulate(circ, params, pts)
+    Wg = O.maxwell_seeds(g, pts, W.MaxwellDesc()) if seeds else None
+    M = 0
+    for p in range(len(pts)):
+        fe, ge, Mp = emulate_point(plan, params, theta[p], J[p], circ.enc.gate == W.ENC_RX,
+                                   None, Wg[p] if seeds else None)
+        np.testing.assert_allclose(fe, f[p], atol=1e-12)
+        np.testing.assert_allclose(ge, g[p], atol=1e-11)
+        if seeds:
+            M = M + Mp
+    if seeds:
+        grad = grads_from_m(plan, params, M)
+        exp = O.grad_reverse(circ, params, pts, None, Wg)
+        np.testing.assert_allclose(grad, exp, atol=1e-11)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_emulated_plan_matches_oracle_on_configs(k):
+    w = W.config(k, P=3)
+    if k == 0:
+        w.circuit.out_qubits = [0, 1, 2]
+    _run(w.circuit, np.asarray(w.params, np.float64), np.asarray(w.points, np.float64))
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 7])
+def test_emulated_plan_mixed_entanglers(n):
+    rng = np.random.default_rng(n)
+    rings = [W.ring(n, W.CNOT, 1) + W.ring(n, W.CZ, 2), W.ring(n, W.CZ, 1), W.ring(n, W.CNOT, 2)]
+    circ = W.layered(n, 3, "xyz", lambda l: rings[l], out_qubits=[0, n - 1, n // 2])
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    pts = rng.uniform(-1, 1, (2, 3))
+    _run(circ, params, pts)
