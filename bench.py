@@ -1,0 +1,209 @@
+"""Benchmark of the fused QPINN circuit step on one MI355X.
+
+A step is one fused Maxwell evaluation over the whole point set: gate table, per-point forward
+with three input tangents, readout, residual loss, adjoint sweep with uncompute, and the FP64
+gradient/loss reductions.  Default workload: 12 qubits, 8 layers of RX/RY/RZ + CNOT ring,
+262144 collocation points (the 64^3 grid size of the paper's training set), complex64.
+
+Prints ONE JSON line on stdout.  Extra legs (on by default, short):
+  * cpu_baseline - the CPU oracle timed on a bounded sample of the same points;
+  * plain_gpu    - the plain per-gate + finite-difference path on the same GPU, timed on a
+                   point subset and a parameter subset, extrapolated to the full step;
+  * parity       - outputs and tangents of sampled points of the timed run vs the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed); see the design doc
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_point(n_fused: int, n: int) -> float:
+    """Algorithmic FP32 flops of one point (mul = 1, fma = 2):
+    forward: 4 statevectors x F gates x 2^n amplitudes x 14 (complex 2x2 row: 1 mul + 3 fma per
+    real part); adjoint: 8 statevectors x F x 2^n x 14 (uncompute + pull-back) plus the gate
+    adjoint products, 4 statevector pairs x 4 entries x 4 fma x 2 per amplitude pair = 64 per
+    amplitude.  Encoding, readout, seeds and the LDS exchanges are not counted."""
+    return float(n_fused) * (2 ** n) * (4 * 14 + 8 * 14 + 64)
+
+
+def cpu_baseline(w, budget_s: float = 12.0, max_points: int = 512):
+    from oracle import qpinn_oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    t0 = time.perf_counter()
+    done, chunk = 0, 16
+    while done < max_points and time.perf_counter() - t0 < budget_s:
+        pts = w.points[done:done + chunk]
+        f, g = O.simulate(w.circuit, w.params, pts)
+        Wg = O.maxwell_seeds(g, pts, w.loss)
+        O.grad_reverse(w.circuit, w.params, pts, None, Wg)
+        done += len(pts)
+    dt = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} points of the same workload: complex128 Kronecker-product forward, "
+                      f"3 tangents, Maxwell seeds and stored-state reverse-mode gradient, {dt:.1f} s "
+                      f"single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c5", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import Batch, Circuit, Context
+
+    ctx = Context(0)
+    k = {"c2": 1, "c3": 2, "c4": 3, "c5": 4}[args.workload]
+    dev = torch.device("cuda", 0)
+    flags = L.QP_FLAG_TUNE if args.tune else 0
+
+    if k == 3:
+        ws_list = W.config(3)
+        batch = Batch(ctx, [w.circuit for w in ws_list], [len(w.points) for w in ws_list])
+        arr, bufs = batch.io([w.params for w in ws_list], [w.points for w in ws_list])
+        P_total = sum(len(w.points) for w in ws_list)
+        flops = sum(flops_per_point(w.circuit.n_params // 3, w.circuit.n) * len(w.points) for w in ws_list)
+
+        def step():
+            batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), flags=0)
+        if args.tune:
+            batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), flags=L.QP_FLAG_TUNE)
+        cfg = {"workload": W.CONFIG_NAMES[3], "circuits": len(ws_list), "points_total": P_total,
+               "grid": batch.info(2), "work_items": batch.info(1)}
+        w = None
+    else:
+        w = W.config(k)
+        c = Circuit(ctx, w.circuit)
+        P_total = len(w.points)
+        prm = torch.tensor(w.params, device=dev)
+        pts = torch.tensor(w.points, device=dev)
+        bufs = {"out": torch.empty((P_total, 3), dtype=torch.float32, device=dev),
+                "tan": torch.empty((P_total, 3, 3), dtype=torch.float32, device=dev),
+                "loss": torch.empty(1, dtype=torch.float64, device=dev),
+                "grad": torch.empty(w.circuit.n_params, dtype=torch.float32, device=dev)}
+        F = c.info(3)
+        flops = flops_per_point(F, w.circuit.n) * P_total
+
+        def step():
+            c.maxwell(prm, pts, w.loss, bufs=bufs)
+        if args.tune:
+            c.maxwell(prm, pts, w.loss, bufs=bufs, flags=L.QP_FLAG_TUNE)
+        cfg = {"workload": w.name, "n_qubits": w.circuit.n, "layers": w.circuit.n_params // (3 * w.circuit.n),
+               "points": P_total, "params": w.circuit.n_params, "fused_gates": F, "rounds": c.info(4),
+               "threads_per_wg": c.info(6), "points_per_tile": c.info(7), "lds_exchange_planes": c.info(8),
+               "wg_per_cu": c.info(9), "loss": {0: "vacuum", 1: "dielectric split", 2: "dielectric intuitive"}[w.loss.kind]}
+
+    log(f"bench: workload {cfg['workload']} P={P_total}; warmup {args.warmup}, steps {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / max(args.steps, 1)
+    value = P_total / (ms_per_step / 1e3)
+    log(f"bench: {ms_per_step:.3f} ms/step, {value:.4g} evals/s")
+
+    # dominant kernel duration with HIP events on its own stream
+    ctx.kernel_timing(True)
+    kms = []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        kms.append(ctx.last_kernel_ms())
+    ctx.kernel_timing(False)
+    kms_avg = float(np.mean(kms))
+    achieved = flops / (kms_avg / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "kernel": "k_fused" if k != 3 else "k_batch", "kernel_ms": round(kms_avg, 4),
+                "algorithmic_flops_per_launch": flops}
+    log(f"bench: main kernel {kms_avg:.3f} ms, {achieved:.2f} TFLOP/s algorithmic")
+
+    line = {"metric": "collocation-point circuit evals/s (fwd+3 input tangents+adjoint grad)", "value": round(value, 1),
+            "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic", "config": cfg, "roofline": roofline}
+
+    if w is not None and not args.no_parity:
+        from oracle import qpinn_oracle as O
+        idx = np.linspace(0, P_total - 1, 8).astype(int)
+        f, g = O.simulate(w.circuit, w.params, w.points[idx])
+        out = bufs["out"][idx].cpu().numpy()
+        tan = bufs["tan"][idx].cpu().numpy()
+        rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+        line["parity"] = {"sampled_points": len(idx), "rel_err_out": rel(out, f), "rel_err_tan": rel(tan, g),
+                          "loss": float(bufs["loss"].cpu()[0]), "grad_norm": float(bufs["grad"].norm().cpu())}
+        log(f"bench: parity {line['parity']}")
+
+    if w is not None and not args.no_plain:
+        P_sub = min(P_total, 4096 if w.circuit.n >= 12 else 16384)
+        sub = torch.tensor(w.points[:P_sub], device=dev)
+        c.plain_eval(prm, sub, precision=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.plain_eval(prm, sub, precision=32)
+        torch.cuda.synchronize()
+        t_eval = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        c.plain_maxwell_fd(prm, sub, w.loss, precision=32, k_begin=0, k_end=2)
+        torch.cuda.synchronize()
+        t_fd2 = time.perf_counter() - t0
+        t_param = max(t_fd2 - t_eval, 0.0) / 2.0
+        K = w.circuit.n_params
+        t_full = (P_total / P_sub) * (t_eval + K * t_param)
+        line["plain_gpu"] = {
+            "what": "per-gate kernels on HBM state, FP32, tangents by central FD (7 forwards), parameter gradient "
+                    "by central FD of the loss (2 FD-tangent evaluations per parameter)",
+            "timed": f"{P_sub} points; 2 of {K} parameters; scaled linearly to {P_total} points and {K} parameters",
+            "fwd_fd_tangents_evals_per_s": round(P_sub / t_eval, 1),
+            "full_step_s_extrapolated": round(t_full, 3),
+            "speedup_fused_vs_plain": round(t_full / (ms_per_step / 1e3), 1),
+            "speedup_fused_vs_plain_fwd_tangents_only": round((P_total / P_sub) * t_eval / (ms_per_step / 1e3), 2)}
+        log(f"bench: plain {line['plain_gpu']}")
+
+    if w is not None and not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+        log(f"bench: cpu {line['cpu_baseline']}")
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -121,6 +121,11 @@ void qp_ctx_destroy(qp_ctx* ctx);
 const char* qp_last_error(const qp_ctx* ctx);
 qp_status qp_sync(qp_ctx* ctx);   /* waits for the stream; reports asynchronous device errors */
 int32_t qp_device_cu_count(const qp_ctx* ctx);
+/* Kernel timing: when enabled, the next fused or batch calls record HIP events on the context
+ * stream immediately around their main (per-point) kernel; qp_ctx_last_kernel_ms waits for the
+ * second event and returns the elapsed time of the most recent such kernel in milliseconds.  */
+qp_status qp_ctx_enable_kernel_timing(qp_ctx* ctx, int32_t on);
+qp_status qp_ctx_last_kernel_ms(qp_ctx* ctx, float* ms);
 
 /* ---- circuits --------------------------------------------------------------------------
  * qp_circuit_compile validates the descriptor, fuses consecutive rotations on a qubit into

@@ -52,6 +52,8 @@ _SIGS = {
     "qp_last_error": (C.c_char_p, [_P]),
     "qp_sync": (C.c_int, [_P]),
     "qp_device_cu_count": (C.c_int32, [_P]),
+    "qp_ctx_enable_kernel_timing": (C.c_int, [_P, C.c_int32]),
+    "qp_ctx_last_kernel_ms": (C.c_int, [_P, C.POINTER(C.c_float)]),
     "qp_circuit_compile": (C.c_int, [_P, C.POINTER(qp_circuit_desc), C.POINTER(_P)]),
     "qp_circuit_destroy": (None, [_P]),
     "qp_circuit_info": (C.c_int64, [_P, C.c_int32]),

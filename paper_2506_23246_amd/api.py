@@ -48,6 +48,14 @@ class Context:
     def sync(self):
         L.check(L.qp_sync(self.h), self.h)
 
+    def kernel_timing(self, on: bool = True):
+        L.check(L.qp_ctx_enable_kernel_timing(self.h, 1 if on else 0), self.h)
+
+    def last_kernel_ms(self) -> float:
+        ms = C.c_float(0.0)
+        L.check(L.qp_ctx_last_kernel_ms(self.h, C.byref(ms)), self.h)
+        return float(ms.value)
+
     @property
     def cu_count(self):
         return L.qp_device_cu_count(self.h)

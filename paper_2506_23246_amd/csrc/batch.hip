@@ -160,13 +160,16 @@ hipError_t batch_prepare(int max_fused) {
 hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* items, int nitems,
                         const BatchGate* gates, int ngates, const BatchCol* cols, int ncols,
                         const BatchGate* pars, int npars, int* counter, float* mpart, float* lpart,
-                        int grid, int max_fused, int count_needed, hipStream_t st) {
+                        int grid, int max_fused, int count_needed, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
   hipLaunchKernelGGL(k_batch_gates, dim3(ngates > 0 ? (ngates + 127) / 128 : 1), dim3(128), 0, st,
                      circs, gates, ngates, counter);
   if (count_needed) hipLaunchKernelGGL(k_batch_counts, dim3(ncirc), dim3(256), 0, st, circs);
+  if (ev0) hipEventRecord(ev0, st);
   if (grid > 0 && nitems > 0)
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), batch_lds_bytes(max_fused), st, circs, items, nitems,
                        counter, mpart, lpart);
+  if (ev1) hipEventRecord(ev1, st);
   hipLaunchKernelGGL(k_batch_reduce, dim3((ncols + 3) / 4), dim3(256), 0, st, circs, cols, ncols, mpart, lpart);
   if (npars > 0) hipLaunchKernelGGL(k_batch_grads, dim3((npars + 127) / 128), dim3(128), 0, st, circs, pars, npars);
   return hipGetLastError();

@@ -33,7 +33,8 @@ struct BatchLayout {
 hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* items, int nitems,
                         const BatchGate* gates, int ngates, const BatchCol* cols, int ncols,
                         const BatchGate* pars, int npars, int* counter, float* mpart, float* lpart,
-                        int grid, int max_fused, int count_needed, hipStream_t st);
+                        int grid, int max_fused, int count_needed, hipStream_t st,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t batch_prepare(int max_fused);
 size_t batch_lds_bytes(int max_fused);
 

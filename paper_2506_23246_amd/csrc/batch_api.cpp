@@ -227,7 +227,8 @@ static hipError_t batch_launch(qp_ctx* ctx, qp_batch* b, const qp_maxwell_desc* 
   return launch_batch(b->dcirc, (int)b->circs.size(), b->ditems, (int)b->items.size(), b->dgates, (int)b->gates.size(),
                       b->dcols, (int)b->cols.size(), b->dpars, (int)b->pars.size(), reinterpret_cast<int*>(w + L.counter),
                       reinterpret_cast<float*>(w + L.mpart), reinterpret_cast<float*>(w + L.lpart), grid, b->max_fused,
-                      ld->kind == QP_LOSS_DIEL_SPLIT ? 1 : 0, ctx->stream);
+                      ld->kind == QP_LOSS_DIEL_SPLIT ? 1 : 0, ctx->stream, ctx->timing ? ctx->ev0 : nullptr,
+                      ctx->timing ? ctx->ev1 : nullptr);
 }
 
 extern "C" qp_status qp_batch_run(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io, const qp_maxwell_desc* ld, void* ws,

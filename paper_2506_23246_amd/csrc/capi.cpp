@@ -62,7 +62,32 @@ extern "C" qp_status qp_ctx_set_stream(qp_ctx* c, void* stream) {
   return QP_OK;
 }
 
-extern "C" void qp_ctx_destroy(qp_ctx* c) { delete c; }
+extern "C" void qp_ctx_destroy(qp_ctx* c) {
+  if (!c) return;
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+extern "C" qp_status qp_ctx_enable_kernel_timing(qp_ctx* c, int32_t on) {
+  if (!c) return QP_EINVAL;
+  hipSetDevice(c->device);
+  if (on && !c->ev0) {
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+      return fail(c, QP_EDEVICE, "qp_ctx_enable_kernel_timing: hipEventCreate failed");
+  }
+  c->timing = on != 0;
+  return QP_OK;
+}
+
+extern "C" qp_status qp_ctx_last_kernel_ms(qp_ctx* c, float* ms) {
+  if (!c || !ms) return QP_EINVAL;
+  if (!c->ev0) return fail(c, QP_EINVAL, "qp_ctx_last_kernel_ms: timing was never enabled");
+  hipSetDevice(c->device);
+  hipError_t e = hipEventSynchronize(c->ev1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, c->ev0, c->ev1);
+  return hipcheck(c, e, "qp_ctx_last_kernel_ms");
+}
 
 extern "C" const char* qp_last_error(const qp_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
@@ -273,7 +298,9 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.mpart = reinterpret_cast<float*>(w + L.mpart);
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
   if (grid > 0) {
+    if (ctx->timing) hipEventRecord(ctx->ev0, st);
     if ((e = launch_fused(n, mode, a, grid, exs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
+    if (ctx->timing) hipEventRecord(ctx->ev1, st);
   }
   if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
   double* m64 = reinterpret_cast<double*>(w + L.m64);

@@ -17,6 +17,8 @@ struct qp_ctx {
   size_t max_lds = 0;
   std::string arch;
   std::string err;
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 struct qp_circuit {
