@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -197,6 +198,36 @@ def main():
             "speedup_fused_vs_plain": round(t_full / (ms_per_step / 1e3), 1),
             "speedup_fused_vs_plain_fwd_tangents_only": round((P_total / P_sub) * t_eval / (ms_per_step / 1e3), 2)}
         log(f"bench: plain {line['plain_gpu']}")
+
+    if w is not None and not args.no_dense and w.circuit.n >= 5:
+        # dense 2^5 blocks on FP32 MFMA (streamed through HBM), same step on a point subset
+        P_d = min(P_total, 16384)
+        sub = torch.tensor(w.points[:P_d], device=dev)
+        bd = {"out": torch.empty((P_d, 3), dtype=torch.float32, device=dev),
+              "tan": torch.empty((P_d, 3, 3), dtype=torch.float32, device=dev),
+              "loss": torch.empty(1, dtype=torch.float64, device=dev),
+              "grad": torch.empty(w.circuit.n_params, dtype=torch.float32, device=dev)}
+        c.maxwell(prm, sub, w.loss, bufs=bd, flags=L.QP_FLAG_DENSE_MFMA)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.maxwell(prm, sub, w.loss, bufs=bd, flags=L.QP_FLAG_DENSE_MFMA)
+        torch.cuda.synchronize()
+        t_d = (time.perf_counter() - t0) / reps
+        G = int(c.info(10))
+        cols = 2 ** (w.circuit.n - 5)
+        mm = 2.0 * 64 * 64 * cols                       # one 64x64 real block on one statevector
+        flops_d = G * (12 * mm + 4 * 4 * 2 * 32 * 32 * cols) * P_d
+        bytes_d = G * (12 * 2 + 8) * (2 ** w.circuit.n) * 8 * P_d
+        line["dense_mfma"] = {
+            "what": "the same fused Maxwell step with every gate run grouped into 32x32 complex blocks on "
+                    "v_mfma_f32_32x32x2f32, statevectors streamed through HBM (amplitude-major)",
+            "points": P_d, "blocks": G, "evals_per_s": round(P_d / t_d, 1),
+            "relative_to_fused": round((P_d / t_d) / value, 4),
+            "algorithmic_mfma_tflops": round(flops_d / t_d / 1e12, 2),
+            "modelled_hbm_gbs": round(bytes_d / t_d / 1e9, 1)}
+        log(f"bench: dense {line['dense_mfma']}")
 
     if w is not None and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)

@@ -135,7 +135,8 @@ qp_status qp_ctx_last_kernel_ms(qp_ctx* ctx, float* ms);
 qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* desc, qp_circuit** out);
 void qp_circuit_destroy(qp_circuit* c);
 /* what: 0 n_qubits, 1 n_params, 2 n_out, 3 fused gates, 4 rounds, 5 register-exchange count,
- *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile            */
+ *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile,
+ *       8 LDS exchange planes, 9 persistent workgroups per CU, 10 dense 2^5 blocks        */
 int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
 
 /* Host-only introspection: builds the execution plan of `desc` without a device and copies its

@@ -128,9 +128,9 @@ class Circuit:
     def info(self, what: int) -> int:
         return int(L.qp_circuit_info(self.h, what))
 
-    def workspace(self, P: int):
-        nb = int(L.qp_workspace_bytes(self.h, int(P), 0))
-        key = ("fused", nb)
+    def workspace(self, P: int, flags: int = 0):
+        nb = int(L.qp_workspace_bytes(self.h, int(P), int(flags) & L.QP_FLAG_DENSE_MFMA))
+        key = ("ws", nb)
         if key not in self._ws:
             self._ws = {key: _aligned_bytes(nb, self.ctx.dev)}
         return self._ws[key]
@@ -139,29 +139,29 @@ class Circuit:
         dev = self.ctx.dev
         return _f32(params, dev), _f32(points, dev), _f32(angles, dev), _f32(jac, dev)
 
-    def simulate(self, params, points=None, angles=None, jac=None, tangents=True, out=None, tan=None):
+    def simulate(self, params, points=None, angles=None, jac=None, tangents=True, out=None, tan=None, flags=0):
         prm, pts, ang, jc = self._inputs(params, points, angles, jac)
         P = int((pts if pts is not None else ang).shape[0])
         dev = self.ctx.dev
         out = out if out is not None else torch.empty((P, self.m), dtype=torch.float32, device=dev)
         if tangents and tan is None:
             tan = torch.empty((P, self.m, 3), dtype=torch.float32, device=dev)
-        _, wp, nb = self.workspace(P)
-        flags = 0 if tangents else L.QP_FLAG_NO_TANGENTS
+        _, wp, nb = self.workspace(P, flags)
+        flags = flags | (0 if tangents else L.QP_FLAG_NO_TANGENTS)
         L.check(L.qp_simulate(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, _ptr(out),
                               _ptr(tan) if tangents else None, wp, nb, flags), self.ctx.h)
         return out, (tan if tangents else None)
 
-    def vjp(self, params, points=None, d_out=None, d_tan=None, angles=None, jac=None, d_params=None):
+    def vjp(self, params, points=None, d_out=None, d_tan=None, angles=None, jac=None, d_params=None, flags=0):
         prm, pts, ang, jc = self._inputs(params, points, angles, jac)
         P = int((pts if pts is not None else ang).shape[0])
         dev = self.ctx.dev
         d_out = _f32(d_out, dev)
         d_tan = _f32(d_tan, dev)
         d_params = d_params if d_params is not None else torch.empty(self.K, dtype=torch.float32, device=dev)
-        _, wp, nb = self.workspace(P)
+        _, wp, nb = self.workspace(P, flags)
         L.check(L.qp_vjp(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, _ptr(d_out), _ptr(d_tan),
-                         _ptr(d_params), wp, nb, 0), self.ctx.h)
+                         _ptr(d_params), wp, nb, flags), self.ctx.h)
         return d_params
 
     def maxwell(self, params, points, loss, angles=None, jac=None, outputs=True, flags=0, bufs=None):
@@ -177,7 +177,7 @@ class Circuit:
                 "loss": torch.empty(1, dtype=torch.float64, device=dev),
                 "grad": torch.empty(self.K, dtype=torch.float32, device=dev),
             }
-        _, wp, nb = self.workspace(P)
+        _, wp, nb = self.workspace(P, flags)
         md = maxwell_desc(loss)
         L.check(L.qp_maxwell_fused(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, C.byref(md),
                                    _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]), _ptr(bufs["grad"]),

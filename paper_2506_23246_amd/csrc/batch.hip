@@ -62,7 +62,7 @@ __device__ __forceinline__ void batch_tiles(const BatchCirc& C, const BatchItem&
     fused_tile<N, kBT, kBEXS, kModeMaxwell>(C.a, t, buf, slots, red, lacc);
 }
 
-__global__ __launch_bounds__(kBT) void k_batch(const BatchCirc* __restrict__ circs, const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ circs, const BatchItem* __restrict__ items,
                                                int nitems, int* __restrict__ counter, float* __restrict__ mpart,
                                                float* __restrict__ lpart) {
   constexpr int WAVES = kBT / 64;

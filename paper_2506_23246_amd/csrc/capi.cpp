@@ -11,6 +11,7 @@
 
 #include "../../include/qpinn.h"
 #include "batch.hpp"
+#include "dense.hpp"
 #include "capi_internal.hpp"
 #include "fused.hpp"
 #include "plain.hpp"
@@ -168,6 +169,7 @@ extern "C" int64_t qp_circuit_info(const qp_circuit* c, int32_t what) {
     case 7: return c->hp.fused_ok ? fused_points_per_tile(c->hp.n) : 0;
     case 8: return c->exs;
     case 9: return c->wg_per_cu;
+    case 10: return c->hp.dense_ok ? (int64_t)c->hp.dgroups.size() : 0;
     default: return -1;
   }
 }
@@ -218,19 +220,33 @@ WsLayout qp::fused_layout(const qp_circuit* c, int64_t P, int grid_cap) {
   return L;
 }
 
+static int dense_nwg(const qp_ctx* ctx, const qp_circuit* c, int Pc) {
+  const long long tiles = (1ll << (c->hp.n - 5)) * ((Pc + 63) / 64);
+  return (int)std::max<long long>(1, std::min<long long>(tiles, (long long)ctx->cu_count * 4));
+}
+
+static DenseLayout dense_ws(const qp_circuit* c, int64_t P, bool grad, int* Pc_out, int* nwg_out) {
+  const int Pc = dense_chunk(c->hp.n, P, grad);
+  const int nwg = dense_nwg(c->ctx, c, Pc);
+  if (Pc_out) *Pc_out = Pc;
+  if (nwg_out) *nwg_out = nwg;
+  return dense_layout(c->hp.n, c->hp.m, (int)c->hp.dgroups.size(), (int)c->hp.docc.size() / 2, P, Pc, nwg, grad);
+}
+
 extern "C" size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags) {
-  (void)flags;
   if (!c || P < 0) return 0;
+  if (flags & QP_FLAG_DENSE_MFMA) return c->hp.dense_ok ? dense_ws(c, P, true, nullptr, nullptr).total : 0;
   const int cap = c->ctx->cu_count * 4;   // covers every launch shape the tuner may pick
   return fused_layout(c, P, cap).total;
 }
 
 static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                               const float* angles, const float* jac, int64_t P, void* ws, size_t ws_bytes,
-                              const char* who) {
+                              const char* who, uint32_t flags) {
   if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
   if (P < 0) return fail(ctx, QP_EINVAL, "%s: P < 0", who);
-  if (!c->hp.fused_ok) return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
+  if (!c->hp.fused_ok && !(flags & QP_FLAG_DENSE_MFMA))
+    return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
   if (c->hp.K > 0 && !params) return fail(ctx, QP_EINVAL, "%s: params is null", who);
   if (P > 0) {
     if (c->hp.enc_kind == QP_ENC_ANGLES) {
@@ -240,9 +256,65 @@ static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* par
     }
   }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or not 256-byte aligned", who);
-  if (ws_bytes < qp_workspace_bytes(c, P, 0)) return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, qp_workspace_bytes(c, P, 0));
+  if (ws_bytes < qp_workspace_bytes(c, P, flags))
+    return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, qp_workspace_bytes(c, P, flags));
   if (P > (int64_t)1 << 40) return fail(ctx, QP_EUNSUPPORTED, "%s: P too large", who);
   return QP_OK;
+}
+
+// Dense-block MFMA sequence (QP_FLAG_DENSE_MFMA) for the three evaluation entry points.
+static qp_status run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
+                           const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
+                           float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
+                           uint32_t flags) {
+  if (!c->hp.dense_ok) return fail(ctx, QP_EUNSUPPORTED, "dense-block path needs 5..12 qubits");
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  DenseCall d{};
+  d.L = dense_ws(c, P, true, &d.Pc, &d.nwg);
+  d.plan = c->dplan;
+  d.n = c->hp.n;
+  d.m = c->hp.m;
+  d.G = (int)c->hp.dgroups.size();
+  d.K = c->hp.K;
+  d.n_docc = (int)c->hp.docc.size() / 2;
+  d.params = params;
+  d.points = points;
+  d.angles = angles;
+  d.jac = jac;
+  d.P = P;
+  d.apply_grid = ctx->cu_count * 8;
+  d.grad = mode != kModeFwd;
+  d.out = out;
+  d.tan = tan;
+  d.loss_out = loss;
+  d.d_params = d_params;
+  d.ws = ws;
+  char* w = static_cast<char*>(ws);
+  hipError_t e = hipSuccess;
+  if (c->hp.enc_kind == QP_ENC_RFF) {
+    d.angles = reinterpret_cast<float*>(w + d.L.angles);
+    d.jac = reinterpret_cast<float*>(w + d.L.jac);
+    if ((e = launch_rff(c->dplan, points, P, const_cast<float*>(d.angles), const_cast<float*>(d.jac), st)) != hipSuccess)
+      return hipcheck(ctx, e, "rff angles");
+  }
+  int* counts = reinterpret_cast<int*>(w + d.L.counts);
+  d.loss.maxwell = mode == kModeMaxwell;
+  d.loss.kind = ld ? ld->kind : QP_LOSS_VACUUM;
+  d.loss.loss_sum = (flags & QP_FLAG_LOSS_SUM) ? 1 : 0;
+  d.loss.eps_r = ld ? ld->eps_r : 1.f;
+  d.loss.x_if = ld ? ld->x_interface : 0.f;
+  d.loss.w_all = d.loss.loss_sum ? 1.f : (P > 0 ? 1.f / (float)P : 0.f);
+  d.loss.counts = counts;
+  d.loss.points = points;
+  d.loss.d_out = d_out;
+  d.loss.d_tan = d_tan;
+  if (mode == kModeMaxwell && ld->kind == QP_LOSS_DIEL_SPLIT)
+    if ((e = launch_count(points, P, ld->x_interface, counts, st)) != hipSuccess) return hipcheck(ctx, e, "count");
+  if (ctx->timing) hipEventRecord(ctx->ev0, st);
+  e = dense_run(d, st);
+  if (ctx->timing) hipEventRecord(ctx->ev1, st);
+  return hipcheck(ctx, e, "dense-block path");
 }
 
 // Shared launch sequence of the three fused entry points.
@@ -315,10 +387,13 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
 extern "C" qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                                  const float* angles, const float* jac, int64_t P, float* out, float* tan, void* ws,
                                  size_t ws_bytes, uint32_t flags) {
-  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_simulate");
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_simulate", flags);
   if (s != QP_OK) return s;
   if (P > 0 && !out) return fail(ctx, QP_EINVAL, "qp_simulate: out is null");
   if (P > 0 && !tan && !(flags & QP_FLAG_NO_TANGENTS)) return fail(ctx, QP_EINVAL, "qp_simulate: tan is null");
+  if (flags & QP_FLAG_DENSE_MFMA)
+    return run_dense(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
+                     (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags);
   return run_fused(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
                    (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags, 0, 0);
 }
@@ -326,9 +401,12 @@ extern "C" qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* 
 extern "C" qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                             const float* angles, const float* jac, int64_t P, const float* d_out, const float* d_tan,
                             float* d_params, void* ws, size_t ws_bytes, uint32_t flags) {
-  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_vjp");
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_vjp", flags);
   if (s != QP_OK) return s;
   if (c->hp.K > 0 && !d_params) return fail(ctx, QP_EINVAL, "qp_vjp: d_params is null");
+  if (flags & QP_FLAG_DENSE_MFMA)
+    return run_dense(ctx, c, kModeVjp, params, points, angles, jac, P, nullptr, nullptr, nullptr, d_out, d_tan, nullptr,
+                     d_params, ws, flags);
   return run_fused(ctx, c, kModeVjp, params, points, angles, jac, P, nullptr, nullptr, nullptr, d_out, d_tan, nullptr,
                    d_params, ws, flags, 0, 0);
 }
@@ -337,13 +415,16 @@ extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const fl
                                       const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld,
                                       float* out, float* tan, double* loss, float* d_params, void* ws,
                                       size_t ws_bytes, uint32_t flags) {
-  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_maxwell_fused");
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_maxwell_fused", flags);
   if (s != QP_OK) return s;
   if (!ld) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss descriptor is null");
   if (ld->kind < QP_LOSS_VACUUM || ld->kind > QP_LOSS_DIEL_INTUITIVE) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: unknown loss kind");
   if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "qp_maxwell_fused: the Maxwell loss needs 3 outputs (E_z, H_x, H_y)");
   if (ld->kind != QP_LOSS_VACUUM && P > 0 && !points) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: dielectric loss needs points");
   if (!loss || (c->hp.K > 0 && !d_params)) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss/d_params null");
+  if (flags & QP_FLAG_DENSE_MFMA)
+    return run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
+                     ws, flags);
   if ((flags & QP_FLAG_TUNE) && P > 0) tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws);
   return run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                    ws, flags, 0, 0);

@@ -390,8 +390,11 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
 #pragma unroll
         for (int i = 0; i < kMaxOut * 4; ++i)
           if (i < 4 * m) acc[i] += __shfl_xor(acc[i], off);
-      if (lane == 0)
-        for (int i = 0; i < 4 * m; ++i) red[wave * 40 + i] = acc[i];
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < kMaxOut * 4; ++i)
+          if (i < 4 * m) red[wave * 40 + i] = acc[i];
+      }
       __syncthreads();
       constexpr int WPP = TP / 64;   // waves per point
       const int w0 = (wave / WPP) * WPP;
@@ -406,7 +409,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       __syncthreads();
     }
     if (valid && u == 0) {
-      for (int i = 0; i < m; ++i) {
+#pragma unroll
+      for (int i = 0; i < kMaxOut; ++i) {
+        if (i >= m) break;
         if (a.out) a.out[pt * m + i] = acc[i * 4];
         if (a.tan) {
           a.tan[(pt * m + i) * 3 + 0] = acc[i * 4 + 1];
@@ -446,7 +451,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
     } else {   // VJP seeds
       if (valid) {
-        for (int i = 0; i < m; ++i) {
+#pragma unroll
+        for (int i = 0; i < kMaxOut; ++i) {
+          if (i >= m) break;
           if (a.d_out) Vv[i] = a.d_out[pt * m + i];
           if (a.d_tan) {
             Wv[i][0] = a.d_tan[(pt * m + i) * 3 + 0];
@@ -504,7 +511,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
 
 // ---- the fused kernel: a persistent grid walks the tiles ------------------------------------
 template <int N, int T, int EXS, int MODE>
-__global__ __launch_bounds__(T) void k_fused(FusedArgs a) {
+__global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   constexpr int WAVES = T / 64;
   constexpr int PLANE = T * 8;
   extern __shared__ float4 smem4[];

@@ -158,6 +158,89 @@ size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 uint32_t gf2_apply(const uint32_t* cols, int n, uint32_t x) { return apply_cols(cols, n, x); }
 
+// Dense grouping for the MFMA path.  (1) Each rotation is delayed to just before the next
+// two-qubit gate on its qubit (rotations commute with gates on other qubits), which keeps
+// every qubit's own gate order and the order of the two-qubit gates.  (2) The reordered list is
+// cut greedily into contiguous runs touching at most five qubits; each run becomes one 32x32
+// block (runs on fewer qubits are padded with untouched qubits, i.e. identity factors).
+static void build_dense(HostPlan* hp) {
+  const int n = hp->n;
+  hp->dense_ok = (n >= kDenseK && n <= kMaxQubits);
+  hp->dgroups.clear();
+  hp->dgates.clear();
+  if (!hp->dense_ok) return;
+  std::vector<qp_gate> order;
+  std::vector<std::vector<qp_gate>> pend(n);
+  for (const auto& g : hp->gates) {
+    if (g.kind <= QP_RZ) { pend[g.q0].push_back(g); continue; }
+    for (int q : {g.q0, g.q1}) {
+      for (auto& r : pend[q]) order.push_back(r);
+      pend[q].clear();
+    }
+    order.push_back(g);
+  }
+  for (int q = 0; q < n; ++q)
+    for (auto& r : pend[q]) order.push_back(r);
+  size_t i = 0;
+  while (i < order.size()) {
+    std::vector<int> qs;
+    auto has = [&](int q) { return std::find(qs.begin(), qs.end(), q) != qs.end(); };
+    QDenseGroup G{};
+    G.gate0 = (int)hp->dgates.size();
+    std::vector<qp_gate> run;
+    while (i < order.size()) {
+      const qp_gate& g = order[i];
+      std::vector<int> add;
+      if (!has(g.q0)) add.push_back(g.q0);
+      if (g.kind >= QP_CNOT && !has(g.q1) && g.q1 != g.q0) add.push_back(g.q1);
+      if ((int)(qs.size() + add.size()) > kDenseK) break;
+      for (int q : add) qs.push_back(q);
+      run.push_back(g);
+      ++i;
+    }
+    // pad to five qubits with the lowest unused qubits, then order block bits by index bit
+    for (int q = 0; q < n && (int)qs.size() < kDenseK; ++q)
+      if (!has(q)) qs.push_back(q);
+    std::sort(qs.begin(), qs.end(), [&](int a, int b) { return (n - 1 - a) < (n - 1 - b); });
+    for (int b = 0; b < kDenseK; ++b) G.pos[b] = n - 1 - qs[b];
+    auto local = [&](int q) {
+      for (int b = 0; b < kDenseK; ++b)
+        if (qs[b] == q) return b;
+      return -1;
+    };
+    for (const auto& g : run) {
+      QDenseGate d{};
+      d.kind = g.kind;
+      d.lq0 = local(g.q0);
+      d.lq1 = g.kind >= QP_CNOT ? local(g.q1) : -1;
+      d.param = (g.kind <= QP_RZ || g.kind == QP_CRZ) ? g.param : -1;
+      hp->dgates.push_back(d);
+    }
+    G.ngates = (int)run.size();
+    hp->dgroups.push_back(G);
+  }
+  // parameter -> (group, gate) occurrences
+  hp->docc.clear();
+  std::vector<std::vector<int>> per(hp->K);
+  for (size_t gi = 0; gi < hp->dgroups.size(); ++gi) {
+    const QDenseGroup& G = hp->dgroups[gi];
+    for (int k = 0; k < G.ngates; ++k) {
+      const QDenseGate& d = hp->dgates[G.gate0 + k];
+      if (d.param >= 0) {
+        per[d.param].push_back((int)hp->docc.size() / 2);
+        hp->docc.push_back((int)gi);
+        hp->docc.push_back(k);
+      }
+    }
+  }
+  hp->dcsr_ptr.assign(hp->K + 1, 0);
+  hp->dcsr_idx.clear();
+  for (int k = 0; k < hp->K; ++k) {
+    for (int o : per[k]) hp->dcsr_idx.push_back(o);
+    hp->dcsr_ptr[k + 1] = (int)hp->dcsr_idx.size();
+  }
+}
+
 std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   *status = QP_EINVAL;
   if (!d) return "null circuit descriptor";
@@ -271,8 +354,14 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
       for (int c = 0; c < hp->fused[fi].ncomp; ++c)
         hp->csr_idx[fill[hp->fused[fi].param[c]]++] = (int)fi * 4 + c;
   }
-  if (!hp->fused_ok) return "";
+  build_dense(hp);
+  if (!hp->fused_ok) {   // no register rounds; the image still carries the dense plan
+    hp->rounds.clear();
+    for (int i = 0; i < hp->m; ++i) hp->zmask[i] = 1u << (n - 1 - hp->out_qubits[i]);
+    goto image;
+  }
 
+  {
   // rounds
   hp->rounds.clear();
   std::vector<Affine> round_ent;    // entangler applied in the exchange before round k
@@ -388,7 +477,11 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     hp->n_exchanges++;
   }
 
+  }
+image:
   // device image
+  const int R = (int)hp->rounds.size();
+  if (hp->xf.size() < (size_t)R) { hp->xf.assign(R, QXchg{}); hp->xb.assign(R, QXchg{}); }
   QPlanDev h{};
   h.n = n;
   h.n_params = hp->K;
@@ -401,6 +494,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   h.n_feat = hp->n_feat;
   for (int q = 0; q < 16; ++q) h.coord_of_qubit[q] = hp->coord[q];
   for (int i = 0; i < kMaxOut; ++i) h.zmask[i] = hp->zmask[i];
+  for (int i = 0; i < kMaxOut; ++i) h.zplain[i] = i < hp->m ? 1u << (n - 1 - hp->out_qubits[i]) : 0u;
   size_t off = align16(sizeof(QPlanDev));
   h.off_rounds = (int)off; off = align16(off + sizeof(QRound) * R);
   h.off_xf = (int)off; off = align16(off + sizeof(QXchg) * R);
@@ -410,6 +504,13 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   h.off_csr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->csr_idx.size()));
   h.off_rff_B = (int)off; off = align16(off + sizeof(float) * hp->rffB.size());
   h.off_rff_W = (int)off; off = align16(off + sizeof(float) * hp->rffW.size());
+  h.n_dgroups = hp->dense_ok ? (int)hp->dgroups.size() : 0;
+  h.off_dgroups = (int)off; off = align16(off + sizeof(QDenseGroup) * hp->dgroups.size());
+  h.off_dgates = (int)off; off = align16(off + sizeof(QDenseGate) * hp->dgates.size());
+  h.n_docc = (int)hp->docc.size() / 2;
+  h.off_docc = (int)off; off = align16(off + sizeof(int32_t) * hp->docc.size());
+  h.off_dcsr_ptr = (int)off; off = align16(off + sizeof(int32_t) * hp->dcsr_ptr.size());
+  h.off_dcsr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->dcsr_idx.size()));
   h.bytes = (int)off;
   hp->blob.assign(off, 0);
   std::memcpy(hp->blob.data(), &h, sizeof(h));
@@ -423,6 +524,11 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     std::memcpy(hp->blob.data() + h.off_csr_idx, hp->csr_idx.data(), sizeof(int32_t) * hp->csr_idx.size());
   if (!hp->rffB.empty()) std::memcpy(hp->blob.data() + h.off_rff_B, hp->rffB.data(), sizeof(float) * hp->rffB.size());
   if (!hp->rffW.empty()) std::memcpy(hp->blob.data() + h.off_rff_W, hp->rffW.data(), sizeof(float) * hp->rffW.size());
+  if (!hp->dgroups.empty()) std::memcpy(hp->blob.data() + h.off_dgroups, hp->dgroups.data(), sizeof(QDenseGroup) * hp->dgroups.size());
+  if (!hp->dgates.empty()) std::memcpy(hp->blob.data() + h.off_dgates, hp->dgates.data(), sizeof(QDenseGate) * hp->dgates.size());
+  if (!hp->docc.empty()) std::memcpy(hp->blob.data() + h.off_docc, hp->docc.data(), sizeof(int32_t) * hp->docc.size());
+  std::memcpy(hp->blob.data() + h.off_dcsr_ptr, hp->dcsr_ptr.data(), sizeof(int32_t) * hp->dcsr_ptr.size());
+  if (!hp->dcsr_idx.empty()) std::memcpy(hp->blob.data() + h.off_dcsr_idx, hp->dcsr_idx.data(), sizeof(int32_t) * hp->dcsr_idx.size());
   return "";
 }
 

@@ -27,6 +27,11 @@ struct HostPlan {
   uint32_t zmask[kMaxOut] = {0};
   std::vector<int32_t> csr_ptr, csr_idx;
   int n_exchanges = 0;                 // exchanges that move data
+  // dense-block plan (MFMA path)
+  bool dense_ok = false;
+  std::vector<QDenseGroup> dgroups;
+  std::vector<QDenseGate> dgates;
+  std::vector<int32_t> docc, dcsr_ptr, dcsr_idx;
   std::vector<unsigned char> blob;     // QPlanDev + arrays (device image)
 };
 

@@ -51,6 +51,17 @@ struct alignas(16) QFused {
 
 enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2 };
 
+// Dense 2^5 blocks (MFMA path): a contiguous run of gates acting on at most five qubits.
+constexpr int kDenseK = 5;
+struct alignas(16) QDenseGate {
+  int32_t kind, lq0, lq1, param;   // local qubit bits inside the block (0..4)
+};
+struct alignas(16) QDenseGroup {
+  int32_t pos[kDenseK];   // logical index-bit position of block bit i
+  int32_t gate0, ngates;  // range in the QDenseGate array
+  int32_t pad;
+};
+
 // Plan header uploaded to the device (followed by the arrays at the given byte offsets).
 struct alignas(16) QPlanDev {
   int32_t n, n_params, n_out, n_fused, n_rounds;
@@ -66,6 +77,14 @@ struct alignas(16) QPlanDev {
   int32_t off_rff_B;                // float[F][3]
   int32_t off_rff_W;                // float[n][2F]
   int32_t bytes;
+  int32_t n_dgroups;                // dense groups (0: no dense plan)
+  int32_t off_dgroups;              // QDenseGroup[n_dgroups]
+  int32_t off_dgates;               // QDenseGate[...]
+  int32_t n_docc;                   // parametrised gates inside dense groups
+  int32_t off_docc;                 // int32[n_docc][2]: group, gate index
+  int32_t off_dcsr_ptr;             // int32[n_params+1] over the occurrences
+  int32_t off_dcsr_idx;             // int32[n_docc]
+  uint32_t zplain[kMaxOut];         // readout parity mask of output i without folding
 };
 
 }  // namespace qp

@@ -1,0 +1,129 @@
+"""Uneven batch (many circuits, one persistent launch) vs the oracle, vs the single-circuit
+fused path, and under hipGraph replay (GPU only)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import qpinn_oracle as O
+from tests.gpu_helpers import TOL, rel, report, t2n
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2506_23246_amd.api import Context
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    return Context(0, stream=s), s
+
+
+def _batch(ctx, ws):
+    from paper_2506_23246_amd.api import Batch
+    return Batch(ctx, [w.circuit for w in ws], [len(w.points) for w in ws])
+
+
+def test_batch_matches_oracle_per_circuit(env):
+    import torch
+    ctx, s = env
+    ws = W.batch_config(P_cap=24)
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    for i in range(0, len(ws), 3):
+        w = ws[i]
+        f, g, L, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+        e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
+                 loss=rel(t2n(bufs[i]["loss"]), [L]), grad=rel(t2n(bufs[i]["grad"]), grad))
+        report(f"batch {w.name}", **e)
+        for k, v in e.items():
+            assert v < TOL, (w.name, k, v)
+
+
+def test_batch_matches_single_circuit_path(env):
+    import torch
+    from paper_2506_23246_amd.api import Circuit
+    ctx, s = env
+    ws = W.batch_config(P_cap=300)
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc())
+        singles = [Circuit(ctx, w.circuit).maxwell(w.params, w.points, w.loss) for w in ws]
+    s.synchronize()
+    for i, w in enumerate(ws):
+        for key in ("out", "tan"):   # same per-point kernels: identical
+            assert np.array_equal(t2n(bufs[i][key]), t2n(singles[i][key])), (w.name, key)
+        assert rel(t2n(bufs[i]["grad"]), t2n(singles[i]["grad"])) < 1e-6
+        assert rel(t2n(bufs[i]["loss"]), t2n(singles[i]["loss"])) < 1e-6
+
+
+def test_batch_graph_replays_match_eager(env):
+    """Capture once, replay several times with new parameters written in place and eager work
+    and synchronisations between the replays; every replay equals an eager run."""
+    import torch
+    ctx, s = env
+    ws = W.batch_config(P_cap=200)
+    b = _batch(ctx, ws)
+    rng = np.random.default_rng(5)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    eager0 = [{k: t2n(v).copy() for k, v in bb.items() if v is not None} for bb in bufs]
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            b.run(arr, W.MaxwellDesc(), graph=True)
+        s.synchronize()
+        got = [{k: t2n(v).copy() for k, v in bb.items() if v is not None} for bb in bufs]
+        for i in range(len(ws)):
+            for k in got[i]:
+                if k == "params" or k == "points":
+                    continue
+                assert np.array_equal(got[i][k], eager0[i][k]), (rep, i, k)
+        _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    assert b.info(3) == 1
+    # new parameters in place: replay == eager on the new values
+    with torch.cuda.stream(s):
+        for i, w in enumerate(ws):
+            bufs[i]["params"].copy_(torch.tensor(rng.uniform(0, 6.28, w.circuit.n_params), dtype=torch.float32))
+        b.run(arr, W.MaxwellDesc(), graph=True)
+    s.synchronize()
+    g1 = [t2n(bb["grad"]).copy() for bb in bufs]
+    with torch.cuda.stream(s):
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    for i in range(len(ws)):
+        assert np.array_equal(g1[i], t2n(bufs[i]["grad"]))
+    w = ws[4]
+    _, _, L, grad = O.maxwell_eval(w.circuit, t2n(bufs[4]["params"]), w.points, w.loss)
+    assert rel(g1[4], grad) < TOL
+
+
+def test_full_size_batch_sampled_outputs(env):
+    """The full uneven batch (about half a million points): sampled outputs against the oracle,
+    finite loss and gradients, deterministic repeat."""
+    import torch
+    ctx, s = env
+    ws = W.batch_config()
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    first = [t2n(bb["grad"]).copy() for bb in bufs]
+    with torch.cuda.stream(s):
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    for i, w in enumerate(ws):
+        assert np.array_equal(first[i], t2n(bufs[i]["grad"]))
+        assert np.all(np.isfinite(first[i]))
+        if i % 4 == 0:
+            idx = np.linspace(0, len(w.points) - 1, 4).astype(int)
+            f, g = O.simulate(w.circuit, w.params, w.points[idx])
+            e = rel(t2n(bufs[i]["out"])[idx], f), rel(t2n(bufs[i]["tan"])[idx], g)
+            report(f"full batch {w.name} P={len(w.points)}", f=e[0], g=e[1])
+            assert e[0] < TOL and e[1] < TOL
