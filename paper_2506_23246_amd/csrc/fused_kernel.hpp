@@ -9,6 +9,12 @@
 
 namespace qp {
 
+// Uniform, read-only kernel data (plan, gate table) is read through the constant address space,
+// so the compiler emits scalar loads (SGPRs) instead of per-lane vector loads that stall a wave.
+#define QP_CONST __attribute__((address_space(4)))
+template <typename T> using CP = const QP_CONST T*;
+template <typename T> __device__ __forceinline__ CP<T> to_const(const T* p) { return (CP<T>)(p); }
+
 __device__ __forceinline__ uint32_t parity(uint32_t x) { return __popc(x) & 1u; }
 
 // LDS index swizzle: XOR the low nibble with the fold of all higher nibbles (a bijection).
@@ -19,8 +25,8 @@ __device__ __forceinline__ uint32_t swz(uint32_t idx) {
   return idx ^ (h & 15u);
 }
 
-template <int N>
-__device__ __forceinline__ uint32_t deposit_thread(uint32_t u, const uint8_t* __restrict__ tpos) {
+template <int N, typename TP>
+__device__ __forceinline__ uint32_t deposit_thread(uint32_t u, TP tpos) {
   uint32_t j = 0;
 #pragma unroll
   for (int k = 3; k < N; ++k) j |= ((u >> (k - 3)) & 1u) << tpos[k];
@@ -113,8 +119,7 @@ __device__ __forceinline__ float wave_reduce_scatter8(const float* v, int lane) 
 // through the exchange descriptor X (index map and sign), in groups of EXS planes.
 template <int N, int T, int NSV, int EXS>
 __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         const QRound* __restrict__ wr, const QRound* __restrict__ rd,
-                                         const QXchg* __restrict__ X, uint32_t u, uint32_t pbase) {
+                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase) {
   constexpr int PLANE = T * 8;
   const uint32_t jw = deposit_thread<N>(u, wr->tpos);
   const uint32_t w0 = wr->tpos[0], w1 = wr->tpos[1], w2 = wr->tpos[2];
@@ -184,11 +189,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
   constexpr int PPW = T / TP;              // points per workgroup tile
   constexpr int DIM = 1 << N;
   static_assert(PPW >= 1, "tile too small");
-  const QPlanDev* __restrict__ plan = a.plan;
-  const char* pb = reinterpret_cast<const char*>(plan);
-  const QRound* __restrict__ rounds = reinterpret_cast<const QRound*>(pb + plan->off_rounds);
-  const QXchg* __restrict__ xf = reinterpret_cast<const QXchg*>(pb + plan->off_xf);
-  const QXchg* __restrict__ xb = reinterpret_cast<const QXchg*>(pb + plan->off_xb);
+  CP<QPlanDev> plan = to_const(a.plan);
+  CP<char> pb = reinterpret_cast<CP<char>>(plan);
+  CP<QRound> rounds = reinterpret_cast<CP<QRound>>(pb + plan->off_rounds);
+  CP<QXchg> xf = reinterpret_cast<CP<QXchg>>(pb + plan->off_xf);
+  CP<QXchg> xb = reinterpret_cast<CP<QXchg>>(pb + plan->off_xb);
+  CP<float> gtab = to_const(a.gtab);
   const int R = plan->n_rounds;
   const int m = plan->n_out;
   const int F = a.n_fused;
@@ -271,7 +277,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- product state and tangent seeds in round 0's mapping ---------------
     {
-      const QRound* r0 = rounds;
+      CP<QRound> r0 = rounds;
       // thread part: (P, D_c) by the product rule over the thread qubits
       float Pr = valid ? 1.f : 0.f, Pi = 0.f;
       float Dr[3] = {0.f, 0.f, 0.f}, Di[3] = {0.f, 0.f, 0.f};
@@ -333,27 +339,27 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- forward rounds -------------------------------------------------------
     for (int k = 0; k < R; ++k) {
-      const QRound* rk = rounds + k;
+      CP<QRound> rk = rounds + k;
       if (k > 0) exchange<N, T, 4, (EXS < 4 ? EXS : 4)>(sr, si, buf, rk - 1, rk, xf + k, u, pbase);
       float g[8];
       if (rk->gate[0] >= 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[0] * 8 + e];
+        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[0] * 8 + e];
         apply_gate<0, 0, 4>(sr, si, g);
       }
       if (rk->gate[1] >= 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[1] * 8 + e];
+        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[1] * 8 + e];
         apply_gate<1, 0, 4>(sr, si, g);
       }
       if (rk->gate[2] >= 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = a.gtab[rk->gate[2] * 8 + e];
+        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[2] * 8 + e];
         apply_gate<2, 0, 4>(sr, si, g);
       }
     }
     // ---------------- readout ----------------------------------------------------------------
-    const QRound* rl = rounds + (R - 1);
+    CP<QRound> rl = rounds + (R - 1);
     const uint32_t jl = deposit_thread<N>(u, rl->tpos);
     const uint32_t l0 = rl->tpos[0], l1 = rl->tpos[1], l2 = rl->tpos[2];
     float acc[kMaxOut * 4];
@@ -486,14 +492,14 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- adjoint sweep with uncompute -----------------------------------------
     for (int k = R - 1; k >= 0; --k) {
-      const QRound* rk = rounds + k;
+      CP<QRound> rk = rounds + k;
 #pragma unroll
       for (int bb = 2; bb >= 0; --bb) {
         const int gid = rk->gate[bb];
         if (gid < 0) continue;
         float g[8], d[8], mm[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) { g[e] = a.gtab[gid * 8 + e]; mm[e] = 0.f; }
+        for (int e = 0; e < 8; ++e) { g[e] = gtab[gid * 8 + e]; mm[e] = 0.f; }
         dagger(g, d);
         if (bb == 0) { apply_gate<0, 0, 4>(sr, si, d); accum_m<0>(sr, si, mm); apply_gate<0, 4, 4>(sr, si, d); }
         if (bb == 1) { apply_gate<1, 0, 4>(sr, si, d); accum_m<1>(sr, si, mm); apply_gate<1, 4, 4>(sr, si, d); }

@@ -94,9 +94,9 @@ uint32_t qform(const std::vector<std::pair<uint32_t, uint32_t>>& terms, uint32_t
 // Thread-bit order for a round: register bits first, then the remaining positions chosen so
 // that each group of four consecutive lane bits lands on distinct position residues mod 4
 // (the LDS swizzle folds higher nibbles into the low four bits).
-void make_tpos(int n, const int reg[3], uint8_t* tpos) {
+void make_tpos(int n, const int reg[3], int32_t* tpos) {
   bool used[16] = {false};
-  for (int i = 0; i < 3; ++i) { tpos[i] = (uint8_t)reg[i]; used[reg[i]] = true; }
+  for (int i = 0; i < 3; ++i) { tpos[i] = reg[i]; used[reg[i]] = true; }
   int k = 3;
   int group_mask = 0;
   while (k < n) {
@@ -109,25 +109,25 @@ void make_tpos(int n, const int reg[3], uint8_t* tpos) {
         if (!used[p]) { pick = p; break; }
     used[pick] = true;
     group_mask |= 1 << (pick & 3);
-    tpos[k++] = (uint8_t)pick;
+    tpos[k++] = pick;
   }
   for (; k < 16; ++k) tpos[k] = 0;
 }
 
-uint32_t jr_of(const uint8_t* tpos, int r) {
+uint32_t jr_of(const int32_t* tpos, int r) {
   return ((uint32_t)(r & 1) << tpos[0]) | ((uint32_t)((r >> 1) & 1) << tpos[1]) |
          ((uint32_t)((r >> 2) & 1) << tpos[2]);
 }
 
 void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool sign_at_src,
-               const uint8_t* read_tpos) {
+               const int32_t* read_tpos) {
   std::memset(X, 0, sizeof(QXchg));
-  for (int k = 0; k < 16; ++k) X->acol[k] = (uint16_t)(k < n ? Acols[k] : 0);
-  for (int r = 0; r < 8; ++r) X->src_r[r] = (uint16_t)apply_cols(Acols, n, jr_of(read_tpos, r));
-  X->nterms = (uint8_t)aff.terms.size();
+  for (int k = 0; k < 16; ++k) X->acol[k] = k < n ? Acols[k] : 0u;
+  for (int r = 0; r < 8; ++r) X->src_r[r] = apply_cols(Acols, n, jr_of(read_tpos, r));
+  X->nterms = (uint32_t)aff.terms.size();
   for (size_t t = 0; t < aff.terms.size(); ++t) {
-    X->qu[t] = (uint16_t)aff.terms[t].first;
-    X->qv[t] = (uint16_t)aff.terms[t].second;
+    X->qu[t] = aff.terms[t].first;
+    X->qv[t] = aff.terms[t].second;
   }
   X->sign_at_src = sign_at_src ? 1 : 0;
   for (int i = 0; i < 3; ++i) {
@@ -141,15 +141,15 @@ void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool s
     X->ue[i] = ue;
     X->ve[i] = ve;
   }
-  uint8_t qs = 0;
+  uint32_t qs = 0;
   for (int r = 0; r < 8; ++r) {
     uint32_t xr = sign_at_src ? X->src_r[r] : jr_of(read_tpos, r);
-    qs |= (uint8_t)(qform(aff.terms, xr) << r);
+    qs |= qform(aff.terms, xr) << r;
   }
   X->qsign_r = qs;
   bool ident = aff.terms.empty();
   for (int k = 0; k < n; ++k) ident = ident && (Acols[k] == (1u << k));
-  X->identity = ident ? 1 : 0;
+  X->identity = ident ? 1u : 0u;
 }
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -371,7 +371,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   bool have_pending = false;
   auto push_round = [&](const int* gate_ids, const int* reg) {
     QRound R{};
-    for (int i = 0; i < 3; ++i) R.gate[i] = (int16_t)gate_ids[i];
+    for (int i = 0; i < 3; ++i) R.gate[i] = gate_ids[i];
     make_tpos(n, reg, R.tpos);
     hp->rounds.push_back(R);
     round_ent.push_back(pending);

@@ -1,5 +1,7 @@
 // Internal types shared by the planner (host C++) and the gfx950 kernels.
 //
+// All fields are 32-bit so that the kernels read them with scalar loads.
+//
 // Index conventions: a basis index j of an n-qubit state has qubit q in bit (n-1-q), so
 // qubit 0 is the most significant bit.  "Logical" index = the index of the state the circuit
 // defines.  In the fused kernels a thread owns 8 amplitudes of each statevector: its three
@@ -17,9 +19,9 @@ constexpr int kMaxTerms = 32;      // sign terms of one entangler stage
 constexpr int kRegBits = 3;        // 8 amplitudes per thread per statevector
 
 struct alignas(16) QRound {
-  int16_t gate[3];    // fused-gate id applied on register bit b (-1: none)
-  int16_t pad0;
-  uint8_t tpos[16];   // logical index-bit position of physical bit k
+  int32_t gate[3];    // fused-gate id applied on register bit b (-1: none)
+  int32_t pad0;
+  int32_t tpos[16];   // logical index-bit position of physical bit k
 };
 
 // One direction of the register exchange that precedes a round.  Reader thread (u, r) in the
@@ -28,18 +30,20 @@ struct alignas(16) QRound {
 // destination coordinates) or x = src (sign in the source coordinates) and
 // Q(x) = XOR_t parity(qu[t] & x) * parity(qv[t] & x).
 struct alignas(16) QXchg {
-  uint16_t acol[16];
-  uint16_t src_r[8];  // A jr(r): uniform part of the source index
-  uint16_t qu[kMaxTerms];
-  uint16_t qv[kMaxTerms];
+  uint32_t acol[16];
+  uint32_t src_r[8];  // A jr(r): uniform part of the source index
+  uint32_t qu[kMaxTerms];
+  uint32_t qv[kMaxTerms];
   uint32_t ue[3];     // bit t: parity(qu[t] & x_e(i)) for register basis i (uniform)
   uint32_t ve[3];
-  uint8_t nterms;
-  uint8_t sign_at_src;
-  uint8_t qsign_r;    // bit r: Q(x_r) for the uniform part x_r
-  uint8_t identity;   // A = I and no sign terms
-  uint32_t pad1;
+  uint32_t nterms;
+  uint32_t sign_at_src;
+  uint32_t qsign_r;   // bit r: Q(x_r) for the uniform part x_r
+  uint32_t identity;  // A = I and no sign terms
+  uint32_t pad1[2];
 };
+static_assert(sizeof(QXchg) == 400, "QXchg layout");
+static_assert(sizeof(QRound) == 80, "QRound layout");
 
 // Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).
 struct alignas(16) QFused {
