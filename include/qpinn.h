@@ -205,8 +205,11 @@ int64_t qp_batch_info(const qp_batch* b, int32_t what);
 
 /* ---- plain baseline (the speedup denominator) -----------------------------------------
  * One kernel launch per gate on a statevector batch held in HBM, a readout kernel, input
- * tangents by central finite differences (6 extra forwards with step fd_h) - the evaluation
- * count of the paper's hardware-derivative cost model (section 2.1, cost per point).
+ * tangents by central finite differences (6 extra forwards with step fd_h): the evaluation
+ * pattern a simulator without backpropagation, or quantum hardware, pays for derivatives
+ * (the paper's measurement passage in section "QPINN architecture and ansatz designs" names
+ * parameter-shift as the hardware route; section "Quantum simulator and performance
+ * optimization" uses backpropagation instead).
  * precision 32: complex64 state; 64: complex128 state.  params [K], points [P][3] and the
  * outputs use the matching real type (float or double).  tan may be NULL (forward only).   */
 size_t qp_plain_workspace_bytes(const qp_circuit* c, int64_t P, int32_t precision);
