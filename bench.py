@@ -35,9 +35,10 @@ def flops_per_point(n_fused: int, n: int) -> float:
     """Algorithmic FP32 flops of one point (mul = 1, fma = 2):
     forward: 4 statevectors x F gates x 2^n amplitudes x 14 (complex 2x2 row: 1 mul + 3 fma per
     real part); adjoint: 8 statevectors x F x 2^n x 14 (uncompute + pull-back) plus the gate
-    adjoint products, 4 statevector pairs x 4 entries x 4 fma x 2 per amplitude pair = 64 per
-    amplitude.  Encoding, readout, seeds and the LDS exchanges are not counted."""
-    return float(n_fused) * (2 ** n) * (4 * 14 + 8 * 14 + 64)
+    statistic S_k = Im <lambda|sigma_k|psi>, 4 statevector pairs x 3 components x 4 fma x 2 per
+    amplitude pair = 48 per amplitude.  Encoding, readout, seeds and the LDS exchanges are not
+    counted."""
+    return float(n_fused) * (2 ** n) * (4 * 14 + 8 * 14 + 48)
 
 
 def cpu_baseline(w, budget_s: float = 12.0, max_points: int = 512):

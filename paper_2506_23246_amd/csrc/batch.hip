@@ -24,6 +24,11 @@ __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGa
   if (g >= ngates) return;
   const BatchGate G = gates[g];
   const BatchCirc& C = circs[G.circ];
+  if (G.idx == C.F) {   // identity entry used for absent gates of a round
+    float* o = const_cast<float*>(C.a.gtab) + G.idx * 8;
+    for (int e = 0; e < 8; ++e) o[e] = (e == 0 || e == 6) ? 1.f : 0.f;
+    return;
+  }
   const QPlanDev* plan = C.a.plan;
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + G.idx;
   double u[8];
@@ -81,8 +86,8 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ 
     const BatchItem it = items[id];
     const BatchCirc& C = circs[it.circ];
     const int F = C.F;
-    float* red = slots + WAVES * F * 8;
-    for (int i = tid; i < WAVES * F * 8; i += kBT) slots[i] = 0.f;
+    float* red = slots + WAVES * F * kGS;
+    for (int i = tid; i < WAVES * F * kGS; i += kBT) slots[i] = 0.f;
     __syncthreads();
     float lacc = 0.f;
     switch (C.n) {
@@ -98,10 +103,10 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ 
       default: break;
     }
     __syncthreads();
-    float* mp = mpart + C.mpart_off + (long long)it.slot * F * 8;
-    for (int i = tid; i < F * 8; i += kBT) {
+    float* mp = mpart + C.mpart_off + (long long)it.slot * F * kGS;
+    for (int i = tid; i < F * kGS; i += kBT) {
       float s = 0.f;
-      for (int w = 0; w < WAVES; ++w) s += slots[w * F * 8 + i];
+      for (int w = 0; w < WAVES; ++w) s += slots[w * F * kGS + i];
       mp[i] = s;
     }
     for (int off = 32; off >= 1; off >>= 1) lacc += __shfl_xor(lacc, off);
@@ -124,7 +129,7 @@ __global__ void k_batch_reduce(const BatchCirc* __restrict__ circs, const BatchC
   if (w >= ncols) return;
   const BatchCol col = cols[w];
   const BatchCirc& C = circs[col.circ];
-  const int ncol = C.F * 8;
+  const int ncol = C.F * kGS;
   double s = 0.0;
   if (col.col < ncol) {
     for (int b = lane; b < C.nitems; b += 64) s += (double)mpart[C.mpart_off + (long long)b * ncol + col.col];
@@ -147,7 +152,7 @@ __global__ void k_batch_grads(const BatchCirc* __restrict__ circs, const BatchGa
 }
 
 size_t batch_lds_bytes(int max_fused) {
-  return (size_t)kBEXS * kBT * 8 * sizeof(float2) + (size_t)(kBT / 64) * max_fused * 8 * sizeof(float) +
+  return (size_t)kBEXS * kBT * 8 * sizeof(float2) + (size_t)(kBT / 64) * max_fused * kGS * sizeof(float) +
          (size_t)(kBT / 64) * 40 * sizeof(float);
 }
 

@@ -61,8 +61,8 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   });
   for (int i = 0; i < count; ++i) {
     const int F = (int)b->circs[i]->hp.fused.size();
-    for (int c = 0; c <= F * 8; ++c) b->cols.push_back(BatchCol{i, c});
-    for (int f = 0; f < F; ++f) b->gates.push_back(BatchGate{i, f});
+    for (int c = 0; c <= F * kGS; ++c) b->cols.push_back(BatchCol{i, c});
+    for (int f = 0; f <= F; ++f) b->gates.push_back(BatchGate{i, f});   // f == F: identity entry
     for (int k = 0; k < b->circs[i]->hp.K; ++k) b->pars.push_back(BatchGate{i, k});
   }
   // workspace layout
@@ -74,11 +74,11 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   L.gtab_c.resize(count); L.counts_c.resize(count); L.m64_c.resize(count); L.mpart_c.resize(count);
   for (int i = 0; i < count; ++i) {
     const int F = (int)b->circs[i]->hp.fused.size();
-    L.gtab_c[i] = off; off = al(off + sizeof(float) * 8 * std::max(F, 1));
+    L.gtab_c[i] = off; off = al(off + sizeof(float) * 8 * (F + 1));
     L.counts_c[i] = off; off = al(off + 2 * sizeof(int));
-    L.m64_c[i] = off; off = al(off + sizeof(double) * 8 * std::max(F, 1));
+    L.m64_c[i] = off; off = al(off + sizeof(double) * kGS * std::max(F, 1));
     L.mpart_c[i] = mp;
-    mp += (long long)nitems[i] * F * 8;
+    mp += (long long)nitems[i] * F * kGS;
   }
   L.mpart = off; off = al(off + sizeof(float) * (size_t)std::max<long long>(mp, 1));
   L.lpart = off; off = al(off + sizeof(float) * (size_t)std::max<size_t>(b->items.size(), 1));

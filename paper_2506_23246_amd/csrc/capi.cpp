@@ -207,15 +207,15 @@ WsLayout qp::fused_layout(const qp_circuit* c, int64_t P, int grid_cap) {
   WsLayout L{};
   const int F = (int)c->hp.fused.size();
   size_t off = 0;
-  L.gtab = off; off = al(off + sizeof(float) * 8 * std::max(F, 1));
+  L.gtab = off; off = al(off + sizeof(float) * 8 * (F + 1));   // + identity entry
   L.counts = off; off = al(off + 2 * sizeof(int));
   if (c->hp.enc_kind == QP_ENC_RFF) {
     L.angles = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n);
     L.jac = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n * 3);
   }
-  L.mpart = off; off = al(off + sizeof(float) * (size_t)grid_cap * F * 8);
+  L.mpart = off; off = al(off + sizeof(float) * (size_t)grid_cap * F * kGS);
   L.lpart = off; off = al(off + sizeof(float) * (size_t)std::max(grid_cap, 1));
-  L.m64 = off; off = al(off + sizeof(double) * (size_t)std::max(F, 1) * 8);
+  L.m64 = off; off = al(off + sizeof(double) * (size_t)std::max(F, 1) * kGS);
   L.total = off;
   return L;
 }
@@ -376,7 +376,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   }
   if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
   double* m64 = reinterpret_cast<double*>(w + L.m64);
-  if ((e = launch_reduce(a.mpart, grid, F * 8, mode == kModeMaxwell ? a.lpart : nullptr, m64,
+  if ((e = launch_reduce(a.mpart, grid, F * kGS, mode == kModeMaxwell ? a.lpart : nullptr, m64,
                          mode == kModeMaxwell ? loss : nullptr, st)) != hipSuccess)
     return hipcheck(ctx, e, "reduce");
   if (d_params && (e = launch_param_grads(c->dplan, c->hp.K, params, m64, d_params, st)) != hipSuccess)

@@ -54,7 +54,13 @@ hipError_t launch_fused_12(int mode, const FusedArgs& a, int grid, int exs, size
 __global__ void k_gate_table64(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
                                float* __restrict__ gtab) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= plan->n_fused) return;
+  if (f > plan->n_fused) return;
+  if (f == plan->n_fused) {   // identity entry used for absent gates of a round
+    float u[8];
+    set_identity(u);
+    for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
+    return;
+  }
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
   double u[8];
   set_identity(u);
@@ -69,7 +75,13 @@ __global__ void k_gate_table64(const QPlanDev* __restrict__ plan, const float* _
 __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
                              float* __restrict__ gtab) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= plan->n_fused) return;
+  if (f > plan->n_fused) return;
+  if (f == plan->n_fused) {   // identity entry used for absent gates of a round
+    float u[8];
+    set_identity(u);
+    for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
+    return;
+  }
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
   float u[8];
   set_identity(u);
@@ -161,7 +173,7 @@ int fused_threads(int n) { return n == 12 ? 512 : 256; }
 int fused_points_per_tile(int n) { return fused_threads(n) / (1 << (n - 3)); }
 size_t fused_lds_bytes(int n, int exs, int n_fused) {
   const int T = fused_threads(n);
-  return (size_t)exs * T * 8 * sizeof(float2) + (size_t)(T / 64) * n_fused * 8 * sizeof(float) +
+  return (size_t)exs * T * 8 * sizeof(float2) + (size_t)(T / 64) * n_fused * kGS * sizeof(float) +
          (size_t)(T / 64) * 40 * sizeof(float);
 }
 
@@ -182,9 +194,9 @@ hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, 
 }
 
 hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, int fp32, hipStream_t st) {
-  if (n_fused == 0) return hipSuccess;
-  if (fp32) hipLaunchKernelGGL(k_gate_table, dim3((n_fused + 127) / 128), dim3(128), 0, st, plan, params, gtab);
-  else hipLaunchKernelGGL(k_gate_table64, dim3((n_fused + 127) / 128), dim3(128), 0, st, plan, params, gtab);
+  const int entries = n_fused + 1;   // + identity
+  if (fp32) hipLaunchKernelGGL(k_gate_table, dim3((entries + 127) / 128), dim3(128), 0, st, plan, params, gtab);
+  else hipLaunchKernelGGL(k_gate_table64, dim3((entries + 127) / 128), dim3(128), 0, st, plan, params, gtab);
   return hipGetLastError();
 }
 

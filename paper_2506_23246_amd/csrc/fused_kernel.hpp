@@ -67,72 +67,89 @@ __device__ __forceinline__ void dagger(const float* u, float* d) {
   d[6] = u[6]; d[7] = -u[7];   // (1,1) <- conj u11
 }
 
-// M_ab += conj(x_a) y_b over register pairs of bit B; x = statevector XS+s, y = statevector s.
 template <int B>
-__device__ __forceinline__ void accum_m(const float (&sr)[8][8], const float (&si)[8][8], float* m) {
+__device__ __forceinline__ void accum_s(const float (&sr)[8][8], const float (&si)[8][8], float* q) {
+  // Pauli components of the gate's adjoint product for the pairs on register bit B, with
+  // x = lambda-family (statevectors 4..7) and y = psi-family (0..3), both before the gate:
+  //   S_x += Im(conj(x0) y1) + Im(conj(x1) y0)
+  //   S_y += Re(conj(x1) y0) - Re(conj(x0) y1)
+  //   S_z += Im(conj(x0) y0) - Im(conj(x1) y1)
+  // Two accumulators per component (even/odd statevector pair) shorten the FMA chains.
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    float* m = q + 3 * (s & 1);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       if (r & (1 << B)) continue;
       const int r1 = r | (1 << B);
       const float x0r = sr[4 + s][r], x0i = si[4 + s][r], x1r = sr[4 + s][r1], x1i = si[4 + s][r1];
       const float y0r = sr[s][r], y0i = si[s][r], y1r = sr[s][r1], y1i = si[s][r1];
-      // conj(x) y = (xr yr + xi yi) + i (xr yi - xi yr)
-      m[0] += x0r * y0r + x0i * y0i;  m[1] += x0r * y0i - x0i * y0r;
-      m[2] += x0r * y1r + x0i * y1i;  m[3] += x0r * y1i - x0i * y1r;
-      m[4] += x1r * y0r + x1i * y0i;  m[5] += x1r * y0i - x1i * y0r;
-      m[6] += x1r * y1r + x1i * y1i;  m[7] += x1r * y1i - x1i * y1r;
+      m[0] = fmaf(x0r, y1i, m[0]); m[0] = fmaf(-x0i, y1r, m[0]);
+      m[0] = fmaf(x1r, y0i, m[0]); m[0] = fmaf(-x1i, y0r, m[0]);
+      m[1] = fmaf(x1r, y0r, m[1]); m[1] = fmaf(x1i, y0i, m[1]);
+      m[1] = fmaf(-x0r, y1r, m[1]); m[1] = fmaf(-x0i, y1i, m[1]);
+      m[2] = fmaf(x0r, y0i, m[2]); m[2] = fmaf(-x0i, y0r, m[2]);
+      m[2] = fmaf(-x1r, y1i, m[2]); m[2] = fmaf(x1i, y1r, m[2]);
     }
   }
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {   // DPP lane permutation (row-local)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Reduce 8 floats over the 64 lanes of a wave; afterwards lane 8*e holds the sum of entry e.
-__device__ __forceinline__ float wave_reduce_scatter8(const float* v, int lane) {
-  const bool h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1;
-  float a[4], b[2], c;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float send = h5 ? v[i] : v[4 + i];
-    const float keep = h5 ? v[4 + i] : v[i];
-    a[i] = keep + __shfl_xor(send, 32);
-  }
+// Reduce-scatter of four per-lane values over the wave: permlane32_swap pairs lanes l and l+32
+// (entries split 2/2), permlane16_swap pairs rows 0/1 and 2/3 (1/1), then DPP row_ror:8,
+// quad_perm xor 1, xor 2 and row_half_mirror sum the sixteen lanes of each row.  Lanes of row e
+// end with entry e.  No LDS traffic.
+__device__ __forceinline__ float wave_reduce_scatter4(const float* v) {
+  float a[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const float send = h4 ? a[i] : a[2 + i];
-    const float keep = h4 ? a[2 + i] : a[i];
-    b[i] = keep + __shfl_xor(send, 16);
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_int(v[i]), __float_as_int(v[2 + i]), false, false);
+    a[i] = __int_as_float(sw[0]) + __int_as_float(sw[1]);
   }
-  {
-    const float send = h3 ? b[0] : b[1];
-    const float keep = h3 ? b[1] : b[0];
-    c = keep + __shfl_xor(send, 8);
-  }
-  c += __shfl_xor(c, 4);
-  c += __shfl_xor(c, 2);
-  c += __shfl_xor(c, 1);
-  return c;   // entry index (h5*4 + h4*2 + h3) on every lane of the octet
+  const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_int(a[0]), __float_as_int(a[1]), false, false);
+  float c = __int_as_float(sw[0]) + __int_as_float(sw[1]);
+  c += dppf<0x128>(c);   // row_ror:8  (lane l <- l ^ 8 within a row)
+  c += dppf<0xB1>(c);    // quad_perm [1,0,3,2]: xor 1
+  c += dppf<0x4E>(c);    // quad_perm [2,3,0,1]: xor 2
+  c += dppf<0x141>(c);   // row_half_mirror: lane l <- 7 - l within eight lanes
+  return c;
 }
 
 // ---- register exchange through LDS ----------------------------------------------------------
 // Writes statevectors [0, NSV) in the writer mapping `wr`, reads them back in mapping `rd`
 // through the exchange descriptor X (index map and sign), in groups of EXS planes.
+// jc: on entry the thread part of the state index in mapping `wr` (deposit of u), on exit the
+// same in mapping `rd`, so consecutive exchanges deposit the thread bits once each.
+// Address arithmetic: pbase is a multiple of 2^N and every index below 2^N, so pbase + x equals
+// pbase ^ x; swz is linear over GF(2), so swz(pbase ^ j ^ o) = swz(pbase ^ j) ^ swz(o).  The
+// register offsets o are uniform across the workgroup, leaving one per-lane XOR per access.
 template <int N, int T, int NSV, int EXS>
 __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase) {
+                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase,
+                                         uint32_t& jc) {
   constexpr int PLANE = T * 8;
-  const uint32_t jw = deposit_thread<N>(u, wr->tpos);
+  const uint32_t jw = jc;
   const uint32_t w0 = wr->tpos[0], w1 = wr->tpos[1], w2 = wr->tpos[2];
   const uint32_t jn = deposit_thread<N>(u, rd->tpos);
+  jc = jn;
   uint32_t sb;
   uint32_t sgn = 0;   // bit r set: negate amplitude r
   if (X->identity) {
     sb = jn;
   } else {
+    // sb = A jn with jn = sum of the thread bits placed at rd->tpos[k]: column A e_tpos[k] is
+    // acol[tpos[k]], so only the N - 3 thread bits are visited.
     sb = 0;
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-      if ((jn >> k) & 1u) sb ^= X->acol[k];
+    for (int k = 3; k < N; ++k) {
+      const uint32_t msk = 0u - ((u >> (k - 3)) & 1u);
+      sb ^= msk & X->acol[rd->tpos[k]];
+    }
     const int nt = X->nterms;
     if (nt > 0) {
       const uint32_t xb = X->sign_at_src ? sb : jn;
@@ -156,32 +173,47 @@ __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], f
       }
     }
   }
-  uint32_t srcr[8];
+  const uint32_t wb = swz(pbase ^ jw), rb = swz(pbase ^ sb);
+  uint32_t wo[8], ro[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) srcr[r] = X->identity ? reg_off(r, rd->tpos[0], rd->tpos[1], rd->tpos[2]) : X->src_r[r];
+  for (int r = 0; r < 8; ++r) {
+    wo[r] = swz(reg_off(r, w0, w1, w2));
+    ro[r] = swz(X->identity ? reg_off(r, rd->tpos[0], rd->tpos[1], rd->tpos[2]) : X->src_r[r]);
+  }
 #pragma unroll
   for (int g = 0; g < NSV; g += EXS) {
 #pragma unroll
     for (int s = 0; s < EXS; ++s)
 #pragma unroll
       for (int r = 0; r < 8; ++r)
-        buf[s * PLANE + swz(pbase + (jw ^ reg_off(r, w0, w1, w2)))] = make_float2(sr[g + s][r], si[g + s][r]);
+        buf[s * PLANE + (wb ^ wo[r])] = make_float2(sr[g + s][r], si[g + s][r]);
     __syncthreads();
+    if (sgn == 0u) {   // uniform when the stage has no sign terms (e.g. a CNOT ring)
 #pragma unroll
-    for (int s = 0; s < EXS; ++s)
+      for (int s = 0; s < EXS; ++s)
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const float2 v = buf[s * PLANE + swz(pbase + (sb ^ srcr[r]))];
-        const bool neg = (sgn >> r) & 1u;
-        sr[g + s][r] = neg ? -v.x : v.x;
-        si[g + s][r] = neg ? -v.y : v.y;
-      }
+        for (int r = 0; r < 8; ++r) {
+          const float2 v = buf[s * PLANE + (rb ^ ro[r])];
+          sr[g + s][r] = v.x;
+          si[g + s][r] = v.y;
+        }
+    } else {
+#pragma unroll
+      for (int s = 0; s < EXS; ++s)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const float2 v = buf[s * PLANE + (rb ^ ro[r])];
+          const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
+          sr[g + s][r] = __uint_as_float(__float_as_uint(v.x) ^ flip);
+          si[g + s][r] = __uint_as_float(__float_as_uint(v.y) ^ flip);
+        }
+    }
     __syncthreads();
   }
 }
 
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
-// buf: EXS exchange planes; slots: per-wave M accumulators [WAVES][F][8]; red: [WAVES][40].
+// buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
 template <int N, int T, int EXS, int MODE>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ red, float& lacc) {
@@ -338,29 +370,28 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
     }
     // ---------------- forward rounds -------------------------------------------------------
+    uint32_t jc = deposit_thread<N>(u, rounds[0].tpos);   // thread bits in the current mapping
     for (int k = 0; k < R; ++k) {
       CP<QRound> rk = rounds + k;
-      if (k > 0) exchange<N, T, 4, (EXS < 4 ? EXS : 4)>(sr, si, buf, rk - 1, rk, xf + k, u, pbase);
+      if (k > 0) exchange<N, T, 4, (EXS < 4 ? EXS : 4)>(sr, si, buf, rk - 1, rk, xf + k, u, pbase, jc);
+      // branch-free: an absent gate is the identity entry F of the gate table
       float g[8];
-      if (rk->gate[0] >= 0) {
+      const int g0 = rk->gate[0] >= 0 ? rk->gate[0] : F;
+      const int g1 = rk->gate[1] >= 0 ? rk->gate[1] : F;
+      const int g2 = rk->gate[2] >= 0 ? rk->gate[2] : F;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[0] * 8 + e];
-        apply_gate<0, 0, 4>(sr, si, g);
-      }
-      if (rk->gate[1] >= 0) {
+      for (int e = 0; e < 8; ++e) g[e] = gtab[g0 * 8 + e];
+      apply_gate<0, 0, 4>(sr, si, g);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[1] * 8 + e];
-        apply_gate<1, 0, 4>(sr, si, g);
-      }
-      if (rk->gate[2] >= 0) {
+      for (int e = 0; e < 8; ++e) g[e] = gtab[g1 * 8 + e];
+      apply_gate<1, 0, 4>(sr, si, g);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = gtab[rk->gate[2] * 8 + e];
-        apply_gate<2, 0, 4>(sr, si, g);
-      }
+      for (int e = 0; e < 8; ++e) g[e] = gtab[g2 * 8 + e];
+      apply_gate<2, 0, 4>(sr, si, g);
     }
     // ---------------- readout ----------------------------------------------------------------
     CP<QRound> rl = rounds + (R - 1);
-    const uint32_t jl = deposit_thread<N>(u, rl->tpos);
+    const uint32_t jl = jc;
     const uint32_t l0 = rl->tpos[0], l1 = rl->tpos[1], l2 = rl->tpos[2];
     float acc[kMaxOut * 4];
 #pragma unroll
@@ -495,22 +526,23 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       CP<QRound> rk = rounds + k;
 #pragma unroll
       for (int bb = 2; bb >= 0; --bb) {
-        const int gid = rk->gate[bb];
-        if (gid < 0) continue;
-        float g[8], d[8], mm[8];
+        const int gsrc = rk->gate[bb];
+        const int gid = gsrc >= 0 ? gsrc : F;   // identity entry: straight-line code, no branch
+        float g[8], d[8], q[6];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) { g[e] = gtab[gid * 8 + e]; mm[e] = 0.f; }
+        for (int e = 0; e < 8; ++e) g[e] = gtab[gid * 8 + e];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) q[e] = 0.f;
         dagger(g, d);
-        if (bb == 0) { apply_gate<0, 0, 4>(sr, si, d); accum_m<0>(sr, si, mm); apply_gate<0, 4, 4>(sr, si, d); }
-        if (bb == 1) { apply_gate<1, 0, 4>(sr, si, d); accum_m<1>(sr, si, mm); apply_gate<1, 4, 4>(sr, si, d); }
-        if (bb == 2) { apply_gate<2, 0, 4>(sr, si, d); accum_m<2>(sr, si, mm); apply_gate<2, 4, 4>(sr, si, d); }
-        const float v = wave_reduce_scatter8(mm, lane);
-        if ((lane & 7) == 0) {
-          const int e = (((lane >> 5) & 1) << 2) | (((lane >> 4) & 1) << 1) | ((lane >> 3) & 1);
-          slots[(wave * F + gid) * 8 + e] += v;
-        }
+        if (bb == 0) { apply_gate<0, 0, 8>(sr, si, d); accum_s<0>(sr, si, q); }
+        if (bb == 1) { apply_gate<1, 0, 8>(sr, si, d); accum_s<1>(sr, si, q); }
+        if (bb == 2) { apply_gate<2, 0, 8>(sr, si, d); accum_s<2>(sr, si, q); }
+        const float v4[4] = {q[0] + q[3], q[1] + q[4], q[2] + q[5], 0.f};
+        const float v = wave_reduce_scatter4(v4);
+        if (gsrc >= 0 && (lane & 15) == 0 && lane < 48)
+          slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
       }
-      if (k > 0) exchange<N, T, 8, EXS>(sr, si, buf, rk, rk - 1, xb + k, u, pbase);
+      if (k > 0) exchange<N, T, 8, EXS>(sr, si, buf, rk, rk - 1, xb + k, u, pbase, jc);
     }
   }
 }
@@ -522,14 +554,14 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   constexpr int PLANE = T * 8;
   extern __shared__ float4 smem4[];
   float2* buf = reinterpret_cast<float2*>(smem4);
-  float* slots = reinterpret_cast<float*>(buf + EXS * PLANE);      // [WAVES][F][8]
-  float* red = slots + WAVES * a.n_fused * 8;                        // [WAVES][40]
+  float* slots = reinterpret_cast<float*>(buf + EXS * PLANE);      // [WAVES][F][kGS]
+  float* red = slots + WAVES * a.n_fused * kGS;                      // [WAVES][40]
   const int F = a.n_fused;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   if (MODE != kModeFwd) {
-    for (int i = tid; i < WAVES * F * 8; i += T) slots[i] = 0.f;
+    for (int i = tid; i < WAVES * F * kGS; i += T) slots[i] = 0.f;
   }
   __syncthreads();
   float lacc = 0.f;
@@ -538,10 +570,10 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
-  for (int i = tid; i < F * 8; i += T) {
+  for (int i = tid; i < F * kGS; i += T) {
     float s = 0.f;
-    for (int w = 0; w < WAVES; ++w) s += slots[w * F * 8 + i];
-    a.mpart[(long long)blockIdx.x * F * 8 + i] = s;
+    for (int w = 0; w < WAVES; ++w) s += slots[w * F * kGS + i];
+    a.mpart[(long long)blockIdx.x * F * kGS + i] = s;
   }
   if (MODE == kModeMaxwell) {
 #pragma unroll

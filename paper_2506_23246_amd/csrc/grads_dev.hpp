@@ -1,6 +1,10 @@
-// Parameter gradient from the reduced gate adjoint products (FP64, the final reduction stage):
-//   d L / d theta_k = sum over gate components driven by theta_k of 2 Re sum_ab (dU/dtheta)_ab M_ab,
-// with U = R_{c-1} ... R_0 the fused gate and dR/dtheta = -(i/2) P R for R = exp(-i theta P/2).
+// Parameter gradient from the reduced gate statistics (FP64, the final reduction stage).
+// A fused gate is U = R_{c-1} ... R_0 with R = exp(-i theta P / 2), so dU/dtheta_c = U (-i/2) G_c
+// with the rotated generator G_c = W^H P_c W, W = R_{c-1} ... R_0 (the components before c).
+// With lambda and psi both taken before the gate,
+//   d L / d theta_c = 2 Re <lambda_after| dU |psi> = Im <lambda|G_c|psi> = sum_k n_k S_k,
+// where G_c = n_x X + n_y Y + n_z Z and S_k = Im <lambda|sigma_k|psi> is what the adjoint sweep
+// accumulates per gate.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -10,8 +14,31 @@
 
 namespace qp {
 
+// Axis (n_x, n_y, n_z) of G_c for component ci of fused gate fu.
+__host__ __device__ inline void generator_axis(const QFused& fu, const float* __restrict__ params, int ci, double* nvec) {
+  double w[8];
+  set_identity(w);
+  for (int c = 0; c < ci; ++c) {
+    double s, co;
+    sincos(0.5 * (double)params[fu.param[c]], &s, &co);
+    left_mul_rot<double>(fu.kind[c], co, s, w);
+  }
+  double v[8];
+  for (int e = 0; e < 8; ++e) v[e] = w[e];
+  left_mul_mhalf_i_pauli<double>(fu.kind[ci], v);   // v = (-i/2) P W, so P W = 2i v
+  double pw[8];
+  for (int e = 0; e < 4; ++e) { pw[2 * e] = -2.0 * v[2 * e + 1]; pw[2 * e + 1] = 2.0 * v[2 * e]; }
+  // G00 = conj(W00) PW00 + conj(W10) PW10;  G10 = conj(W01) PW00 + conj(W11) PW10
+  const double g00r = w[0] * pw[0] + w[1] * pw[1] + w[4] * pw[4] + w[5] * pw[5];
+  const double g10r = w[2] * pw[0] + w[3] * pw[1] + w[6] * pw[4] + w[7] * pw[5];
+  const double g10i = w[2] * pw[1] - w[3] * pw[0] + w[6] * pw[5] - w[7] * pw[4];
+  nvec[0] = g10r;
+  nvec[1] = g10i;
+  nvec[2] = g00r;
+}
+
 __device__ inline double param_grad_one(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
-                                        const double* __restrict__ m64, int k) {
+                                        const double* __restrict__ s64, int k) {
   const char* pb = reinterpret_cast<const char*>(plan);
   const QFused* fused = reinterpret_cast<const QFused*>(pb + plan->off_fused);
   const int* ptr = reinterpret_cast<const int*>(pb + plan->off_csr_ptr);
@@ -19,19 +46,10 @@ __device__ inline double param_grad_one(const QPlanDev* __restrict__ plan, const
   double gsum = 0.0;
   for (int e = ptr[k]; e < ptr[k + 1]; ++e) {
     const int fi = idx[e] >> 2, ci = idx[e] & 3;
-    const QFused& fu = fused[fi];
-    double u[8];
-    set_identity(u);
-    for (int c = 0; c < fu.ncomp; ++c) {
-      double s, co;
-      sincos(0.5 * (double)params[fu.param[c]], &s, &co);
-      left_mul_rot<double>(fu.kind[c], co, s, u);
-      if (c == ci) left_mul_mhalf_i_pauli<double>(fu.kind[c], u);
-    }
-    const double* M = m64 + fi * 8;
-    double re = 0.0;
-    for (int ab = 0; ab < 4; ++ab) re += u[2 * ab] * M[2 * ab] - u[2 * ab + 1] * M[2 * ab + 1];
-    gsum += 2.0 * re;
+    double nv[3];
+    generator_axis(fused[fi], params, ci, nv);
+    const double* S = s64 + fi * kGS;
+    gsum += nv[0] * S[0] + nv[1] * S[1] + nv[2] * S[2];
   }
   return gsum;
 }

@@ -17,6 +17,9 @@ constexpr int kMaxQubitsPlain = 14;
 constexpr int kMaxOut = 8;
 constexpr int kMaxTerms = 32;      // sign terms of one entangler stage
 constexpr int kRegBits = 3;        // 8 amplitudes per thread per statevector
+// Per fused gate the adjoint sweep accumulates S_k = Im <lambda|sigma_k|psi> (k = x, y, z) over
+// all points and statevector pairs, stored as kGS floats/doubles per gate (the last unused).
+constexpr int kGS = 4;
 
 struct alignas(16) QRound {
   int32_t gate[3];    // fused-gate id applied on register bit b (-1: none)

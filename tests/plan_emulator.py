@@ -136,7 +136,9 @@ def _apply(regs, svs, bit, U):
 
 
 def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
-    """One point: returns f [m], g [m,3] and (if seeds given) M [F,2,2] contributions."""
+    """One point: returns f [m], g [m,3] and (if seeds given) the per-gate adjoint products:
+    M [F,2,2] (lambda after the gate, psi before it) and S [F,3] = Im <lambda|sigma_k|psi> with
+    both taken before the gate (k = x, y, z), the statistic the kernel accumulates."""
     h = plan["h"]
     n, m, R = int(h["n"]), int(h["n_out"]), int(h["n_rounds"])
     TP = 1 << (n - 3)
@@ -182,13 +184,14 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
         for cc in range(3):
             gg[i, cc] = 2 * np.sum(z[i] * np.real(np.conj(psi) * regs[1 + cc]))
     if seeds_g is None:
-        return f, gg, None
+        return f, gg, None, None
     Df = sum(seeds_f[i] * z[i] for i in range(m)) if seeds_f is not None else 0.0
     D = [sum(seeds_g[i, cc] * z[i] for i in range(m)) for cc in range(3)]
     regs[4] = Df * regs[0] + D[0] * regs[1] + D[1] * regs[2] + D[2] * regs[3]
     for cc in range(3):
         regs[5 + cc] = D[cc] * regs[0]
     M = np.zeros((len(fused), 2, 2), complex)
+    S = np.zeros((len(fused), 3))
     for k in range(R - 1, -1, -1):
         for b in (2, 1, 0):
             g = int(rounds[k]["gate"][b])
@@ -208,9 +211,19 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
                     M[g, 1, 0] += np.sum(np.conj(x1) * y0)
                     M[g, 1, 1] += np.sum(np.conj(x1) * y1)
             _apply(regs, slice(4, 8), b, Ud)
+            for r in range(8):
+                if r & (1 << b):
+                    continue
+                r1 = r | (1 << b)
+                for sv in range(4):
+                    x0, x1 = regs[4 + sv, :, r], regs[4 + sv, :, r1]
+                    y0, y1 = regs[sv, :, r], regs[sv, :, r1]
+                    S[g, 0] += np.sum(np.imag(np.conj(x0) * y1 + np.conj(x1) * y0))
+                    S[g, 1] += np.sum(np.real(np.conj(x1) * y0 - np.conj(x0) * y1))
+                    S[g, 2] += np.sum(np.imag(np.conj(x0) * y0 - np.conj(x1) * y1))
         if k > 0:
             regs = _exchange(regs, rounds[k], rounds[k - 1], xb[k], n, TP)
-    return f, gg, M
+    return f, gg, M, S
 
 
 def grads_from_m(plan, params, M):
@@ -229,4 +242,24 @@ def grads_from_m(plan, params, M):
                     Rm = -0.5j * P[int(f["kind"][c])] @ Rm
                 U = Rm @ U
             out[k] += 2 * np.real(np.sum(U * M[fi]))
+    return out
+
+
+def grads_from_s(plan, params, S):
+    """d L / d theta_k = sum over components c driven by theta_k of n(c) . S_gate, where
+    n(c) is the axis of G_c = W^H P_c W, W the product of the gate's components before c."""
+    K = int(plan["h"]["n_params"])
+    out = np.zeros(K)
+    P = {0: np.array([[0, 1], [1, 0]]), 1: np.array([[0, -1j], [1j, 0]]), 2: np.diag([1, -1])}
+    paulis = [P[0], P[1], P[2]]
+    for k in range(K):
+        for e in range(int(plan["csr_ptr"][k]), int(plan["csr_ptr"][k + 1])):
+            fi, ci = int(plan["csr_idx"][e]) >> 2, int(plan["csr_idx"][e]) & 3
+            f = plan["fused"][fi]
+            Wm = np.eye(2, dtype=complex)
+            for c in range(ci):
+                Wm = _rot(int(f["kind"][c]), float(params[int(f["param"][c])])) @ Wm
+            G = Wm.conj().T @ P[int(f["kind"][ci])] @ Wm
+            nvec = [0.5 * np.real(np.trace(sk @ G)) for sk in paulis]
+            out[k] += float(np.dot(nvec, S[fi]))
     return out

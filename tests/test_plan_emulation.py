@@ -15,23 +15,25 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not bui
 
 
 def _run(circ, params, pts, seeds=True):
-    from tests.plan_emulator import emulate_point, grads_from_m, plan_image
+    from tests.plan_emulator import emulate_point, grads_from_m, grads_from_s, plan_image
     plan = plan_image(circ)
     theta, J = O.encoding_angles(circ, pts)
     f, g = O.simulate(circ, params, pts)
     Wg = O.maxwell_seeds(g, pts, W.MaxwellDesc()) if seeds else None
-    M = 0
+    M = S = 0
     for p in range(len(pts)):
-        fe, ge, Mp = emulate_point(plan, params, theta[p], J[p], circ.enc.gate == W.ENC_RX,
+        fe, ge, Mp, Sp = emulate_point(plan, params, theta[p], J[p], circ.enc.gate == W.ENC_RX,
                                    None, Wg[p] if seeds else None)
         np.testing.assert_allclose(fe, f[p], atol=1e-12)
         np.testing.assert_allclose(ge, g[p], atol=1e-11)
         if seeds:
             M = M + Mp
+            S = S + Sp
     if seeds:
-        grad = grads_from_m(plan, params, M)
         exp = O.grad_reverse(circ, params, pts, None, Wg)
-        np.testing.assert_allclose(grad, exp, atol=1e-11)
+        np.testing.assert_allclose(grads_from_m(plan, params, M), exp, atol=1e-11)
+        # the kernel's statistic: Pauli components with the rotated generator axes
+        np.testing.assert_allclose(grads_from_s(plan, params, S), exp, atol=1e-11)
 
 
 @pytest.mark.parametrize("k", [0, 1, 2])
