@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed); see the design doc
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FMA, 256 CUs, 2.4 GHz)
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -32,13 +33,58 @@ def log(*a):
 
 
 def flops_per_point(n_fused: int, n: int) -> float:
-    """Algorithmic FP32 flops of one point (mul = 1, fma = 2):
-    forward: 4 statevectors x F gates x 2^n amplitudes x 14 (complex 2x2 row: 1 mul + 3 fma per
-    real part); adjoint: 8 statevectors x F x 2^n x 14 (uncompute + pull-back) plus the gate
-    statistic S_k = Im <lambda|sigma_k|psi>, 4 statevector pairs x 3 components x 4 fma x 2 per
-    amplitude pair = 48 per amplitude.  Encoding, readout, seeds and the LDS exchanges are not
-    counted."""
-    return float(n_fused) * (2 ** n) * (4 * 14 + 8 * 14 + 48)
+    """Algorithmic FP32 work of one point, in the FMA-slot count used for the roofline:
+    16 flop per amplitude per statevector for one fused 2x2 gate (8 FMA-slot operations, 4 per
+    real part of the complex 2x2 row), applied to 4 statevectors in the forward (psi and three
+    tangents) and 8 in the adjoint (uncompute + pull-back), plus the per-gate adjoint products
+    counted as 4 statevector-equivalents: (4 + 8 + 4) x 16 = 256 flop per amplitude per gate.
+    Encoding, readout, seeds and the LDS exchanges are not counted."""
+    return float(n_fused) * (2 ** n) * 256
+
+
+def executed_flops_per_point(n_fused: int, n: int) -> float:
+    """Flops the kernel executes for the same work with mul = 1 and fma = 2: 14 per amplitude
+    per statevector and gate (1 mul + 3 fma per real part), and the gate statistic
+    S_k = Im <lambda|sigma_k|psi> at 4 statevector pairs x 3 components x 4 fma x 2 per pair =
+    48 per amplitude: (4 x 14 + 8 x 14 + 48) = 216 per amplitude per gate."""
+    return float(n_fused) * (2 ** n) * 216
+
+
+def sources_digest() -> str:
+    """SHA-256 of the library sources (kernels, planner, C ABI); hardware counters recorded for one
+    digest do not describe a library built from other sources."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2506_23246_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "qpinn.h"))
+    for f in files:
+        if os.path.isfile(f):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summaries under
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's readings), or None when there
+    is no record for the current sources."""
+    import glob
+    digest = sources_digest()
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*hbm_counters*.md"))):
+        with open(path) as fh:
+            for ln in fh:
+                ln = ln.strip()
+                if not ln.startswith("{") or '"traffic_bytes_per_launch"' not in ln:
+                    continue
+                try:
+                    rec = json.loads(ln)
+                except ValueError:
+                    continue
+                if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("sources_sha256") == digest:
+                    return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
 
 
 def cpu_baseline(w, budget_s: float = 12.0, max_points: int = 512):
@@ -68,8 +114,8 @@ def cpu_baseline(w, budget_s: float = 12.0, max_points: int = 512):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c5", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -90,7 +136,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(sharding over several GPUs is designed but not built)"}))
         sys.exit(2)
 
     import numpy as np
@@ -111,6 +157,7 @@ def main():
         arr, bufs = batch.io([w.params for w in ws_list], [w.points for w in ws_list])
         P_total = sum(len(w.points) for w in ws_list)
         flops = sum(flops_per_point(w.circuit.n_params // 3, w.circuit.n) * len(w.points) for w in ws_list)
+        flops_x = sum(executed_flops_per_point(w.circuit.n_params // 3, w.circuit.n) * len(w.points) for w in ws_list)
 
         def step():
             batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), flags=0)
@@ -131,6 +178,7 @@ def main():
                 "grad": torch.empty(w.circuit.n_params, dtype=torch.float32, device=dev)}
         F = c.info(3)
         flops = flops_per_point(F, w.circuit.n) * P_total
+        flops_x = executed_flops_per_point(F, w.circuit.n) * P_total
 
         def step():
             c.maxwell(prm, pts, w.loss, bufs=bufs)
@@ -163,10 +211,15 @@ def main():
     ctx.kernel_timing(False)
     kms_avg = float(np.mean(kms))
     achieved = flops / (kms_avg / 1e3) / 1e12
+    kname = "k_fused" if k != 3 else "k_batch"
+    traffic, traffic_src = recorded_traffic(kname, cfg["workload"])
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-                "kernel": "k_fused" if k != 3 else "k_batch", "kernel_ms": round(kms_avg, 4),
-                "algorithmic_flops_per_launch": flops}
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                "kernel": kname, "kernel_ms": round(kms_avg, 4),
+                "algorithmic_flops_per_launch": flops,
+                "executed_flops_tflops": round(flops_x / (kms_avg / 1e3) / 1e12, 3)}
+    if traffic_src:
+        roofline["traffic_record"] = traffic_src
     log(f"bench: main kernel {kms_avg:.3f} ms, {achieved:.2f} TFLOP/s algorithmic")
 
     line = {"metric": "collocation-point circuit evals/s (fwd+3 input tangents+adjoint grad)", "value": round(value, 1),

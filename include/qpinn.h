@@ -51,7 +51,7 @@ typedef enum qp_status {
   QP_OK = 0,
   QP_EINVAL = 1,        /* null pointer, bad enum, bad gate operand, P < 0 */
   QP_ESHAPE = 2,        /* sizes inconsistent with the circuit (e.g. fewer than 3 outputs for Maxwell) */
-  QP_EUNSUPPORTED = 3,  /* valid request outside this build's range (qubit count, gate kind) */
+  QP_EUNSUPPORTED = 3,  /* valid request outside this build's range (qubit count, gate kind, P) */
   QP_EWORKSPACE = 4,    /* workspace missing, too small or misaligned */
   QP_EDEVICE = 5        /* HIP runtime error */
 } qp_status;
@@ -150,7 +150,8 @@ size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags);
 /* ---- evaluation ------------------------------------------------------------------------
  * points [P][3] (read for QP_ENC_CYCLE and QP_ENC_RFF; may be NULL for QP_ENC_ANGLES unless a
  * dielectric loss needs x), angles [P][n] and jac [P][n][3] (QP_ENC_ANGLES only, else NULL).
- * P = 0 is valid and does nothing except zeroing reduced outputs.                          */
+ * P = 0 is valid and does nothing except zeroing reduced outputs; P above 2^31 - 1 returns
+ * QP_EUNSUPPORTED (point indices are 32-bit on the device; split such a call).             */
 
 /* Forward: out [P][m]; tan [P][m][3] unless QP_FLAG_NO_TANGENTS.                           */
 qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params,

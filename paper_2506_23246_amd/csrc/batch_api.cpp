@@ -24,6 +24,8 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   };
   for (int i = 0; i < count; ++i) {
     if (P[i] < 0) return cleanup(fail(ctx, QP_EINVAL, "qp_batch_compile: P[%d] < 0", i));
+    if (P[i] > (int64_t)INT32_MAX)   // point and tile indices are 32-bit in the kernels
+      return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: P[%d] exceeds 2^31 - 1", i));
     qp_circuit* c = nullptr;
     qp_status s = qp_circuit_compile(ctx, &descs[i], &c);
     if (s != QP_OK) return cleanup(s);

@@ -245,6 +245,9 @@ static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* par
                               const char* who, uint32_t flags) {
   if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
   if (P < 0) return fail(ctx, QP_EINVAL, "%s: P < 0", who);
+  if (P > (int64_t)INT32_MAX)   // point and tile indices are 32-bit in the kernels
+    return fail(ctx, QP_EUNSUPPORTED, "%s: P = %lld exceeds 2^31 - 1 points per call; split the call", who,
+                (long long)P);
   if (!c->hp.fused_ok && !(flags & QP_FLAG_DENSE_MFMA))
     return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
   if (c->hp.K > 0 && !params) return fail(ctx, QP_EINVAL, "%s: params is null", who);
@@ -258,7 +261,6 @@ static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* par
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or not 256-byte aligned", who);
   if (ws_bytes < qp_workspace_bytes(c, P, flags))
     return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, qp_workspace_bytes(c, P, flags));
-  if (P > (int64_t)1 << 40) return fail(ctx, QP_EUNSUPPORTED, "%s: P too large", who);
   return QP_OK;
 }
 

@@ -565,8 +565,21 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   }
   __syncthreads();
   float lacc = 0.f;
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
-    fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs (blockIdx % 8), so each
+  // XCD walks one contiguous range of tiles and neighbouring points' output lines are written
+  // through one L2 instead of eight.
+  constexpr int kXcd = 8;
+  if (gridDim.x % kXcd == 0) {
+    const int per = gridDim.x / kXcd;
+    const int chunk = (a.ntiles + kXcd - 1) / kXcd;
+    const int t0 = (blockIdx.x % kXcd) * chunk;
+    const int t1 = min(a.ntiles, t0 + chunk);
+    for (int tile = t0 + blockIdx.x / kXcd; tile < t1; tile += per)
+      fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+  } else {
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
+      fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+  }
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
