@@ -139,6 +139,12 @@ void qp_circuit_destroy(qp_circuit* c);
  *       8 LDS exchange planes, 9 persistent workgroups per CU, 10 dense 2^5 blocks        */
 int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
 
+/* Launch shape of the fused kernel for this circuit (what the autotuner sets): exchange_planes
+ * 4 = software-pipelined exchanges over two plane pairs, 2 = one plane pair, unpipelined;
+ * wg_per_cu = persistent workgroups per CU.  The choice changes speed, not results beyond
+ * rounding order.  QP_EINVAL for other values or a shape whose LDS does not fit a CU.       */
+qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_planes, int32_t wg_per_cu);
+
 /* Host-only introspection: builds the execution plan of `desc` without a device and copies its
  * device image (header, rounds, exchange descriptors, fused gates, gradient map) into host_buf
  * (capacity cap bytes); *bytes receives the image size.  QP_EWORKSPACE if cap is too small.  */

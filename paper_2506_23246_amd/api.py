@@ -128,6 +128,9 @@ class Circuit:
     def info(self, what: int) -> int:
         return int(L.qp_circuit_info(self.h, what))
 
+    def set_launch(self, exchange_planes: int, wg_per_cu: int) -> None:
+        L.check(L.qp_circuit_set_launch(self.h, int(exchange_planes), int(wg_per_cu)), self.ctx.h)
+
     def workspace(self, P: int, flags: int = 0):
         nb = int(L.qp_workspace_bytes(self.h, int(P), int(flags) & L.QP_FLAG_DENSE_MFMA))
         key = ("ws", nb)

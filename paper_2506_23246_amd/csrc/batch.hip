@@ -25,8 +25,9 @@ __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGa
   const BatchGate G = gates[g];
   const BatchCirc& C = circs[G.circ];
   if (G.idx == C.F) {   // identity entry used for absent gates of a round
-    float* o = const_cast<float*>(C.a.gtab) + G.idx * 8;
-    for (int e = 0; e < 8; ++e) o[e] = (e == 0 || e == 6) ? 1.f : 0.f;
+    float u[8];
+    set_identity(u);
+    store_gate_entry(const_cast<float*>(C.a.gtab) + G.idx * kGT, u);
     return;
   }
   const QPlanDev* plan = C.a.plan;
@@ -38,8 +39,7 @@ __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGa
     sincos(0.5 * (double)C.params[fu->param[c]], &s, &co);
     left_mul_rot<double>(fu->kind[c], co, s, u);
   }
-  float* o = const_cast<float*>(C.a.gtab) + G.idx * 8;
-  for (int e = 0; e < 8; ++e) o[e] = (float)u[e];
+  store_gate_entry(const_cast<float*>(C.a.gtab) + G.idx * kGT, u);
 }
 
 // Dielectric point counts per circuit (one workgroup per circuit).
@@ -72,9 +72,10 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ 
                                                float* __restrict__ lpart) {
   constexpr int WAVES = kBT / 64;
   constexpr int PLANE = kBT * 8;
+  __shared__ float4 planes[kBEXS * PLANE / 2];   // exchange planes (static: one-XOR addressing)
   extern __shared__ float4 smem4[];
-  float2* buf = reinterpret_cast<float2*>(smem4);
-  float* slots = reinterpret_cast<float*>(buf + kBEXS * PLANE);
+  float2* buf = reinterpret_cast<float2*>(planes);
+  float* slots = reinterpret_cast<float*>(smem4);
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (;;) {
@@ -151,13 +152,17 @@ __global__ void k_batch_grads(const BatchCirc* __restrict__ circs, const BatchGa
   C.d_params[g.idx] = (float)param_grad_one(C.a.plan, C.params, C.m64, g.idx);
 }
 
-size_t batch_lds_bytes(int max_fused) {
-  return (size_t)kBEXS * kBT * 8 * sizeof(float2) + (size_t)(kBT / 64) * max_fused * kGS * sizeof(float) +
-         (size_t)(kBT / 64) * 40 * sizeof(float);
+// Dynamic LDS of k_batch: per-wave gate statistics and readout scratch.
+static size_t batch_dyn_lds_bytes(int max_fused) {
+  return (size_t)(kBT / 64) * max_fused * kGS * sizeof(float) + (size_t)(kBT / 64) * 40 * sizeof(float);
+}
+
+size_t batch_lds_bytes(int max_fused) {   // static exchange planes + dynamic part
+  return (size_t)kBEXS * kBT * 8 * sizeof(float2) + batch_dyn_lds_bytes(max_fused);
 }
 
 hipError_t batch_prepare(int max_fused) {
-  const size_t lds = batch_lds_bytes(max_fused);
+  const size_t lds = batch_dyn_lds_bytes(max_fused);
   if (lds <= 64 * 1024) return hipSuccess;
   return hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
@@ -172,7 +177,7 @@ hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* item
   if (count_needed) hipLaunchKernelGGL(k_batch_counts, dim3(ncirc), dim3(256), 0, st, circs);
   if (ev0) hipEventRecord(ev0, st);
   if (grid > 0 && nitems > 0)
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), batch_lds_bytes(max_fused), st, circs, items, nitems,
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), batch_dyn_lds_bytes(max_fused), st, circs, items, nitems,
                        counter, mpart, lpart);
   if (ev1) hipEventRecord(ev1, st);
   hipLaunchKernelGGL(k_batch_reduce, dim3((ncols + 3) / 4), dim3(256), 0, st, circs, cols, ncols, mpart, lpart);

@@ -76,7 +76,7 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   L.gtab_c.resize(count); L.counts_c.resize(count); L.m64_c.resize(count); L.mpart_c.resize(count);
   for (int i = 0; i < count; ++i) {
     const int F = (int)b->circs[i]->hp.fused.size();
-    L.gtab_c[i] = off; off = al(off + sizeof(float) * 8 * (F + 1));
+    L.gtab_c[i] = off; off = al(off + sizeof(float) * kGT * (F + 1));
     L.counts_c[i] = off; off = al(off + 2 * sizeof(int));
     L.m64_c[i] = off; off = al(off + sizeof(double) * kGS * std::max(F, 1));
     L.mpart_c[i] = mp;

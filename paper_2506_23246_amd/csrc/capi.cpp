@@ -137,6 +137,20 @@ extern "C" qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* d, q
   return QP_OK;
 }
 
+extern "C" qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_planes, int32_t wg_per_cu) {
+  if (!c) return QP_EINVAL;
+  if (!c->hp.fused_ok) return fail(c->ctx, QP_EUNSUPPORTED, "qp_circuit_set_launch: %s", c->hp.fused_reason.c_str());
+  if (exchange_planes != 2 && exchange_planes != 4)
+    return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: exchange_planes must be 2 or 4");
+  const int max_wg = fused_threads(c->hp.n) == 512 ? 1 : 2;   // register file: 2 waves per SIMD
+  const size_t lds = fused_lds_bytes(c->hp.n, exchange_planes, (int)c->hp.fused.size());
+  if (wg_per_cu < 1 || wg_per_cu > max_wg || lds * (size_t)wg_per_cu > 160 * 1024)
+    return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: %d workgroups of %zu LDS bytes do not fit a CU", wg_per_cu, lds);
+  c->exs = exchange_planes;
+  c->wg_per_cu = wg_per_cu;
+  return QP_OK;
+}
+
 extern "C" qp_status qp_plan_image(const qp_circuit_desc* d, void* host_buf, size_t cap, size_t* bytes) {
   if (!d || !bytes) return QP_EINVAL;
   HostPlan hp;
@@ -207,7 +221,7 @@ WsLayout qp::fused_layout(const qp_circuit* c, int64_t P, int grid_cap) {
   WsLayout L{};
   const int F = (int)c->hp.fused.size();
   size_t off = 0;
-  L.gtab = off; off = al(off + sizeof(float) * 8 * (F + 1));   // + identity entry
+  L.gtab = off; off = al(off + sizeof(float) * kGT * (F + 1));   // + identity entry
   L.counts = off; off = al(off + 2 * sizeof(int));
   if (c->hp.enc_kind == QP_ENC_RFF) {
     L.angles = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n);

@@ -58,7 +58,7 @@ __global__ void k_gate_table64(const QPlanDev* __restrict__ plan, const float* _
   if (f == plan->n_fused) {   // identity entry used for absent gates of a round
     float u[8];
     set_identity(u);
-    for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
+    store_gate_entry(gtab + f * kGT, u);
     return;
   }
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
@@ -69,7 +69,7 @@ __global__ void k_gate_table64(const QPlanDev* __restrict__ plan, const float* _
     sincos(0.5 * (double)params[fu->param[c]], &s, &co);
     left_mul_rot<double>(fu->kind[c], co, s, u);
   }
-  for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = (float)u[e];
+  store_gate_entry(gtab + f * kGT, u);
 }
 
 __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
@@ -79,7 +79,7 @@ __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __r
   if (f == plan->n_fused) {   // identity entry used for absent gates of a round
     float u[8];
     set_identity(u);
-    for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
+    store_gate_entry(gtab + f * kGT, u);
     return;
   }
   const QFused* fu = reinterpret_cast<const QFused*>(reinterpret_cast<const char*>(plan) + plan->off_fused) + f;
@@ -90,7 +90,7 @@ __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __r
     sincosf(0.5f * params[fu->param[c]], &s, &co);
     left_mul_rot<float>(fu->kind[c], co, s, u);
   }
-  for (int e = 0; e < 8; ++e) gtab[f * 8 + e] = u[e];
+  store_gate_entry(gtab + f * kGT, u);
 }
 
 // Random-Fourier-feature angles: phi = [cos(Bp); sin(Bp)], theta = W phi, J = W dphi/dp.

@@ -12,7 +12,7 @@ namespace qp {
 
 struct FusedArgs {
   const QPlanDev* plan;
-  const float* gtab;      // [F][8] fused gate matrices
+  const float* gtab;      // [F + 1][kGT] fused gate matrices U, U^H (entry F: identity)
   const float* points;    // [P][3]
   const float* angles;    // [P][n]   (angle-given or RFF encodings)
   const float* jac;       // [P][n][3]

@@ -17,13 +17,7 @@ template <typename T> __device__ __forceinline__ CP<T> to_const(const T* p) { re
 
 __device__ __forceinline__ uint32_t parity(uint32_t x) { return __popc(x) & 1u; }
 
-// LDS index swizzle: XOR the low nibble with the fold of all higher nibbles (a bijection).
-__device__ __forceinline__ uint32_t swz(uint32_t idx) {
-  uint32_t h = idx >> 4;
-  h ^= h >> 4;
-  h ^= h >> 8;
-  return idx ^ (h & 15u);
-}
+__device__ __forceinline__ uint32_t swz(uint32_t idx) { return lds_swizzle(idx); }
 
 template <int N, typename TP>
 __device__ __forceinline__ uint32_t deposit_thread(uint32_t u, TP tpos) {
@@ -65,6 +59,28 @@ __device__ __forceinline__ void dagger(const float* u, float* d) {
   d[2] = u[4]; d[3] = -u[5];   // (0,1) <- conj u10
   d[4] = u[2]; d[5] = -u[3];   // (1,0) <- conj u01
   d[6] = u[6]; d[7] = -u[7];   // (1,1) <- conj u11
+}
+
+// Gate statistic of one statevector pair (lambda-family 4 + C, psi-family C), both taken
+// before the gate, for the register pairs on bit B:
+//   S_x += Im(conj(x0) y1) + Im(conj(x1) y0)
+//   S_y += Re(conj(x1) y0) - Re(conj(x0) y1)
+//   S_z += Im(conj(x0) y0) - Im(conj(x1) y1)
+template <int B, int C>
+__device__ __forceinline__ void accum_s1(const float (&sr)[8][8], const float (&si)[8][8], float* m) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << B)) continue;
+    const int r1 = r | (1 << B);
+    const float x0r = sr[4 + C][r], x0i = si[4 + C][r], x1r = sr[4 + C][r1], x1i = si[4 + C][r1];
+    const float y0r = sr[C][r], y0i = si[C][r], y1r = sr[C][r1], y1i = si[C][r1];
+    m[0] = fmaf(x0r, y1i, m[0]); m[0] = fmaf(-x0i, y1r, m[0]);
+    m[0] = fmaf(x1r, y0i, m[0]); m[0] = fmaf(-x1i, y0r, m[0]);
+    m[1] = fmaf(x1r, y0r, m[1]); m[1] = fmaf(x1i, y0i, m[1]);
+    m[1] = fmaf(-x0r, y1r, m[1]); m[1] = fmaf(-x0i, y1i, m[1]);
+    m[2] = fmaf(x0r, y0i, m[2]); m[2] = fmaf(-x0i, y0r, m[2]);
+    m[2] = fmaf(-x1r, y1i, m[2]); m[2] = fmaf(x1i, y1r, m[2]);
+  }
 }
 
 template <int B>
@@ -121,27 +137,30 @@ __device__ __forceinline__ float wave_reduce_scatter4(const float* v) {
 }
 
 // ---- register exchange through LDS ----------------------------------------------------------
-// Writes statevectors [0, NSV) in the writer mapping `wr`, reads them back in mapping `rd`
-// through the exchange descriptor X (index map and sign), in groups of EXS planes.
-// jc: on entry the thread part of the state index in mapping `wr` (deposit of u), on exit the
-// same in mapping `rd`, so consecutive exchanges deposit the thread bits once each.
-// Address arithmetic: pbase is a multiple of 2^N and every index below 2^N, so pbase + x equals
-// pbase ^ x; swz is linear over GF(2), so swz(pbase ^ j ^ o) = swz(pbase ^ j) ^ swz(o).  The
-// register offsets o are uniform across the workgroup, leaving one per-lane XOR per access.
-template <int N, int T, int NSV, int EXS>
-__device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase,
-                                         uint32_t& jc) {
-  constexpr int PLANE = T * 8;
-  const uint32_t jw = jc;
-  const uint32_t w0 = wr->tpos[0], w1 = wr->tpos[1], w2 = wr->tpos[2];
+// An exchange moves the statevectors from the writer round's mapping to the reader round's
+// mapping: each thread writes its registers at their logical indices (swizzled) and reads back
+// the amplitudes its registers hold in the new mapping, through the descriptor X (index map A
+// and sign (-1)^Q).  Address arithmetic: pbase is a multiple of 2^N and every index is below
+// 2^N, so pbase + x equals pbase ^ x; the swizzle is linear over GF(2), so
+// swz(pbase ^ j ^ o) = swz(pbase ^ j) ^ swz(o), and the planner stores 8 swz(o) (byte offsets of
+// complex64 entries) for the eight register offsets (woff for the writer, roff for the reader).
+// Per exchange a lane needs three words: its writer and reader byte bases and the sign bits of
+// its eight reads; each access then costs one XOR.
+struct XLane {
+  uint32_t wb, rb, sgn;
+};
+
+// jc: on entry the thread part of the logical index in the writer mapping (deposit of u), on
+// exit the same in the reader mapping rd.
+template <int N>
+__device__ __forceinline__ XLane xsetup(CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase, uint32_t& jc) {
+  XLane x;
+  x.wb = swz(pbase ^ jc) * 8u;
   const uint32_t jn = deposit_thread<N>(u, rd->tpos);
   jc = jn;
-  uint32_t sb;
-  uint32_t sgn = 0;   // bit r set: negate amplitude r
-  if (X->identity) {
-    sb = jn;
-  } else {
+  uint32_t sb = jn;
+  x.sgn = 0;   // bit r set: negate amplitude r
+  if (!X->identity) {
     // sb = A jn with jn = sum of the thread bits placed at rd->tpos[k]: column A e_tpos[k] is
     // acol[tpos[k]], so only the N - 3 thread bits are visited.
     sb = 0;
@@ -163,53 +182,215 @@ __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], f
       const uint32_t b1 = parity((pu & X->ve[1]) ^ (X->ue[1] & pv));
       const uint32_t b2 = parity((pu & X->ve[2]) ^ (X->ue[2] & pv));
       const uint32_t qs = X->qsign_r;
+      uint32_t sg = 0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        uint32_t s = q0 ^ ((qs >> r) & 1u);
-        if (r & 1) s ^= b0;
-        if (r & 2) s ^= b1;
-        if (r & 4) s ^= b2;
-        sgn |= s << r;
+        uint32_t sr_ = q0 ^ ((qs >> r) & 1u);
+        if (r & 1) sr_ ^= b0;
+        if (r & 2) sr_ ^= b1;
+        if (r & 4) sr_ ^= b2;
+        sg |= sr_ << r;
       }
+      x.sgn = sg;
     }
   }
-  const uint32_t wb = swz(pbase ^ jw), rb = swz(pbase ^ sb);
-  uint32_t wo[8], ro[8];
+  x.rb = swz(pbase ^ sb) * 8u;
+  return x;
+}
+
+// Writes statevectors SV0 and SV1 to LDS planes PL and PL + 1 in the writer mapping wr.
+template <int T, int SV0, int SV1, int PL>
+__device__ __forceinline__ void xwrite(const float (&sr)[8][8], const float (&si)[8][8], float2* __restrict__ buf,
+                                       CP<QRound> wr, uint32_t wb) {
+  constexpr int PLANE = T * 8 * 8;   // bytes
+  char* b = reinterpret_cast<char*>(buf);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    wo[r] = swz(reg_off(r, w0, w1, w2));
-    ro[r] = swz(X->identity ? reg_off(r, rd->tpos[0], rd->tpos[1], rd->tpos[2]) : X->src_r[r]);
+    const uint32_t o = wb ^ wr->woff[r];
+    *reinterpret_cast<float2*>(b + PL * PLANE + o) = make_float2(sr[SV0][r], si[SV0][r]);
+    *reinterpret_cast<float2*>(b + (PL + 1) * PLANE + o) = make_float2(sr[SV1][r], si[SV1][r]);
   }
+}
+
+// Reads statevectors SV0 and SV1 back from planes PL, PL + 1 through the descriptor X.
+template <int T, int SV0, int SV1, int PL>
+__device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], const float2* __restrict__ buf,
+                                      CP<QXchg> X, uint32_t rb, uint32_t sgn) {
+  constexpr int PLANE = T * 8 * 8;   // bytes
+  const char* b = reinterpret_cast<const char*>(buf);
+  if (X->nterms == 0) {   // no sign terms (identity or a CNOT stage): uniform fast path
 #pragma unroll
-  for (int g = 0; g < NSV; g += EXS) {
-#pragma unroll
-    for (int s = 0; s < EXS; ++s)
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        buf[s * PLANE + (wb ^ wo[r])] = make_float2(sr[g + s][r], si[g + s][r]);
-    __syncthreads();
-    if (sgn == 0u) {   // uniform when the stage has no sign terms (e.g. a CNOT ring)
-#pragma unroll
-      for (int s = 0; s < EXS; ++s)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const float2 v = buf[s * PLANE + (rb ^ ro[r])];
-          sr[g + s][r] = v.x;
-          si[g + s][r] = v.y;
-        }
-    } else {
-#pragma unroll
-      for (int s = 0; s < EXS; ++s)
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const float2 v = buf[s * PLANE + (rb ^ ro[r])];
-          const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
-          sr[g + s][r] = __uint_as_float(__float_as_uint(v.x) ^ flip);
-          si[g + s][r] = __uint_as_float(__float_as_uint(v.y) ^ flip);
-        }
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t o = rb ^ X->roff[r];
+      const float2 v0 = *reinterpret_cast<const float2*>(b + PL * PLANE + o);
+      const float2 v1 = *reinterpret_cast<const float2*>(b + (PL + 1) * PLANE + o);
+      sr[SV0][r] = v0.x; si[SV0][r] = v0.y;
+      sr[SV1][r] = v1.x; si[SV1][r] = v1.y;
     }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t o = rb ^ X->roff[r];
+      const float2 v0 = *reinterpret_cast<const float2*>(b + PL * PLANE + o);
+      const float2 v1 = *reinterpret_cast<const float2*>(b + (PL + 1) * PLANE + o);
+      const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
+      sr[SV0][r] = __uint_as_float(__float_as_uint(v0.x) ^ flip);
+      si[SV0][r] = __uint_as_float(__float_as_uint(v0.y) ^ flip);
+      sr[SV1][r] = __uint_as_float(__float_as_uint(v1.x) ^ flip);
+      si[SV1][r] = __uint_as_float(__float_as_uint(v1.y) ^ flip);
+    }
+  }
+}
+
+// Unpipelined exchange of statevectors [0, NSV) in groups of EXS planes (used when the LDS
+// holds only two planes per workgroup).
+template <int N, int T, int NSV, int EXS>
+__device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
+                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase,
+                                         uint32_t& jc) {
+  static_assert(EXS == 2, "pairs of planes");
+  const XLane x = xsetup<N>(rd, X, u, pbase, jc);
+#pragma unroll
+  for (int g = 0; g < NSV; g += 2) {
+    if (g == 0) xwrite<T, 0, 1, 0>(sr, si, buf, wr, x.wb);
+    if (g == 2) xwrite<T, 2, 3, 0>(sr, si, buf, wr, x.wb);
+    if (g == 4) xwrite<T, 4, 5, 0>(sr, si, buf, wr, x.wb);
+    if (g == 6) xwrite<T, 6, 7, 0>(sr, si, buf, wr, x.wb);
+    __syncthreads();
+    if (g == 0) xread<T, 0, 1, 0>(sr, si, buf, X, x.rb, x.sgn);
+    if (g == 2) xread<T, 2, 3, 0>(sr, si, buf, X, x.rb, x.sgn);
+    if (g == 4) xread<T, 4, 5, 0>(sr, si, buf, X, x.rb, x.sgn);
+    if (g == 6) xread<T, 6, 7, 0>(sr, si, buf, X, x.rb, x.sgn);
     __syncthreads();
   }
+}
+
+// Forward gates of round rk on statevectors S0, S0 + 1 (an absent gate is the identity entry F).
+template <int S0>
+__device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab, int F) {
+  float g[8];
+  const int g0 = rk->gate[0] >= 0 ? rk->gate[0] : F;
+  const int g1 = rk->gate[1] >= 0 ? rk->gate[1] : F;
+  const int g2 = rk->gate[2] >= 0 ? rk->gate[2] : F;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) g[e] = gtab[g0 * kGT + e];
+  apply_gate<0, S0, 2>(sr, si, g);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) g[e] = gtab[g1 * kGT + e];
+  apply_gate<1, S0, 2>(sr, si, g);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) g[e] = gtab[g2 * kGT + e];
+  apply_gate<2, S0, 2>(sr, si, g);
+}
+
+// Wave-reduces the round's three gate statistics and adds them to the per-wave LDS slots.
+__device__ __forceinline__ void round_stat_flush(CP<QRound> rk, float* __restrict__ slots, const float* q, int F,
+                                                 int wave, int lane) {
+#pragma unroll
+  for (int bb = 0; bb < 3; ++bb) {
+    const int gsrc = rk->gate[bb];
+    const float v4[4] = {q[3 * bb], q[3 * bb + 1], q[3 * bb + 2], 0.f};
+    const float v = wave_reduce_scatter4(v4);
+    if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+  }
+}
+
+// Adjoint gates of round rk (in reverse) on the pair (C, 4 + C): psi_C and lambda_C <- U^H, then
+// the pair's share of the three gate statistics is added to q[3 * bb + k] (per lane).
+template <int C>
+__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab, int F,
+                                          float* q) {
+#pragma unroll
+  for (int bb = 2; bb >= 0; --bb) {
+    const int gsrc = rk->gate[bb];
+    const int gid = gsrc >= 0 ? gsrc : F;
+    float d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
+    if (bb == 0) { apply_gate<0, C, 1>(sr, si, d); apply_gate<0, 4 + C, 1>(sr, si, d); accum_s1<0, C>(sr, si, q); }
+    if (bb == 1) { apply_gate<1, C, 1>(sr, si, d); apply_gate<1, 4 + C, 1>(sr, si, d); accum_s1<1, C>(sr, si, q + 3); }
+    if (bb == 2) { apply_gate<2, C, 1>(sr, si, d); apply_gate<2, 4 + C, 1>(sr, si, d); accum_s1<2, C>(sr, si, q + 6); }
+  }
+}
+
+// Adjoint gates of round rk on all four pairs, gate by gate, each gate's statistic flushed at
+// once (where no pipelining separates the pairs; keeps one gate's values live at a time).
+__device__ __forceinline__ void round_adj_all(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab,
+                                              int F, float* __restrict__ slots, int wave, int lane) {
+#pragma unroll
+  for (int bb = 2; bb >= 0; --bb) {
+    const int gsrc = rk->gate[bb];
+    const int gid = gsrc >= 0 ? gsrc : F;
+    float d[8], q6[6];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
+#pragma unroll
+    for (int e = 0; e < 6; ++e) q6[e] = 0.f;
+    if (bb == 0) { apply_gate<0, 0, 8>(sr, si, d); accum_s<0>(sr, si, q6); }
+    if (bb == 1) { apply_gate<1, 0, 8>(sr, si, d); accum_s<1>(sr, si, q6); }
+    if (bb == 2) { apply_gate<2, 0, 8>(sr, si, d); accum_s<2>(sr, si, q6); }
+    const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
+    const float v = wave_reduce_scatter4(v4);
+    if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+  }
+}
+
+
+// ---- angle encoding of one qubit ------------------------------------------------------------
+// Embedded single-qubit state e(b) (b = 0, 1) and its angle derivative d(b) for qubit q, with the
+// Jacobian d theta_q / d(t, x, y).  RY: e = (cos, sin), RX: e = (cos, -i sin), of theta/2.
+struct QEnc {
+  float e0, e1r, e1i, d0, d1r, d1i, j[3];
+};
+
+template <int N>
+__device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, const FusedArgs& a, long long pt, bool valid,
+                                             const float* p3, int q) {
+  float c, s, j0 = 0.f, j1 = 0.f, j2 = 0.f;
+  if (plan->enc_kind == QP_ENC_CYCLE) {
+    const int cc = plan->coord_of_qubit[q];
+    const float x = cc == 0 ? p3[0] : (cc == 1 ? p3[1] : p3[2]);
+    float jv;
+    const int sc = plan->enc_scale;
+    if (sc == QP_SCALE_PI) {           // theta/2 = pi x/2
+      sincospif(0.5f * x, &s, &c);
+      jv = 3.14159265358979323846f;
+    } else if (sc == QP_SCALE_BIAS) {  // theta/2 = pi (x+1)/4
+      sincospif(0.25f * (x + 1.f), &s, &c);
+      jv = 1.57079632679489661923f;
+    } else if (sc == QP_SCALE_NONE) {
+      sincosf(0.5f * x, &s, &c);
+      jv = 1.f;
+    } else {
+      const float xx = fminf(fmaxf(x, -1.f), 1.f);
+      const float th = (sc == QP_SCALE_ASIN) ? asinf(xx) + 1.57079632679489661923f : acosf(xx);
+      sincosf(0.5f * th, &s, &c);
+      const float rs = 1.f / sqrtf(fmaxf(1.f - xx * xx, 0.f));
+      jv = (sc == QP_SCALE_ASIN) ? rs : -rs;
+    }
+    j0 = cc == 0 ? jv : 0.f;
+    j1 = cc == 1 ? jv : 0.f;
+    j2 = cc == 2 ? jv : 0.f;
+  } else {   // angles given per point (QP_ENC_ANGLES, or random Fourier features formed beforehand)
+    float th = 0.f;
+    if (valid) {
+      th = a.angles[pt * N + q];
+      j0 = a.jac[(pt * N + q) * 3 + 0];
+      j1 = a.jac[(pt * N + q) * 3 + 1];
+      j2 = a.jac[(pt * N + q) * 3 + 2];
+    }
+    sincosf(0.5f * th, &s, &c);
+  }
+  QEnc E;
+  E.e0 = c;
+  E.d0 = -0.5f * s;
+  if (plan->enc_gate == QP_ENC_RY) {
+    E.e1r = s; E.e1i = 0.f; E.d1r = 0.5f * c; E.d1i = 0.f;
+  } else {   // RX|0> = (cos, -i sin)
+    E.e1r = 0.f; E.e1i = -s; E.d1r = 0.f; E.d1i = -0.5f * c;
+  }
+  E.j[0] = j0; E.j[1] = j1; E.j[2] = j2;
+  return E;
 }
 
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
@@ -251,63 +432,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     const long long pt = (long long)tile * PPW + ps;
     const bool valid = pt < a.P;
 
-    // ---------------- encoding: per-qubit embedded amplitudes and derivatives -------------
-    float e0r[N], e1r[N], e1i[N], d0r[N], d1r[N], d1i[N], jq[N][3];
-    {
-      float p3[3] = {0.f, 0.f, 0.f};
-      if (valid && a.points && plan->enc_kind != QP_ENC_ANGLES) {
-        p3[0] = a.points[pt * 3 + 0];
-        p3[1] = a.points[pt * 3 + 1];
-        p3[2] = a.points[pt * 3 + 2];
-      }
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        float c, s, j0 = 0.f, j1 = 0.f, j2 = 0.f;
-        if (plan->enc_kind == QP_ENC_CYCLE) {
-          const int cc = plan->coord_of_qubit[q];
-          const float x = cc == 0 ? p3[0] : (cc == 1 ? p3[1] : p3[2]);
-          float jv;
-          const int sc = plan->enc_scale;
-          if (sc == QP_SCALE_PI) {           // theta/2 = pi x/2
-            sincospif(0.5f * x, &s, &c);
-            jv = 3.14159265358979323846f;
-          } else if (sc == QP_SCALE_BIAS) {  // theta/2 = pi (x+1)/4
-            sincospif(0.25f * (x + 1.f), &s, &c);
-            jv = 1.57079632679489661923f;
-          } else if (sc == QP_SCALE_NONE) {
-            sincosf(0.5f * x, &s, &c);
-            jv = 1.f;
-          } else {
-            const float xx = fminf(fmaxf(x, -1.f), 1.f);
-            const float th = (sc == QP_SCALE_ASIN) ? asinf(xx) + 1.57079632679489661923f : acosf(xx);
-            sincosf(0.5f * th, &s, &c);
-            const float rs = 1.f / sqrtf(fmaxf(1.f - xx * xx, 0.f));
-            jv = (sc == QP_SCALE_ASIN) ? rs : -rs;
-          }
-          j0 = cc == 0 ? jv : 0.f;
-          j1 = cc == 1 ? jv : 0.f;
-          j2 = cc == 2 ? jv : 0.f;
-        } else {
-          float th = 0.f;
-          if (valid) {
-            th = a.angles[pt * N + q];
-            j0 = a.jac[(pt * N + q) * 3 + 0];
-            j1 = a.jac[(pt * N + q) * 3 + 1];
-            j2 = a.jac[(pt * N + q) * 3 + 2];
-          }
-          sincosf(0.5f * th, &s, &c);
-        }
-        e0r[q] = c;
-        d0r[q] = -0.5f * s;
-        if (plan->enc_gate == QP_ENC_RY) {
-          e1r[q] = s; e1i[q] = 0.f; d1r[q] = 0.5f * c; d1i[q] = 0.f;
-        } else {   // RX|0> = (cos, -i sin)
-          e1r[q] = 0.f; e1i[q] = -s; d1r[q] = 0.f; d1i[q] = -0.5f * c;
-        }
-        jq[q][0] = j0; jq[q][1] = j1; jq[q][2] = j2;
-      }
+    // ---------------- encoding and product state in round 0's mapping ---------------------
+    // Each qubit's embedded amplitudes are formed where they are used (qubit index uniform
+    // across the workgroup), so no per-qubit arrays are indexed at run time.
+    float p3[3] = {0.f, 0.f, 0.f};
+    if (valid && a.points && plan->enc_kind != QP_ENC_ANGLES) {
+      p3[0] = a.points[pt * 3 + 0];
+      p3[1] = a.points[pt * 3 + 1];
+      p3[2] = a.points[pt * 3 + 2];
     }
-    // ---------------- product state and tangent seeds in round 0's mapping ---------------
     {
       CP<QRound> r0 = rounds;
       // thread part: (P, D_c) by the product rule over the thread qubits
@@ -315,50 +448,34 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       float Dr[3] = {0.f, 0.f, 0.f}, Di[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int k = 3; k < N; ++k) {
-        const int q = N - 1 - r0->tpos[k];
+        const QEnc E = encode_qubit<N>(plan, a, pt, valid, p3, N - 1 - r0->tpos[k]);
         const bool bit = (u >> (k - 3)) & 1u;
-        float er = 0.f, ei = 0.f, dr = 0.f, di = 0.f, jj[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int qq = 0; qq < N; ++qq)
-          if (qq == q) {
-            er = bit ? e1r[qq] : e0r[qq];
-            ei = bit ? e1i[qq] : 0.f;
-            dr = bit ? d1r[qq] : d0r[qq];
-            di = bit ? d1i[qq] : 0.f;
-            jj[0] = jq[qq][0]; jj[1] = jq[qq][1]; jj[2] = jq[qq][2];
-          }
+        const float er = bit ? E.e1r : E.e0, ei = bit ? E.e1i : 0.f;
+        const float dr = bit ? E.d1r : E.d0, di = bit ? E.d1i : 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float nr = Dr[c] * er - Di[c] * ei + jj[c] * (Pr * dr - Pi * di);
-          const float ni = Dr[c] * ei + Di[c] * er + jj[c] * (Pr * di + Pi * dr);
+          const float nr = Dr[c] * er - Di[c] * ei + E.j[c] * (Pr * dr - Pi * di);
+          const float ni = Dr[c] * ei + Di[c] * er + E.j[c] * (Pr * di + Pi * dr);
           Dr[c] = nr; Di[c] = ni;
         }
         const float npr = Pr * er - Pi * ei, npi = Pr * ei + Pi * er;
         Pr = npr; Pi = npi;
       }
-      float qer[3][2], qei[3][2], qdr[3][2], qdi[3][2], qj[3][3];
+      QEnc Q[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int q = N - 1 - r0->tpos[i];
-#pragma unroll
-        for (int qq = 0; qq < N; ++qq)
-          if (qq == q) {
-            qer[i][0] = e0r[qq]; qei[i][0] = 0.f; qer[i][1] = e1r[qq]; qei[i][1] = e1i[qq];
-            qdr[i][0] = d0r[qq]; qdi[i][0] = 0.f; qdr[i][1] = d1r[qq]; qdi[i][1] = d1i[qq];
-            qj[i][0] = jq[qq][0]; qj[i][1] = jq[qq][1]; qj[i][2] = jq[qq][2];
-          }
-      }
+      for (int i = 0; i < 3; ++i) Q[i] = encode_qubit<N>(plan, a, pt, valid, p3, N - 1 - r0->tpos[i]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         float pr = Pr, pi = Pi, dr[3] = {Dr[0], Dr[1], Dr[2]}, di[3] = {Di[0], Di[1], Di[2]};
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const int b = (r >> i) & 1;
-          const float er = qer[i][b], ei = qei[i][b], ddr = qdr[i][b], ddi = qdi[i][b];
+          const bool b = (r >> i) & 1;
+          const float er = b ? Q[i].e1r : Q[i].e0, ei = b ? Q[i].e1i : 0.f;
+          const float ddr = b ? Q[i].d1r : Q[i].d0, ddi = b ? Q[i].d1i : 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float nr = dr[c] * er - di[c] * ei + qj[i][c] * (pr * ddr - pi * ddi);
-            const float ni = dr[c] * ei + di[c] * er + qj[i][c] * (pr * ddi + pi * ddr);
+            const float nr = dr[c] * er - di[c] * ei + Q[i].j[c] * (pr * ddr - pi * ddi);
+            const float ni = dr[c] * ei + di[c] * er + Q[i].j[c] * (pr * ddi + pi * ddr);
             dr[c] = nr; di[c] = ni;
           }
           const float npr = pr * er - pi * ei, npi = pr * ei + pi * er;
@@ -371,23 +488,38 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- forward rounds -------------------------------------------------------
     uint32_t jc = deposit_thread<N>(u, rounds[0].tpos);   // thread bits in the current mapping
-    for (int k = 0; k < R; ++k) {
-      CP<QRound> rk = rounds + k;
-      if (k > 0) exchange<N, T, 4, (EXS < 4 ? EXS : 4)>(sr, si, buf, rk - 1, rk, xf + k, u, pbase, jc);
-      // branch-free: an absent gate is the identity entry F of the gate table
-      float g[8];
-      const int g0 = rk->gate[0] >= 0 ? rk->gate[0] : F;
-      const int g1 = rk->gate[1] >= 0 ? rk->gate[1] : F;
-      const int g2 = rk->gate[2] >= 0 ? rk->gate[2] : F;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) g[e] = gtab[g0 * 8 + e];
-      apply_gate<0, 0, 4>(sr, si, g);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) g[e] = gtab[g1 * 8 + e];
-      apply_gate<1, 0, 4>(sr, si, g);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) g[e] = gtab[g2 * 8 + e];
-      apply_gate<2, 0, 4>(sr, si, g);
+    if constexpr (EXS == 4) {
+      // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
+      // (planes 2, 3).  Each group's LDS writes drain while the other group's gates run; every
+      // barrier separates a plane pair's reads from its next writes.
+      round_fwd<0>(sr, si, rounds, gtab, F);
+      round_fwd<2>(sr, si, rounds, gtab, F);
+      if (R > 1) {
+        XLane x = xsetup<N>(rounds + 1, xf + 1, u, pbase, jc);
+        xwrite<T, 0, 1, 0>(sr, si, buf, rounds, x.wb);
+        for (int k = 1; k < R; ++k) {
+          CP<QRound> rk = rounds + k;
+          __syncthreads();
+          xread<T, 0, 1, 0>(sr, si, buf, xf + k, x.rb, x.sgn);
+          xwrite<T, 2, 3, 2>(sr, si, buf, rk - 1, x.wb);
+          round_fwd<0>(sr, si, rk, gtab, F);
+          __syncthreads();
+          xread<T, 2, 3, 2>(sr, si, buf, xf + k, x.rb, x.sgn);
+          if (k + 1 < R) {
+            x = xsetup<N>(rk + 1, xf + k + 1, u, pbase, jc);
+            xwrite<T, 0, 1, 0>(sr, si, buf, rk, x.wb);
+          }
+          round_fwd<2>(sr, si, rk, gtab, F);
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int k = 0; k < R; ++k) {
+        CP<QRound> rk = rounds + k;
+        if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, rk - 1, rk, xf + k, u, pbase, jc);
+        round_fwd<0>(sr, si, rk, gtab, F);
+        round_fwd<2>(sr, si, rk, gtab, F);
+      }
     }
     // ---------------- readout ----------------------------------------------------------------
     CP<QRound> rl = rounds + (R - 1);
@@ -522,27 +654,50 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       sr[7][r] = D2 * sr[0][r]; si[7][r] = D2 * si[0][r];
     }
     // ---------------- adjoint sweep with uncompute -----------------------------------------
-    for (int k = R - 1; k >= 0; --k) {
-      CP<QRound> rk = rounds + k;
+    // Per round in reverse: psi-family <- U^H (uncompute), lambda-family <- U^H, gate statistics,
+    // then the inverse exchange.  The pair (psi_c, lambda_c) for c = 0..3 is a self-contained
+    // group (its gates and its share of the statistics need no other statevector).
+    if constexpr (EXS == 4) {
+      // Software-pipelined over the four pair groups with plane pairs {0, 1} and {2, 3} in turn.
+      CP<QRound> rl = rounds + (R - 1);
+      round_adj_all(sr, si, rl, gtab, F, slots, wave, lane);
+      if (R > 1) {
+        XLane x = xsetup<N>(rounds + (R - 2), xb + (R - 1), u, pbase, jc);
+        xwrite<T, 0, 4, 0>(sr, si, buf, rl, x.wb);
+        for (int k = R - 1; k >= 1; --k) {
+          CP<QRound> rk = rounds + k, rp = rounds + (k - 1);
+          float q[9];
 #pragma unroll
-      for (int bb = 2; bb >= 0; --bb) {
-        const int gsrc = rk->gate[bb];
-        const int gid = gsrc >= 0 ? gsrc : F;   // identity entry: straight-line code, no branch
-        float g[8], d[8], q[6];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = gtab[gid * 8 + e];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) q[e] = 0.f;
-        dagger(g, d);
-        if (bb == 0) { apply_gate<0, 0, 8>(sr, si, d); accum_s<0>(sr, si, q); }
-        if (bb == 1) { apply_gate<1, 0, 8>(sr, si, d); accum_s<1>(sr, si, q); }
-        if (bb == 2) { apply_gate<2, 0, 8>(sr, si, d); accum_s<2>(sr, si, q); }
-        const float v4[4] = {q[0] + q[3], q[1] + q[4], q[2] + q[5], 0.f};
-        const float v = wave_reduce_scatter4(v4);
-        if (gsrc >= 0 && (lane & 15) == 0 && lane < 48)
-          slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+          for (int i = 0; i < 9; ++i) q[i] = 0.f;
+          __syncthreads();
+          xread<T, 0, 4, 0>(sr, si, buf, xb + k, x.rb, x.sgn);
+          xwrite<T, 1, 5, 2>(sr, si, buf, rk, x.wb);
+          round_adj<0>(sr, si, rp, gtab, F, q);
+          __syncthreads();
+          xread<T, 1, 5, 2>(sr, si, buf, xb + k, x.rb, x.sgn);
+          xwrite<T, 2, 6, 0>(sr, si, buf, rk, x.wb);
+          round_adj<1>(sr, si, rp, gtab, F, q);
+          __syncthreads();
+          xread<T, 2, 6, 0>(sr, si, buf, xb + k, x.rb, x.sgn);
+          xwrite<T, 3, 7, 2>(sr, si, buf, rk, x.wb);
+          round_adj<2>(sr, si, rp, gtab, F, q);
+          __syncthreads();
+          xread<T, 3, 7, 2>(sr, si, buf, xb + k, x.rb, x.sgn);
+          if (k > 1) {
+            x = xsetup<N>(rounds + (k - 2), xb + (k - 1), u, pbase, jc);
+            xwrite<T, 0, 4, 0>(sr, si, buf, rp, x.wb);
+          }
+          round_adj<3>(sr, si, rp, gtab, F, q);
+          round_stat_flush(rp, slots, q, F, wave, lane);
+        }
+        __syncthreads();
       }
-      if (k > 0) exchange<N, T, 8, EXS>(sr, si, buf, rk, rk - 1, xb + k, u, pbase, jc);
+    } else {
+      for (int k = R - 1; k >= 0; --k) {
+        CP<QRound> rk = rounds + k;
+        round_adj_all(sr, si, rk, gtab, F, slots, wave, lane);
+        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk, rk - 1, xb + k, u, pbase, jc);
+      }
     }
   }
 }
@@ -552,9 +707,12 @@ template <int N, int T, int EXS, int MODE>
 __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   constexpr int WAVES = T / 64;
   constexpr int PLANE = T * 8;
+  // Exchange planes in static LDS (their address is a link-time constant, so every access is
+  // one XOR of a byte offset); gate statistics and readout scratch in the dynamic part.
+  __shared__ float4 planes[EXS * PLANE / 2];
   extern __shared__ float4 smem4[];
-  float2* buf = reinterpret_cast<float2*>(smem4);
-  float* slots = reinterpret_cast<float*>(buf + EXS * PLANE);      // [WAVES][F][kGS]
+  float2* buf = reinterpret_cast<float2*>(planes);
+  float* slots = reinterpret_cast<float*>(smem4);                   // [WAVES][F][kGS]
   float* red = slots + WAVES * a.n_fused * kGS;                      // [WAVES][40]
   const int F = a.n_fused;
   const int tid = threadIdx.x;
@@ -569,17 +727,15 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   // XCD walks one contiguous range of tiles and neighbouring points' output lines are written
   // through one L2 instead of eight.
   constexpr int kXcd = 8;
+  int t_begin = blockIdx.x, t_end = a.ntiles, t_step = gridDim.x;
   if (gridDim.x % kXcd == 0) {
-    const int per = gridDim.x / kXcd;
     const int chunk = (a.ntiles + kXcd - 1) / kXcd;
-    const int t0 = (blockIdx.x % kXcd) * chunk;
-    const int t1 = min(a.ntiles, t0 + chunk);
-    for (int tile = t0 + blockIdx.x / kXcd; tile < t1; tile += per)
-      fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
-  } else {
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x)
-      fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+    t_begin = (blockIdx.x % kXcd) * chunk + blockIdx.x / kXcd;
+    t_end = min(a.ntiles, (int)(blockIdx.x % kXcd) * chunk + chunk);
+    t_step = gridDim.x / kXcd;
   }
+  for (int tile = t_begin; tile < t_end; tile += t_step)
+    fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
@@ -607,13 +763,16 @@ template <int N, int EXS, int MODE>
 hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) {
   constexpr int T = (N == 12) ? 512 : 256;
   auto kern = k_fused<N, T, EXS, MODE>;
+  // lds counts the static exchange planes and the dynamic part; only the latter is passed.
+  const size_t planes = (size_t)EXS * T * 8 * sizeof(float2);
+  const size_t dyn = lds > planes ? lds - planes : 0;
   static size_t attr_bytes = 0;
-  if (lds > 64 * 1024 && lds > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (dyn > 0 && dyn > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    attr_bytes = lds;
+    attr_bytes = dyn;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(T), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(T), dyn, st, a);
   return hipGetLastError();
 }
 

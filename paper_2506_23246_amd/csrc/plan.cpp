@@ -150,6 +150,7 @@ void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool s
   bool ident = aff.terms.empty();
   for (int k = 0; k < n; ++k) ident = ident && (Acols[k] == (1u << k));
   X->identity = ident ? 1u : 0u;
+  for (int r = 0; r < 8; ++r) X->roff[r] = 8u * lds_swizzle(ident ? jr_of(read_tpos, r) : X->src_r[r]);
 }
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -373,6 +374,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     QRound R{};
     for (int i = 0; i < 3; ++i) R.gate[i] = gate_ids[i];
     make_tpos(n, reg, R.tpos);
+    for (int r = 0; r < 8; ++r) R.woff[r] = 8u * lds_swizzle(jr_of(R.tpos, r));   // complex64 bytes
     hp->rounds.push_back(R);
     round_ent.push_back(pending);
     round_has_ent.push_back(have_pending);

@@ -10,7 +10,19 @@
 #pragma once
 #include <cstdint>
 
+#if defined(__HIPCC__) || defined(__HIP__)
+#define QP_HD __host__ __device__
+#else
+#define QP_HD
+#endif
+
 namespace qp {
+
+// LDS index swizzle of the fused kernels: XOR the low nibble with the fold of all higher
+// nibbles.  A bijection, and linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b).
+QP_HD inline constexpr uint32_t lds_swizzle(uint32_t idx) {
+  return idx ^ (((idx >> 4) ^ (idx >> 8) ^ (idx >> 12) ^ (idx >> 16)) & 15u);
+}
 
 constexpr int kMaxQubits = 12;     // fused register/LDS kernels
 constexpr int kMaxQubitsPlain = 14;
@@ -20,11 +32,15 @@ constexpr int kRegBits = 3;        // 8 amplitudes per thread per statevector
 // Per fused gate the adjoint sweep accumulates S_k = Im <lambda|sigma_k|psi> (k = x, y, z) over
 // all points and statevector pairs, stored as kGS floats/doubles per gate (the last unused).
 constexpr int kGS = 4;
+// Gate-table entry: U (8 floats, row-major complex) followed by U^H (8 floats), so that the
+// adjoint reads its coefficients as they are used.
+constexpr int kGT = 16;
 
 struct alignas(16) QRound {
   int32_t gate[3];    // fused-gate id applied on register bit b (-1: none)
   int32_t pad0;
   int32_t tpos[16];   // logical index-bit position of physical bit k
+  uint32_t woff[8];   // 8 * lds_swizzle of register r's logical offset: byte offset, writer side
 };
 
 // One direction of the register exchange that precedes a round.  Reader thread (u, r) in the
@@ -44,9 +60,10 @@ struct alignas(16) QXchg {
   uint32_t qsign_r;   // bit r: Q(x_r) for the uniform part x_r
   uint32_t identity;  // A = I and no sign terms
   uint32_t pad1[2];
+  uint32_t roff[8];   // 8 * lds_swizzle of register r's uniform source offset: byte offset, reader side
 };
-static_assert(sizeof(QXchg) == 400, "QXchg layout");
-static_assert(sizeof(QRound) == 80, "QRound layout");
+static_assert(sizeof(QXchg) == 432, "QXchg layout");
+static_assert(sizeof(QRound) == 112, "QRound layout");
 
 // Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).
 struct alignas(16) QFused {

@@ -48,6 +48,16 @@ __host__ __device__ inline void left_mul_mhalf_i_pauli(int kind, T* u) {
   for (int e = 0; e < 8; ++e) u[e] = n[e];
 }
 
+// Writes U and U^H (rounded to float) to a gate-table entry o[0..15].
+template <typename T>
+__host__ __device__ inline void store_gate_entry(float* o, const T* u) {
+  for (int e = 0; e < 8; ++e) o[e] = (float)u[e];
+  o[8] = (float)u[0];  o[9] = -(float)u[1];    // (0,0) <- conj u00
+  o[10] = (float)u[4]; o[11] = -(float)u[5];   // (0,1) <- conj u10
+  o[12] = (float)u[2]; o[13] = -(float)u[3];   // (1,0) <- conj u01
+  o[14] = (float)u[6]; o[15] = -(float)u[7];   // (1,1) <- conj u11
+}
+
 template <typename T>
 __host__ __device__ inline void set_identity(T* u) {
   u[0] = T(1); u[1] = T(0); u[2] = T(0); u[3] = T(0);

@@ -20,12 +20,12 @@ HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused",
                 ("coord", "<i4", 16), ("zmask", "<u4", 8), ("off_rounds", "<i4"), ("off_xf", "<i4"),
                 ("off_xb", "<i4"), ("off_fused", "<i4"), ("off_csr_ptr", "<i4"), ("off_csr_idx", "<i4"),
                 ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4")])
-ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("tpos", "<i4", 16)])
+ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("tpos", "<i4", 16), ("woff", "<u4", 8)])
 XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("qv", "<u4", 32), ("ue", "<u4", 3),
                  ("ve", "<u4", 3), ("nterms", "<u4"), ("sign_at_src", "<u4"), ("qsign_r", "<u4"), ("identity", "<u4"),
-                 ("pad1", "<u4", 2)])
+                 ("pad1", "<u4", 2), ("roff", "<u4", 8)])
 FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3)])
-assert ROUND.itemsize == 80 and XCHG.itemsize == 400 and FUSED.itemsize == 32
+assert ROUND.itemsize == 112 and XCHG.itemsize == 432 and FUSED.itemsize == 32
 
 
 def plan_image(circ):

@@ -138,6 +138,36 @@ def test_maxwell_loss_kinds(ctx, kind):
     _check_maxwell(ctx, w, name=f"loss kind {kind}")
 
 
+@pytest.mark.parametrize("n,layers", [(3, 1), (4, 3), (8, 3), (11, 2), (12, 2)])
+def test_maxwell_both_exchange_shapes(ctx, n, layers):
+    """Whole Maxwell step with the software-pipelined exchange (two plane pairs) and with the
+    unpipelined one (one plane pair): both against the oracle, on mixed CNOT/CZ rings (sign and
+    sign-free exchanges), single-round circuits included; P spans tiles plus a ragged tail."""
+    from paper_2506_23246_amd.api import Circuit
+    rng = np.random.default_rng(300 + n)
+    rings = [W.ring(n, W.CNOT, 1) + W.ring(n, W.CZ, 2), W.ring(n, W.CZ, 1), W.ring(n, W.CNOT, 2)]
+    circ = W.layered(n, layers, "xyz", lambda l: rings[l % 3] if layers > 1 else [],
+                     out_qubits=[0, n - 1, n // 2])
+    params = rng.uniform(0, 2 * math.pi, circ.n_params).astype(np.float32)
+    ppw = max(1, (512 if n == 12 else 256) // (1 << (n - 3)))
+    P = 2 * ppw + 1 if n < 12 else 3
+    pts = rng.uniform(-1, 1, (P, 3)).astype(np.float32)
+    loss = W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=0.0)
+    f, g, L, grad = O.maxwell_eval(circ, params, pts, loss)
+    res = {}
+    for planes in (4, 2):
+        c = Circuit(ctx, circ)
+        c.set_launch(planes, 1)
+        r = c.maxwell(params, pts, loss)
+        errs = dict(f=rel(t2n(r["out"]), f), g=rel(t2n(r["tan"]), g), loss=rel(t2n(r["loss"]), [L]),
+                    grad=rel(t2n(r["grad"]), grad))
+        report(f"maxwell exchange planes={planes} n={n} L={layers} P={P}", **errs)
+        for k, v in errs.items():
+            assert v < TOL, (planes, k, v)
+        res[planes] = t2n(r["grad"])
+    assert rel(res[2], res[4]) < TOL
+
+
 def test_maxwell_batch_circuits_individually(ctx):
     """Every circuit of the uneven batch through the single-circuit fused path (small P)."""
     for w in W.batch_config(P_cap=40)[:8]:

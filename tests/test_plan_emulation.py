@@ -52,3 +52,29 @@ def test_emulated_plan_mixed_entanglers(n):
     params = rng.uniform(0, 2 * math.pi, circ.n_params)
     pts = rng.uniform(-1, 1, (2, 3))
     _run(circ, params, pts)
+
+
+def _swz(i):
+    return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12) ^ (i >> 16)) & 15)
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_plan_lds_offset_tables(k):
+    """The planner's swizzled LDS byte offsets: writer side woff[r] = 8 swz(register offset of r in
+    the round's mapping); reader side roff[r] = 8 swz(uniform source offset), which for an identity
+    exchange is the reader round's own register offset.  swz must also be linear over GF(2),
+    which the kernel's address arithmetic relies on."""
+    from tests.plan_emulator import _regoff, plan_image
+    plan = plan_image(W.config(k, P=1).circuit)
+    rounds = plan["rounds"]
+    for rd in rounds:
+        for r in range(8):
+            assert int(rd["woff"][r]) == 8 * _swz(_regoff(r, rd["tpos"]))
+    for kk in range(1, len(rounds)):
+        for X, read in ((plan["xf"][kk], rounds[kk]), (plan["xb"][kk], rounds[kk - 1])):
+            for r in range(8):
+                src = _regoff(r, read["tpos"]) if X["identity"] else int(X["src_r"][r])
+                assert int(X["roff"][r]) == 8 * _swz(src)
+    rng = np.random.default_rng(0)
+    for a, b in rng.integers(0, 1 << 12, (200, 2)):
+        assert _swz(int(a) ^ int(b)) == _swz(int(a)) ^ _swz(int(b))
