@@ -150,6 +150,55 @@ struct XLane {
   uint32_t wb, rb, sgn;
 };
 
+// Per-round uniform data, loaded once before the round's first barrier and pinned in SGPRs:
+// scalar loads share the lgkm counter with LDS operations, so a scalar load inside a slot would
+// make the next use wait for every outstanding LDS write as well.
+template <typename V>
+__device__ __forceinline__ void pin_sgpr(V& v) { asm volatile("" : "+s"(v)); }
+
+// Marks statevector S as computed at this point of the instruction stream: keeps the compiler
+// from sinking a group's gate arithmetic past the following barrier, which would undo the
+// overlap of that group's arithmetic with another group's LDS traffic.
+template <int S>
+__device__ __forceinline__ void pin_sv(float (&sr)[8][8], float (&si)[8][8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) asm volatile("" : "+v"(sr[S][r]), "+v"(si[S][r]));
+}
+
+struct RoundCoef {
+  float c[24];   // gate b's 2x2 matrix (U, or U^H in the adjoint) at c[8b .. 8b+7]
+  int gid[3];    // fused-gate ids (-1: none)
+};
+
+template <bool ADJ>
+__device__ __forceinline__ RoundCoef load_round(CP<QRound> rk, CP<float> gtab, int F) {
+  RoundCoef R;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int g = rk->gate[b];
+    R.gid[b] = g;
+    const int gi = g >= 0 ? g : F;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) R.c[8 * b + e] = gtab[gi * kGT + (ADJ ? 8 : 0) + e];
+  }
+#pragma unroll
+  for (int i = 0; i < 24; ++i) pin_sgpr(R.c[i]);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) pin_sgpr(R.gid[b]);
+  return R;
+}
+
+struct Offs {
+  uint32_t o[8];
+};
+
+__device__ __forceinline__ Offs load_offs(CP<uint32_t> p) {
+  Offs O;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) { O.o[r] = p[r]; pin_sgpr(O.o[r]); }
+  return O;
+}
+
 // jc: on entry the thread part of the logical index in the writer mapping (deposit of u), on
 // exit the same in the reader mapping rd.
 template <int N>
@@ -201,12 +250,12 @@ __device__ __forceinline__ XLane xsetup(CP<QRound> rd, CP<QXchg> X, uint32_t u, 
 // Writes statevectors SV0 and SV1 to LDS planes PL and PL + 1 in the writer mapping wr.
 template <int T, int SV0, int SV1, int PL>
 __device__ __forceinline__ void xwrite(const float (&sr)[8][8], const float (&si)[8][8], float2* __restrict__ buf,
-                                       CP<QRound> wr, uint32_t wb) {
+                                       const Offs& wo, uint32_t wb) {
   constexpr int PLANE = T * 8 * 8;   // bytes
   char* b = reinterpret_cast<char*>(buf);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const uint32_t o = wb ^ wr->woff[r];
+    const uint32_t o = wb ^ wo.o[r];
     *reinterpret_cast<float2*>(b + PL * PLANE + o) = make_float2(sr[SV0][r], si[SV0][r]);
     *reinterpret_cast<float2*>(b + (PL + 1) * PLANE + o) = make_float2(sr[SV1][r], si[SV1][r]);
   }
@@ -215,30 +264,31 @@ __device__ __forceinline__ void xwrite(const float (&sr)[8][8], const float (&si
 // Reads statevectors SV0 and SV1 back from planes PL, PL + 1 through the descriptor X.
 template <int T, int SV0, int SV1, int PL>
 __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], const float2* __restrict__ buf,
-                                      CP<QXchg> X, uint32_t rb, uint32_t sgn) {
+                                      const Offs& ro, bool signs, uint32_t rb, uint32_t sgn) {
+  // SV0 is read completely before SV1, so the gates on SV0 can start while SV1 is in flight.
   constexpr int PLANE = T * 8 * 8;   // bytes
   const char* b = reinterpret_cast<const char*>(buf);
-  if (X->nterms == 0) {   // no sign terms (identity or a CNOT stage): uniform fast path
+  if (!signs) {   // no sign terms (identity or a CNOT stage): uniform fast path
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const uint32_t o = rb ^ X->roff[r];
-      const float2 v0 = *reinterpret_cast<const float2*>(b + PL * PLANE + o);
-      const float2 v1 = *reinterpret_cast<const float2*>(b + (PL + 1) * PLANE + o);
-      sr[SV0][r] = v0.x; si[SV0][r] = v0.y;
-      sr[SV1][r] = v1.x; si[SV1][r] = v1.y;
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t o = rb ^ ro.o[r];
+        const float2 v = *reinterpret_cast<const float2*>(b + (PL + h) * PLANE + o);
+        if (h == 0) { sr[SV0][r] = v.x; si[SV0][r] = v.y; } else { sr[SV1][r] = v.x; si[SV1][r] = v.y; }
+      }
   } else {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const uint32_t o = rb ^ X->roff[r];
-      const float2 v0 = *reinterpret_cast<const float2*>(b + PL * PLANE + o);
-      const float2 v1 = *reinterpret_cast<const float2*>(b + (PL + 1) * PLANE + o);
-      const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
-      sr[SV0][r] = __uint_as_float(__float_as_uint(v0.x) ^ flip);
-      si[SV0][r] = __uint_as_float(__float_as_uint(v0.y) ^ flip);
-      sr[SV1][r] = __uint_as_float(__float_as_uint(v1.x) ^ flip);
-      si[SV1][r] = __uint_as_float(__float_as_uint(v1.y) ^ flip);
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t o = rb ^ ro.o[r];
+        const float2 v = *reinterpret_cast<const float2*>(b + (PL + h) * PLANE + o);
+        const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
+        const float vr = __uint_as_float(__float_as_uint(v.x) ^ flip);
+        const float vi = __uint_as_float(__float_as_uint(v.y) ^ flip);
+        if (h == 0) { sr[SV0][r] = vr; si[SV0][r] = vi; } else { sr[SV1][r] = vr; si[SV1][r] = vi; }
+      }
   }
 }
 
@@ -249,68 +299,52 @@ __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], f
                                          CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase,
                                          uint32_t& jc) {
   static_assert(EXS == 2, "pairs of planes");
+  const Offs wo = load_offs(wr->woff), ro = load_offs(X->roff);
+  const bool sg = X->nterms != 0;
   const XLane x = xsetup<N>(rd, X, u, pbase, jc);
 #pragma unroll
   for (int g = 0; g < NSV; g += 2) {
-    if (g == 0) xwrite<T, 0, 1, 0>(sr, si, buf, wr, x.wb);
-    if (g == 2) xwrite<T, 2, 3, 0>(sr, si, buf, wr, x.wb);
-    if (g == 4) xwrite<T, 4, 5, 0>(sr, si, buf, wr, x.wb);
-    if (g == 6) xwrite<T, 6, 7, 0>(sr, si, buf, wr, x.wb);
+    if (g == 0) xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
+    if (g == 2) xwrite<T, 2, 3, 0>(sr, si, buf, wo, x.wb);
+    if (g == 4) xwrite<T, 4, 5, 0>(sr, si, buf, wo, x.wb);
+    if (g == 6) xwrite<T, 6, 7, 0>(sr, si, buf, wo, x.wb);
     __syncthreads();
-    if (g == 0) xread<T, 0, 1, 0>(sr, si, buf, X, x.rb, x.sgn);
-    if (g == 2) xread<T, 2, 3, 0>(sr, si, buf, X, x.rb, x.sgn);
-    if (g == 4) xread<T, 4, 5, 0>(sr, si, buf, X, x.rb, x.sgn);
-    if (g == 6) xread<T, 6, 7, 0>(sr, si, buf, X, x.rb, x.sgn);
+    if (g == 0) xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+    if (g == 2) xread<T, 2, 3, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+    if (g == 4) xread<T, 4, 5, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+    if (g == 6) xread<T, 6, 7, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
     __syncthreads();
   }
 }
 
-// Forward gates of round rk on statevectors S0, S0 + 1 (an absent gate is the identity entry F).
+// Forward gates of a round on statevectors S0, S0 + 1 (an absent gate is the identity entry).
 template <int S0>
-__device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab, int F) {
-  float g[8];
-  const int g0 = rk->gate[0] >= 0 ? rk->gate[0] : F;
-  const int g1 = rk->gate[1] >= 0 ? rk->gate[1] : F;
-  const int g2 = rk->gate[2] >= 0 ? rk->gate[2] : F;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) g[e] = gtab[g0 * kGT + e];
-  apply_gate<0, S0, 2>(sr, si, g);
-#pragma unroll
-  for (int e = 0; e < 8; ++e) g[e] = gtab[g1 * kGT + e];
-  apply_gate<1, S0, 2>(sr, si, g);
-#pragma unroll
-  for (int e = 0; e < 8; ++e) g[e] = gtab[g2 * kGT + e];
-  apply_gate<2, S0, 2>(sr, si, g);
+__device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+  // statevector-major: all gates of S0 first (its reads land first), then S0 + 1
+  apply_gate<0, S0, 1>(sr, si, R.c); apply_gate<1, S0, 1>(sr, si, R.c + 8); apply_gate<2, S0, 1>(sr, si, R.c + 16);
+  apply_gate<0, S0 + 1, 1>(sr, si, R.c); apply_gate<1, S0 + 1, 1>(sr, si, R.c + 8);
+  apply_gate<2, S0 + 1, 1>(sr, si, R.c + 16);
 }
 
 // Wave-reduces the round's three gate statistics and adds them to the per-wave LDS slots.
-__device__ __forceinline__ void round_stat_flush(CP<QRound> rk, float* __restrict__ slots, const float* q, int F,
+__device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __restrict__ slots, const float* q, int F,
                                                  int wave, int lane) {
 #pragma unroll
   for (int bb = 0; bb < 3; ++bb) {
-    const int gsrc = rk->gate[bb];
+    const int gsrc = R.gid[bb];
     const float v4[4] = {q[3 * bb], q[3 * bb + 1], q[3 * bb + 2], 0.f};
     const float v = wave_reduce_scatter4(v4);
     if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
   }
 }
 
-// Adjoint gates of round rk (in reverse) on the pair (C, 4 + C): psi_C and lambda_C <- U^H, then
+// Adjoint gates of a round (in reverse) on the pair (C, 4 + C): psi_C and lambda_C <- U^H, then
 // the pair's share of the three gate statistics is added to q[3 * bb + k] (per lane).
 template <int C>
-__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab, int F,
-                                          float* q) {
-#pragma unroll
-  for (int bb = 2; bb >= 0; --bb) {
-    const int gsrc = rk->gate[bb];
-    const int gid = gsrc >= 0 ? gsrc : F;
-    float d[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
-    if (bb == 0) { apply_gate<0, C, 1>(sr, si, d); apply_gate<0, 4 + C, 1>(sr, si, d); accum_s1<0, C>(sr, si, q); }
-    if (bb == 1) { apply_gate<1, C, 1>(sr, si, d); apply_gate<1, 4 + C, 1>(sr, si, d); accum_s1<1, C>(sr, si, q + 3); }
-    if (bb == 2) { apply_gate<2, C, 1>(sr, si, d); apply_gate<2, 4 + C, 1>(sr, si, d); accum_s1<2, C>(sr, si, q + 6); }
-  }
+__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R, float* q) {
+  apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16); accum_s1<2, C>(sr, si, q + 6);
+  apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);  accum_s1<1, C>(sr, si, q + 3);
+  apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);      accum_s1<0, C>(sr, si, q);
 }
 
 // Adjoint gates of round rk on all four pairs, gate by gate, each gate's statistic flushed at
@@ -492,24 +526,34 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
       // (planes 2, 3).  Each group's LDS writes drain while the other group's gates run; every
       // barrier separates a plane pair's reads from its next writes.
-      round_fwd<0>(sr, si, rounds, gtab, F);
-      round_fwd<2>(sr, si, rounds, gtab, F);
+      {
+        const RoundCoef R0 = load_round<false>(rounds, gtab, F);
+        round_fwd<0>(sr, si, R0);
+        round_fwd<2>(sr, si, R0);
+      }
       if (R > 1) {
+        Offs wo = load_offs(rounds[0].woff);
         XLane x = xsetup<N>(rounds + 1, xf + 1, u, pbase, jc);
-        xwrite<T, 0, 1, 0>(sr, si, buf, rounds, x.wb);
+        xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
         for (int k = 1; k < R; ++k) {
           CP<QRound> rk = rounds + k;
+          const RoundCoef Rk = load_round<false>(rk, gtab, F);
+          const Offs ro = load_offs(xf[k].roff);
+          const bool sg = xf[k].nterms != 0;
           __syncthreads();
-          xread<T, 0, 1, 0>(sr, si, buf, xf + k, x.rb, x.sgn);
-          xwrite<T, 2, 3, 2>(sr, si, buf, rk - 1, x.wb);
-          round_fwd<0>(sr, si, rk, gtab, F);
+          xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
+          round_fwd<0>(sr, si, Rk);
+          pin_sv<0>(sr, si); pin_sv<1>(sr, si);
           __syncthreads();
-          xread<T, 2, 3, 2>(sr, si, buf, xf + k, x.rb, x.sgn);
+          xread<T, 2, 3, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           if (k + 1 < R) {
+            wo = load_offs(rk->woff);
             x = xsetup<N>(rk + 1, xf + k + 1, u, pbase, jc);
-            xwrite<T, 0, 1, 0>(sr, si, buf, rk, x.wb);
+            xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
           }
-          round_fwd<2>(sr, si, rk, gtab, F);
+          round_fwd<2>(sr, si, Rk);
+          pin_sv<2>(sr, si); pin_sv<3>(sr, si);
         }
         __syncthreads();
       }
@@ -517,8 +561,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = 0; k < R; ++k) {
         CP<QRound> rk = rounds + k;
         if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, rk - 1, rk, xf + k, u, pbase, jc);
-        round_fwd<0>(sr, si, rk, gtab, F);
-        round_fwd<2>(sr, si, rk, gtab, F);
+        const RoundCoef Rk = load_round<false>(rk, gtab, F);
+        round_fwd<0>(sr, si, Rk);
+        round_fwd<2>(sr, si, Rk);
       }
     }
     // ---------------- readout ----------------------------------------------------------------
@@ -662,33 +707,48 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       CP<QRound> rl = rounds + (R - 1);
       round_adj_all(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
+        Offs wo = load_offs(rl->woff);
         XLane x = xsetup<N>(rounds + (R - 2), xb + (R - 1), u, pbase, jc);
-        xwrite<T, 0, 4, 0>(sr, si, buf, rl, x.wb);
+        xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
         for (int k = R - 1; k >= 1; --k) {
-          CP<QRound> rk = rounds + k, rp = rounds + (k - 1);
+          CP<QRound> rp = rounds + (k - 1);
+          const RoundCoef Rp = load_round<true>(rp, gtab, F);
+          const Offs ro = load_offs(xb[k].roff);
+          const bool sg = xb[k].nterms != 0;
           float q[9];
 #pragma unroll
           for (int i = 0; i < 9; ++i) q[i] = 0.f;
           __syncthreads();
-          xread<T, 0, 4, 0>(sr, si, buf, xb + k, x.rb, x.sgn);
-          xwrite<T, 1, 5, 2>(sr, si, buf, rk, x.wb);
-          round_adj<0>(sr, si, rp, gtab, F, q);
+          xread<T, 0, 4, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xwrite<T, 1, 5, 2>(sr, si, buf, wo, x.wb);
+          round_adj<0>(sr, si, Rp, q);
+          pin_sv<0>(sr, si); pin_sv<4>(sr, si);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
           __syncthreads();
-          xread<T, 1, 5, 2>(sr, si, buf, xb + k, x.rb, x.sgn);
-          xwrite<T, 2, 6, 0>(sr, si, buf, rk, x.wb);
-          round_adj<1>(sr, si, rp, gtab, F, q);
+          xread<T, 1, 5, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xwrite<T, 2, 6, 0>(sr, si, buf, wo, x.wb);
+          round_adj<1>(sr, si, Rp, q);
+          pin_sv<1>(sr, si); pin_sv<5>(sr, si);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
           __syncthreads();
-          xread<T, 2, 6, 0>(sr, si, buf, xb + k, x.rb, x.sgn);
-          xwrite<T, 3, 7, 2>(sr, si, buf, rk, x.wb);
-          round_adj<2>(sr, si, rp, gtab, F, q);
+          xread<T, 2, 6, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xwrite<T, 3, 7, 2>(sr, si, buf, wo, x.wb);
+          round_adj<2>(sr, si, Rp, q);
+          pin_sv<2>(sr, si); pin_sv<6>(sr, si);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
           __syncthreads();
-          xread<T, 3, 7, 2>(sr, si, buf, xb + k, x.rb, x.sgn);
+          xread<T, 3, 7, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           if (k > 1) {
+            wo = load_offs(rp->woff);
             x = xsetup<N>(rounds + (k - 2), xb + (k - 1), u, pbase, jc);
-            xwrite<T, 0, 4, 0>(sr, si, buf, rp, x.wb);
+            xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
           }
-          round_adj<3>(sr, si, rp, gtab, F, q);
-          round_stat_flush(rp, slots, q, F, wave, lane);
+          round_adj<3>(sr, si, Rp, q);
+          pin_sv<3>(sr, si); pin_sv<7>(sr, si);
+          round_stat_flush(Rp, slots, q, F, wave, lane);
         }
         __syncthreads();
       }
