@@ -251,13 +251,14 @@ __device__ __forceinline__ XLane xsetup(CP<QRound> rd, CP<QXchg> X, uint32_t u, 
 template <int T, int SV0, int SV1, int PL>
 __device__ __forceinline__ void xwrite(const float (&sr)[8][8], const float (&si)[8][8], float2* __restrict__ buf,
                                        const Offs& wo, uint32_t wb) {
-  constexpr int PLANE = T * 8 * 8;   // bytes
+  constexpr uint32_t PLANE = T * 8 * 8;   // bytes; a power of two above every in-plane offset
   char* b = reinterpret_cast<char*>(buf);
+  const uint32_t base = wb | (PL * PLANE);   // plane PL folded into the base: one XOR per access
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const uint32_t o = wb ^ wo.o[r];
-    *reinterpret_cast<float2*>(b + PL * PLANE + o) = make_float2(sr[SV0][r], si[SV0][r]);
-    *reinterpret_cast<float2*>(b + (PL + 1) * PLANE + o) = make_float2(sr[SV1][r], si[SV1][r]);
+    const uint32_t o = base ^ wo.o[r];
+    *reinterpret_cast<float2*>(b + o) = make_float2(sr[SV0][r], si[SV0][r]);
+    *reinterpret_cast<float2*>(b + PLANE + o) = make_float2(sr[SV1][r], si[SV1][r]);
   }
 }
 
@@ -266,15 +267,16 @@ template <int T, int SV0, int SV1, int PL>
 __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], const float2* __restrict__ buf,
                                       const Offs& ro, bool signs, uint32_t rb, uint32_t sgn) {
   // SV0 is read completely before SV1, so the gates on SV0 can start while SV1 is in flight.
-  constexpr int PLANE = T * 8 * 8;   // bytes
+  constexpr uint32_t PLANE = T * 8 * 8;   // bytes; a power of two above every in-plane offset
   const char* b = reinterpret_cast<const char*>(buf);
+  const uint32_t base = rb | (PL * PLANE);   // plane PL folded into the base: one XOR per access
   if (!signs) {   // no sign terms (identity or a CNOT stage): uniform fast path
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const uint32_t o = rb ^ ro.o[r];
-        const float2 v = *reinterpret_cast<const float2*>(b + (PL + h) * PLANE + o);
+        const uint32_t o = base ^ ro.o[r];
+        const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
         if (h == 0) { sr[SV0][r] = v.x; si[SV0][r] = v.y; } else { sr[SV1][r] = v.x; si[SV1][r] = v.y; }
       }
   } else {
@@ -282,8 +284,8 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const uint32_t o = rb ^ ro.o[r];
-        const float2 v = *reinterpret_cast<const float2*>(b + (PL + h) * PLANE + o);
+        const uint32_t o = base ^ ro.o[r];
+        const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
         const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
         const float vr = __uint_as_float(__float_as_uint(v.x) ^ flip);
         const float vi = __uint_as_float(__float_as_uint(v.y) ^ flip);
@@ -317,13 +319,22 @@ __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], f
   }
 }
 
-// Forward gates of a round on statevectors S0, S0 + 1 (an absent gate is the identity entry).
+// Forward gates of a round on statevectors S0, S0 + 1 (an absent gate is the identity entry):
+// gates01 applies the gates on register bits 0 and 1, gate2 the gate on bit 2 (gates on
+// different qubits commute, so the split point is free).
+template <int S0>
+__device__ __forceinline__ void gates01(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+  apply_gate<0, S0, 1>(sr, si, R.c); apply_gate<1, S0, 1>(sr, si, R.c + 8);
+  apply_gate<0, S0 + 1, 1>(sr, si, R.c); apply_gate<1, S0 + 1, 1>(sr, si, R.c + 8);
+}
+template <int S0>
+__device__ __forceinline__ void gate2(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+  apply_gate<2, S0, 1>(sr, si, R.c + 16); apply_gate<2, S0 + 1, 1>(sr, si, R.c + 16);
+}
 template <int S0>
 __device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
-  // statevector-major: all gates of S0 first (its reads land first), then S0 + 1
-  apply_gate<0, S0, 1>(sr, si, R.c); apply_gate<1, S0, 1>(sr, si, R.c + 8); apply_gate<2, S0, 1>(sr, si, R.c + 16);
-  apply_gate<0, S0 + 1, 1>(sr, si, R.c); apply_gate<1, S0 + 1, 1>(sr, si, R.c + 8);
-  apply_gate<2, S0 + 1, 1>(sr, si, R.c + 16);
+  gates01<S0>(sr, si, R);
+  gate2<S0>(sr, si, R);
 }
 
 // Wave-reduces the round's three gate statistics and adds them to the per-wave LDS slots.
@@ -338,13 +349,28 @@ __device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __re
   }
 }
 
-// Adjoint gates of a round (in reverse) on the pair (C, 4 + C): psi_C and lambda_C <- U^H, then
-// the pair's share of the three gate statistics is added to q[3 * bb + k] (per lane).
+// Adjoint gates of a round on the pair (C, 4 + C): psi_C and lambda_C <- U^H for its three gates.
 template <int C>
-__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R, float* q) {
-  apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16); accum_s1<2, C>(sr, si, q + 6);
-  apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);  accum_s1<1, C>(sr, si, q + 3);
-  apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);      accum_s1<0, C>(sr, si, q);
+__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+  apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16);
+  apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);
+  apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);
+}
+
+// The pair's share of the round's three gate statistics, q[3 b + k] += S_k(bit b).  The gates of
+// one round act on different qubits and commute, so every gate's statistic may be taken with
+// both statevectors at the round input (all three gates pulled back): then the pull-backs of the
+// other two gates cancel inside <lambda|sigma_b|psi>.
+template <int C>
+__device__ __forceinline__ void stat_accum(const float (&sr)[8][8], const float (&si)[8][8], float* q) {
+  accum_s1<0, C>(sr, si, q);
+  accum_s1<1, C>(sr, si, q + 3);
+  accum_s1<2, C>(sr, si, q + 6);
+}
+
+__device__ __forceinline__ void pin_q(float* q) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
 }
 
 // Adjoint gates of round rk on all four pairs, gate by gate, each gate's statistic flushed at
@@ -526,11 +552,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
       // (planes 2, 3).  Each group's LDS writes drain while the other group's gates run; every
       // barrier separates a plane pair's reads from its next writes.
-      {
-        const RoundCoef R0 = load_round<false>(rounds, gtab, F);
-        round_fwd<0>(sr, si, R0);
-        round_fwd<2>(sr, si, R0);
-      }
+      // Each slot: read one group, finish the other group's round (its bit-2 gate) and write it,
+      // then the bit-0/1 gates of the group just read.  The finishing gate covers the read
+      // latency and the writes drain under the following gates.
+      RoundCoef Rc = load_round<false>(rounds, gtab, F);
+      round_fwd<0>(sr, si, Rc);
+      gates01<2>(sr, si, Rc);
       if (R > 1) {
         Offs wo = load_offs(rounds[0].woff);
         XLane x = xsetup<N>(rounds + 1, xf + 1, u, pbase, jc);
@@ -542,21 +569,25 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           const bool sg = xf[k].nterms != 0;
           __syncthreads();
           xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          gate2<2>(sr, si, Rc);                        // group B finishes round k - 1
           xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
-          round_fwd<0>(sr, si, Rk);
+          gates01<0>(sr, si, Rk);
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
           __syncthreads();
           xread<T, 2, 3, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          gate2<0>(sr, si, Rk);                        // group A finishes round k
           if (k + 1 < R) {
             wo = load_offs(rk->woff);
             x = xsetup<N>(rk + 1, xf + k + 1, u, pbase, jc);
             xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
           }
-          round_fwd<2>(sr, si, Rk);
+          gates01<2>(sr, si, Rk);
           pin_sv<2>(sr, si); pin_sv<3>(sr, si);
+          Rc = Rk;
         }
         __syncthreads();
       }
+      gate2<2>(sr, si, Rc);                            // group B finishes the last round
     } else {
       for (int k = 0; k < R; ++k) {
         CP<QRound> rk = rounds + k;
@@ -704,52 +735,61 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     // group (its gates and its share of the statistics need no other statevector).
     if constexpr (EXS == 4) {
       // Software-pipelined over the four pair groups with plane pairs {0, 1} and {2, 3} in turn.
+      // Each slot: read one pair group and write the next, add the previous group's gate
+      // statistics (covering the read latency), then pull the group just read back through the
+      // round.  A round's statistics are flushed in the next round's first slot.
       CP<QRound> rl = rounds + (R - 1);
       round_adj_all(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
         Offs wo = load_offs(rl->woff);
         XLane x = xsetup<N>(rounds + (R - 2), xb + (R - 1), u, pbase, jc);
         xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
+        float q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) q[i] = 0.f;
+        RoundCoef Rq = load_round<true>(rl, gtab, F);   // gate ids of the round whose q is pending
         for (int k = R - 1; k >= 1; --k) {
           CP<QRound> rp = rounds + (k - 1);
           const RoundCoef Rp = load_round<true>(rp, gtab, F);
           const Offs ro = load_offs(xb[k].roff);
           const bool sg = xb[k].nterms != 0;
-          float q[9];
-#pragma unroll
-          for (int i = 0; i < 9; ++i) q[i] = 0.f;
           __syncthreads();
           xread<T, 0, 4, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 1, 5, 2>(sr, si, buf, wo, x.wb);
-          round_adj<0>(sr, si, Rp, q);
-          pin_sv<0>(sr, si); pin_sv<4>(sr, si);
+          if (k < R - 1) {                             // finish the previous round's statistics
+            stat_accum<3>(sr, si, q);
+            round_stat_flush(Rq, slots, q, F, wave, lane);
 #pragma unroll
-          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
+            for (int i = 0; i < 9; ++i) q[i] = 0.f;
+          }
+          round_adj<0>(sr, si, Rp);
+          pin_sv<0>(sr, si); pin_sv<4>(sr, si); pin_q(q);
           __syncthreads();
           xread<T, 1, 5, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 2, 6, 0>(sr, si, buf, wo, x.wb);
-          round_adj<1>(sr, si, Rp, q);
-          pin_sv<1>(sr, si); pin_sv<5>(sr, si);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
+          stat_accum<0>(sr, si, q);
+          round_adj<1>(sr, si, Rp);
+          pin_sv<1>(sr, si); pin_sv<5>(sr, si); pin_q(q);
           __syncthreads();
           xread<T, 2, 6, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 3, 7, 2>(sr, si, buf, wo, x.wb);
-          round_adj<2>(sr, si, Rp, q);
-          pin_sv<2>(sr, si); pin_sv<6>(sr, si);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
+          stat_accum<1>(sr, si, q);
+          round_adj<2>(sr, si, Rp);
+          pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q(q);
           __syncthreads();
           xread<T, 3, 7, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          stat_accum<2>(sr, si, q);
           if (k > 1) {
             wo = load_offs(rp->woff);
             x = xsetup<N>(rounds + (k - 2), xb + (k - 1), u, pbase, jc);
             xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
           }
-          round_adj<3>(sr, si, Rp, q);
-          pin_sv<3>(sr, si); pin_sv<7>(sr, si);
-          round_stat_flush(Rp, slots, q, F, wave, lane);
+          round_adj<3>(sr, si, Rp);
+          pin_sv<3>(sr, si); pin_sv<7>(sr, si); pin_q(q);
+          Rq = Rp;
         }
+        stat_accum<3>(sr, si, q);                      // round 0's last group
+        round_stat_flush(Rq, slots, q, F, wave, lane);
         __syncthreads();
       }
     } else {

@@ -135,10 +135,27 @@ def _apply(regs, svs, bit, U):
         regs[svs, :, r1] = U[1, 0] * x + U[1, 1] * y
 
 
-def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
+def _stats(regs, b, s):
+    """s += (S_x, S_y, S_z) of the pairs on register bit b (lambda-family 4..7, psi-family 0..3)."""
+    for r in range(8):
+        if r & (1 << b):
+            continue
+        r1 = r | (1 << b)
+        for sv in range(4):
+            x0, x1 = regs[4 + sv, :, r], regs[4 + sv, :, r1]
+            y0, y1 = regs[sv, :, r], regs[sv, :, r1]
+            s[0] += np.sum(np.imag(np.conj(x0) * y1 + np.conj(x1) * y0))
+            s[1] += np.sum(np.real(np.conj(x1) * y0 - np.conj(x0) * y1))
+            s[2] += np.sum(np.imag(np.conj(x0) * y0 - np.conj(x1) * y1))
+
+
+def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, stats_at_round_input=False):
     """One point: returns f [m], g [m,3] and (if seeds given) the per-gate adjoint products:
     M [F,2,2] (lambda after the gate, psi before it) and S [F,3] = Im <lambda|sigma_k|psi> with
-    both taken before the gate (k = x, y, z), the statistic the kernel accumulates."""
+    both taken before the gate (k = x, y, z), the statistic the kernel accumulates.  With
+    stats_at_round_input, S of every gate of a round is taken after all of the round's gates are
+    pulled back (valid because they act on different qubits and commute), as the pipelined
+    kernel does."""
     h = plan["h"]
     n, m, R = int(h["n"]), int(h["n_out"]), int(h["n_rounds"])
     TP = 1 << (n - 3)
@@ -211,16 +228,13 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None):
                     M[g, 1, 0] += np.sum(np.conj(x1) * y0)
                     M[g, 1, 1] += np.sum(np.conj(x1) * y1)
             _apply(regs, slice(4, 8), b, Ud)
-            for r in range(8):
-                if r & (1 << b):
-                    continue
-                r1 = r | (1 << b)
-                for sv in range(4):
-                    x0, x1 = regs[4 + sv, :, r], regs[4 + sv, :, r1]
-                    y0, y1 = regs[sv, :, r], regs[sv, :, r1]
-                    S[g, 0] += np.sum(np.imag(np.conj(x0) * y1 + np.conj(x1) * y0))
-                    S[g, 1] += np.sum(np.real(np.conj(x1) * y0 - np.conj(x0) * y1))
-                    S[g, 2] += np.sum(np.imag(np.conj(x0) * y0 - np.conj(x1) * y1))
+            if not stats_at_round_input:
+                _stats(regs, b, S[g])
+        if stats_at_round_input:
+            for b in range(3):
+                g = int(rounds[k]["gate"][b])
+                if g >= 0:
+                    _stats(regs, b, S[g])
         if k > 0:
             regs = _exchange(regs, rounds[k], rounds[k - 1], xb[k], n, TP)
     return f, gg, M, S

@@ -34,6 +34,12 @@ def _run(circ, params, pts, seeds=True):
         np.testing.assert_allclose(grads_from_m(plan, params, M), exp, atol=1e-11)
         # the kernel's statistic: Pauli components with the rotated generator axes
         np.testing.assert_allclose(grads_from_s(plan, params, S), exp, atol=1e-11)
+        # ... also when every gate's statistic is taken at its round's input (pipelined kernel)
+        S2 = 0
+        for p in range(len(pts)):
+            S2 = S2 + emulate_point(plan, params, theta[p], J[p], circ.enc.gate == W.ENC_RX, None, Wg[p],
+                                    stats_at_round_input=True)[3]
+        np.testing.assert_allclose(grads_from_s(plan, params, S2), exp, atol=1e-11)
 
 
 @pytest.mark.parametrize("k", [0, 1, 2])
