@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of replays of the step captured in a HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -190,13 +192,37 @@ def main():
                "wg_per_cu": c.info(9), "loss": {0: "vacuum", 1: "dielectric split", 2: "dielectric intuitive"}[w.loss.kind]}
 
     log(f"bench: workload {cfg['workload']} P={P_total}; warmup {args.warmup}, steps {args.steps}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
+    # The timed step is one replay of the whole sequence (gate table, fused kernel, FP64
+    # reductions) captured in a HIP graph on a dedicated stream; --no-graph times eager launches.
+    run_step, timing = step, "eager launches"
+    gs = torch.cuda.Stream()
+    ctx.use_stream(gs)
+    with torch.cuda.stream(gs):
+        step()                       # first use on this stream (launch attributes, plan upload)
+    gs.synchronize()
+    if not args.no_graph:
+        try:
+            if k == 3:
+                def run_step():
+                    batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), graph=True)
+            else:
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph, stream=gs):
+                    step()
+                run_step = graph.replay
+            timing = "HIP graph replays"
+        except Exception as e:  # pragma: no cover - reported, eager timing instead
+            log(f"bench: graph capture failed ({e}); timing eager launches")
+            run_step = step
+    cfg["timing"] = timing
+    with torch.cuda.stream(gs):
+        for _ in range(args.warmup):
+            run_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            run_step()
+        torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / max(args.steps, 1)
     value = P_total / (ms_per_step / 1e3)
@@ -205,9 +231,12 @@ def main():
     # dominant kernel duration with HIP events on its own stream
     ctx.kernel_timing(True)
     kms = []
-    for _ in range(max(3, min(args.steps, 10))):
-        step()
-        kms.append(ctx.last_kernel_ms())
+    with torch.cuda.stream(gs):
+        for _ in range(max(3, min(args.steps, 10))):
+            step()
+            kms.append(ctx.last_kernel_ms())
+    torch.cuda.synchronize()
+    ctx.use_stream(torch.cuda.current_stream(dev))   # the extra legs below run on torch's stream
     ctx.kernel_timing(False)
     kms_avg = float(np.mean(kms))
     achieved = flops / (kms_avg / 1e3) / 1e12
