@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
+    ap.add_argument("--no-paper-context", action="store_true",
+                    help="skip the run of the paper's own circuit shape at its grid sizes")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the step captured in a HIP graph")
@@ -322,6 +324,37 @@ def main():
             "algorithmic_mfma_tflops": round(flops_d / t_d / 1e12, 2),
             "modelled_hbm_gbs": round(bytes_d / t_d / 1e9, 1)}
         log(f"bench: dense {line['dense_mfma']}")
+
+    if w is not None and not args.no_paper_context and k == 4:
+        # The paper's PQC shape (7 qubits, 4 layers of Rot + CNOT ring, RX(acos a) embedding of 7
+        # angles produced by its classical layer) at the grid sizes of its timing table.  Angles and
+        # their Jacobian are synthetic; context only, not a like-for-like comparison.
+        pc = W.paper_context_circuit("basic")
+        cc = Circuit(ctx, pc)
+        rng = np.random.default_rng(7)
+        prm_c = torch.tensor(rng.uniform(0, 2 * math.pi, pc.n_params).astype(np.float32), device=dev)
+        ours = {}
+        for side in (40, 87):
+            Pc = side ** 3
+            ang = torch.tensor(rng.uniform(0.0, math.pi, (Pc, pc.n)).astype(np.float32), device=dev)
+            jac = torch.tensor(rng.standard_normal((Pc, pc.n, 3)).astype(np.float32), device=dev)
+            cc.maxwell(prm_c, None, W.MaxwellDesc(), angles=ang, jac=jac)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                cc.maxwell(prm_c, None, W.MaxwellDesc(), angles=ang, jac=jac)
+            torch.cuda.synchronize()
+            ours[f"{side}^3"] = round(Pc / ((time.perf_counter() - t0) / 5), 1)
+            del ang, jac
+        line["paper_context"] = {
+            "what": "the paper's circuit shape: 7 qubits x 4 layers, Rot + CNOT ring, RX(acos) embedding of given "
+                    "angles, fused forward + 3 input tangents + Maxwell loss + adjoint gradient",
+            "ours_evals_per_s": ours,
+            "paper_torq_points_per_s": {"40^3": 4.41e5, "87^3": 7.75e5},
+            "paper_scope": "grid^3 / seconds per training epoch of the whole hybrid model (66848-parameter MLP, "
+                           "the PQC, autograd input derivatives, all loss terms, backward, Adam) on NVIDIA L40S or "
+                           "A100, precision not stated; context only"}
+        log(f"bench: paper context {line['paper_context']['ours_evals_per_s']}")
 
     if w is not None and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
