@@ -53,14 +53,6 @@ __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8],
   }
 }
 
-// conj-transpose of a gate table entry
-__device__ __forceinline__ void dagger(const float* u, float* d) {
-  d[0] = u[0]; d[1] = -u[1];   // (0,0) <- conj u00
-  d[2] = u[4]; d[3] = -u[5];   // (0,1) <- conj u10
-  d[4] = u[2]; d[5] = -u[3];   // (1,0) <- conj u01
-  d[6] = u[6]; d[7] = -u[7];   // (1,1) <- conj u11
-}
-
 // Gate statistic of one statevector pair (lambda-family 4 + C, psi-family C), both taken
 // before the gate, for the register pairs on bit B:
 //   S_x += Im(conj(x0) y1) + Im(conj(x1) y0)
