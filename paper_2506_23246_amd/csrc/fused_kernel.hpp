@@ -158,25 +158,25 @@ __device__ __forceinline__ void pin_sv(float (&sr)[8][8], float (&si)[8][8]) {
 }
 
 struct RoundCoef {
-  float c[24];   // gate b's 2x2 matrix (U, or U^H in the adjoint) at c[8b .. 8b+7]
-  int gid[3];    // fused-gate ids (-1: none)
+  float c[40];   // gate b's 2x2 matrix (U, or U^H in the adjoint) at c[8b .. 8b+7]; b = 3, 4: swap slots
+  int gid[5];    // fused-gate ids (-1: none): register bits 0..2, then swap slots 0, 1
 };
 
-template <bool ADJ>
+template <bool ADJ, int NS>
 __device__ __forceinline__ RoundCoef load_round(CP<QRound> rk, CP<float> gtab, int F) {
   RoundCoef R;
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int g = rk->gate[b];
+  for (int b = 0; b < 3 + NS; ++b) {
+    const int g = b < 3 ? rk->gate[b] : rk->sgate[b - 3];
     R.gid[b] = g;
     const int gi = g >= 0 ? g : F;
 #pragma unroll
     for (int e = 0; e < 8; ++e) R.c[8 * b + e] = gtab[gi * kGT + (ADJ ? 8 : 0) + e];
   }
 #pragma unroll
-  for (int i = 0; i < 24; ++i) pin_sgpr(R.c[i]);
+  for (int i = 0; i < 8 * (3 + NS); ++i) pin_sgpr(R.c[i]);
 #pragma unroll
-  for (int b = 0; b < 3; ++b) pin_sgpr(R.gid[b]);
+  for (int b = 0; b < 3 + NS; ++b) pin_sgpr(R.gid[b]);
   return R;
 }
 
@@ -191,24 +191,25 @@ __device__ __forceinline__ Offs load_offs(CP<uint32_t> p) {
   return O;
 }
 
-// jc: on entry the thread part of the logical index in the writer mapping (deposit of u), on
-// exit the same in the reader mapping rd.
+// jc: on entry the thread part of the logical index in the writer's mapping (deposit of u), on
+// exit the same in the reader's mapping rpos (a round's input map tpos or its output map tpost),
+// so consecutive exchanges deposit the thread bits once each.
 template <int N>
-__device__ __forceinline__ XLane xsetup(CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase, uint32_t& jc) {
+__device__ __forceinline__ XLane xsetup(CP<int32_t> rpos, CP<QXchg> X, uint32_t u, uint32_t pbase, uint32_t& jc) {
   XLane x;
   x.wb = swz(pbase ^ jc) * 8u;
-  const uint32_t jn = deposit_thread<N>(u, rd->tpos);
+  const uint32_t jn = deposit_thread<N>(u, rpos);
   jc = jn;
   uint32_t sb = jn;
   x.sgn = 0;   // bit r set: negate amplitude r
   if (!X->identity) {
-    // sb = A jn with jn = sum of the thread bits placed at rd->tpos[k]: column A e_tpos[k] is
-    // acol[tpos[k]], so only the N - 3 thread bits are visited.
+    // sb = A jn with jn = sum of the thread bits placed at rpos[k]: column A e_rpos[k] is
+    // acol[rpos[k]], so only the N - 3 thread bits are visited.
     sb = 0;
 #pragma unroll
     for (int k = 3; k < N; ++k) {
       const uint32_t msk = 0u - ((u >> (k - 3)) & 1u);
-      sb ^= msk & X->acol[rd->tpos[k]];
+      sb ^= msk & X->acol[rpos[k]];
     }
     const int nt = X->nterms;
     if (nt > 0) {
@@ -237,6 +238,27 @@ __device__ __forceinline__ XLane xsetup(CP<QRound> rd, CP<QXchg> X, uint32_t u, 
   }
   x.rb = swz(pbase ^ sb) * 8u;
   return x;
+}
+
+// The carried thread deposit across a round's swap slots: thread bit 4 + i sits at logical position
+// tpos[7 + i] in the input map and at tpos[i] in the output map.
+template <int NS>
+__device__ __forceinline__ uint32_t to_post(uint32_t j, CP<QRound> rk, uint32_t u) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const uint32_t b = (u >> (4 + i)) & 1u;
+    j = (j & ~(1u << rk->tpos[7 + i])) | (b << rk->tpos[i]);
+  }
+  return j;
+}
+template <int NS>
+__device__ __forceinline__ uint32_t to_pre(uint32_t j, CP<QRound> rk, uint32_t u) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const uint32_t b = (u >> (4 + i)) & 1u;
+    j = (j & ~(1u << rk->tpos[i])) | (b << rk->tpos[7 + i]);
+  }
+  return j;
 }
 
 // Writes statevectors SV0 and SV1 to LDS planes PL and PL + 1 in the writer mapping wr.
@@ -290,12 +312,12 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
 // holds only two planes per workgroup).
 template <int N, int T, int NSV, int EXS>
 __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         CP<QRound> wr, CP<QRound> rd, CP<QXchg> X, uint32_t u, uint32_t pbase,
-                                         uint32_t& jc) {
+                                         CP<uint32_t> woff, CP<int32_t> rpos, CP<QXchg> X, uint32_t u,
+                                         uint32_t pbase, uint32_t& jc) {
   static_assert(EXS == 2, "pairs of planes");
-  const Offs wo = load_offs(wr->woff), ro = load_offs(X->roff);
+  const Offs wo = load_offs(woff), ro = load_offs(X->roff);
   const bool sg = X->nterms != 0;
-  const XLane x = xsetup<N>(rd, X, u, pbase, jc);
+  const XLane x = xsetup<N>(rpos, X, u, pbase, jc);
 #pragma unroll
   for (int g = 0; g < NSV; g += 2) {
     if (g == 0) xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
@@ -311,6 +333,33 @@ __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], f
   }
 }
 
+// Swap slot I of statevectors [S0, S0 + NSV): register bit I trades places with lane bit 4 + I
+// (thread bit 4 + I).  For each register pair (r, r | 2^I) a cross-lane swap exchanges odd rows of
+// the first with even rows of the second (lane bit 4, permlane16_swap) or the upper half of the
+// first with the lower half of the second (lane bit 5, permlane32_swap); the value at (register
+// bit q', lane bit h') afterwards is the one that was at (q = h', h = q').  An involution.
+template <int I, int S0, int NSV>
+__device__ __forceinline__ void swap_slot(float (&sr)[8][8], float (&si)[8][8]) {
+#pragma unroll
+  for (int s = S0; s < S0 + NSV; ++s)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r & (1 << I)) continue;
+      const int r1 = r | (1 << I);
+      if (I == 0) {
+        const auto a = __builtin_amdgcn_permlane16_swap(__float_as_int(sr[s][r]), __float_as_int(sr[s][r1]), false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(__float_as_int(si[s][r]), __float_as_int(si[s][r1]), false, false);
+        sr[s][r] = __int_as_float(a[0]); sr[s][r1] = __int_as_float(a[1]);
+        si[s][r] = __int_as_float(b[0]); si[s][r1] = __int_as_float(b[1]);
+      } else {
+        const auto a = __builtin_amdgcn_permlane32_swap(__float_as_int(sr[s][r]), __float_as_int(sr[s][r1]), false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(__float_as_int(si[s][r]), __float_as_int(si[s][r1]), false, false);
+        sr[s][r] = __int_as_float(a[0]); sr[s][r1] = __int_as_float(a[1]);
+        si[s][r] = __int_as_float(b[0]); si[s][r1] = __int_as_float(b[1]);
+      }
+    }
+}
+
 // Forward gates of a round on statevectors S0, S0 + 1 (an absent gate is the identity entry):
 // gates01 applies the gates on register bits 0 and 1, gate2 the gate on bit 2 (gates on
 // different qubits commute, so the split point is free).
@@ -323,17 +372,33 @@ template <int S0>
 __device__ __forceinline__ void gate2(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
   apply_gate<2, S0, 1>(sr, si, R.c + 16); apply_gate<2, S0 + 1, 1>(sr, si, R.c + 16);
 }
-template <int S0>
+// The rest of a round after the bit-0/1 gates: the bit-2 gate, then the swap slots with their gates
+// (the statevectors end in the round's output mapping).
+template <int S0, int NS>
+__device__ __forceinline__ void finish(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+  gate2<S0>(sr, si, R);
+  if (NS > 0) {
+    swap_slot<0, S0, 2>(sr, si);
+    apply_gate<0, S0, 1>(sr, si, R.c + 24); apply_gate<0, S0 + 1, 1>(sr, si, R.c + 24);
+  }
+  if (NS > 1) {
+    swap_slot<1, S0, 2>(sr, si);
+    apply_gate<1, S0, 1>(sr, si, R.c + 32); apply_gate<1, S0 + 1, 1>(sr, si, R.c + 32);
+  }
+}
+template <int S0, int NS>
 __device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
   gates01<S0>(sr, si, R);
-  gate2<S0>(sr, si, R);
+  finish<S0, NS>(sr, si, R);
 }
 
-// Wave-reduces the round's three gate statistics and adds them to the per-wave LDS slots.
+// Wave-reduces the round's gate statistics (register bits 0..2, then the NS swap slots) and adds
+// them to the per-wave LDS slots.
+template <int NS>
 __device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __restrict__ slots, const float* q, int F,
                                                  int wave, int lane) {
 #pragma unroll
-  for (int bb = 0; bb < 3; ++bb) {
+  for (int bb = 0; bb < 3 + NS; ++bb) {
     const int gsrc = R.gid[bb];
     const float v4[4] = {q[3 * bb], q[3 * bb + 1], q[3 * bb + 2], 0.f};
     const float v = wave_reduce_scatter4(v4);
@@ -341,16 +406,29 @@ __device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __re
   }
 }
 
-// Adjoint gates of a round on the pair (C, 4 + C): psi_C and lambda_C <- U^H for its three gates.
-template <int C>
-__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R) {
+// Adjoint of a round on the pair (C, 4 + C), starting in the round's output mapping: the swap-slot
+// gates are pulled back first, each gate's statistic taken right after its pull-back (q[9 + 3i]),
+// the swaps undone, then the three register-bit gates pulled back (their statistics follow in
+// stat_accum, at the round input).
+template <int C, int NS>
+__device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R, float* q) {
+  if (NS > 1) {
+    apply_gate<1, C, 1>(sr, si, R.c + 32); apply_gate<1, 4 + C, 1>(sr, si, R.c + 32);
+    accum_s1<1, C>(sr, si, q + 12);
+    swap_slot<1, C, 1>(sr, si); swap_slot<1, 4 + C, 1>(sr, si);
+  }
+  if (NS > 0) {
+    apply_gate<0, C, 1>(sr, si, R.c + 24); apply_gate<0, 4 + C, 1>(sr, si, R.c + 24);
+    accum_s1<0, C>(sr, si, q + 9);
+    swap_slot<0, C, 1>(sr, si); swap_slot<0, 4 + C, 1>(sr, si);
+  }
   apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16);
   apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);
   apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);
 }
 
-// The pair's share of the round's three gate statistics, q[3 b + k] += S_k(bit b).  The gates of
-// one round act on different qubits and commute, so every gate's statistic may be taken with
+// The pair's share of the round's three register-bit gate statistics, q[3 b + k] += S_k(bit b).
+// These gates act on different qubits and commute, so every gate's statistic may be taken with
 // both statevectors at the round input (all three gates pulled back): then the pull-backs of the
 // other two gates cancel inside <lambda|sigma_b|psi>.
 template <int C>
@@ -360,33 +438,48 @@ __device__ __forceinline__ void stat_accum(const float (&sr)[8][8], const float 
   accum_s1<2, C>(sr, si, q + 6);
 }
 
+template <int NQ>
 __device__ __forceinline__ void pin_q(float* q) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(q[i]));
+  for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(q[i]));
 }
 
-// Adjoint gates of round rk on all four pairs, gate by gate, each gate's statistic flushed at
-// once (where no pipelining separates the pairs; keeps one gate's values live at a time).
+// One gate of round_adj_all: all eight statevectors <- U^H on register bit B, its statistic
+// flushed at once.
+template <int B>
+__device__ __forceinline__ void adj_gate_all(float (&sr)[8][8], float (&si)[8][8], int gsrc, CP<float> gtab, int F,
+                                             float* __restrict__ slots, int wave, int lane) {
+  const int gid = gsrc >= 0 ? gsrc : F;
+  float d[8], q6[6];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
+#pragma unroll
+  for (int e = 0; e < 6; ++e) q6[e] = 0.f;
+  apply_gate<B, 0, 8>(sr, si, d);
+  accum_s<B>(sr, si, q6);
+  const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
+  const float v = wave_reduce_scatter4(v4);
+  if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+}
+
+// Adjoint of round rk on all four pairs, gate by gate (where no pipelining separates the pairs;
+// keeps one gate's values live at a time): swap-slot gates and swaps in reverse, then the
+// register-bit gates.
+template <int NS>
 __device__ __forceinline__ void round_adj_all(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab,
                                               int F, float* __restrict__ slots, int wave, int lane) {
-#pragma unroll
-  for (int bb = 2; bb >= 0; --bb) {
-    const int gsrc = rk->gate[bb];
-    const int gid = gsrc >= 0 ? gsrc : F;
-    float d[8], q6[6];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
-#pragma unroll
-    for (int e = 0; e < 6; ++e) q6[e] = 0.f;
-    if (bb == 0) { apply_gate<0, 0, 8>(sr, si, d); accum_s<0>(sr, si, q6); }
-    if (bb == 1) { apply_gate<1, 0, 8>(sr, si, d); accum_s<1>(sr, si, q6); }
-    if (bb == 2) { apply_gate<2, 0, 8>(sr, si, d); accum_s<2>(sr, si, q6); }
-    const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
-    const float v = wave_reduce_scatter4(v4);
-    if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+  if (NS > 1) {
+    adj_gate_all<1>(sr, si, rk->sgate[1], gtab, F, slots, wave, lane);
+    swap_slot<1, 0, 8>(sr, si);
   }
+  if (NS > 0) {
+    adj_gate_all<0>(sr, si, rk->sgate[0], gtab, F, slots, wave, lane);
+    swap_slot<0, 0, 8>(sr, si);
+  }
+  adj_gate_all<2>(sr, si, rk->gate[2], gtab, F, slots, wave, lane);
+  adj_gate_all<1>(sr, si, rk->gate[1], gtab, F, slots, wave, lane);
+  adj_gate_all<0>(sr, si, rk->gate[0], gtab, F, slots, wave, lane);
 }
-
 
 // ---- angle encoding of one qubit ------------------------------------------------------------
 // Embedded single-qubit state e(b) (b = 0, 1) and its angle derivative d(b) for qubit q, with the
@@ -539,38 +632,40 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
     }
     // ---------------- forward rounds -------------------------------------------------------
+    constexpr int NS = swap_slots(N);
     uint32_t jc = deposit_thread<N>(u, rounds[0].tpos);   // thread bits in the current mapping
     if constexpr (EXS == 4) {
       // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
-      // (planes 2, 3).  Each group's LDS writes drain while the other group's gates run; every
-      // barrier separates a plane pair's reads from its next writes.
-      // Each slot: read one group, finish the other group's round (its bit-2 gate) and write it,
-      // then the bit-0/1 gates of the group just read.  The finishing gate covers the read
-      // latency and the writes drain under the following gates.
-      RoundCoef Rc = load_round<false>(rounds, gtab, F);
-      round_fwd<0>(sr, si, Rc);
+      // (planes 2, 3).  Each slot reads one group, finishes the other group's round (its bit-2
+      // gate and swap slots) and writes it, then runs the bit-0/1 gates of the group just read:
+      // the finishing work covers the read latency and the writes drain under the following
+      // gates.  Every barrier separates a plane pair's reads from its next writes.
+      RoundCoef Rc = load_round<false, NS>(rounds, gtab, F);
+      round_fwd<0, NS>(sr, si, Rc);
       gates01<2>(sr, si, Rc);
       if (R > 1) {
         Offs wo = load_offs(rounds[0].woff);
-        XLane x = xsetup<N>(rounds + 1, xf + 1, u, pbase, jc);
+        jc = to_post<NS>(jc, rounds, u);
+        XLane x = xsetup<N>(rounds[1].tpos, xf + 1, u, pbase, jc);
         xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
         for (int k = 1; k < R; ++k) {
           CP<QRound> rk = rounds + k;
-          const RoundCoef Rk = load_round<false>(rk, gtab, F);
+          const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
           const Offs ro = load_offs(xf[k].roff);
           const bool sg = xf[k].nterms != 0;
           __syncthreads();
           xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          gate2<2>(sr, si, Rc);                        // group B finishes round k - 1
+          finish<2, NS>(sr, si, Rc);                   // group B finishes round k - 1
           xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
           gates01<0>(sr, si, Rk);
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
           __syncthreads();
           xread<T, 2, 3, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          gate2<0>(sr, si, Rk);                        // group A finishes round k
+          finish<0, NS>(sr, si, Rk);                   // group A finishes round k
           if (k + 1 < R) {
             wo = load_offs(rk->woff);
-            x = xsetup<N>(rk + 1, xf + k + 1, u, pbase, jc);
+            jc = to_post<NS>(jc, rk, u);
+            x = xsetup<N>(rk[1].tpos, xf + k + 1, u, pbase, jc);
             xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
           }
           gates01<2>(sr, si, Rk);
@@ -579,20 +674,24 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         }
         __syncthreads();
       }
-      gate2<2>(sr, si, Rc);                            // group B finishes the last round
+      finish<2, NS>(sr, si, Rc);                       // group B finishes the last round
     } else {
       for (int k = 0; k < R; ++k) {
         CP<QRound> rk = rounds + k;
-        if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, rk - 1, rk, xf + k, u, pbase, jc);
-        const RoundCoef Rk = load_round<false>(rk, gtab, F);
-        round_fwd<0>(sr, si, Rk);
-        round_fwd<2>(sr, si, Rk);
+        if (k > 0) {
+          jc = to_post<NS>(jc, rk - 1, u);
+          exchange<N, T, 4, 2>(sr, si, buf, rk[-1].woff, rk->tpos, xf + k, u, pbase, jc);
+        }
+        const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
+        round_fwd<0, NS>(sr, si, Rk);
+        round_fwd<2, NS>(sr, si, Rk);
       }
     }
     // ---------------- readout ----------------------------------------------------------------
-    CP<QRound> rl = rounds + (R - 1);
+    CP<QRound> rl = rounds + (R - 1);   // the statevectors are in the last round's output mapping
+    jc = to_post<NS>(jc, rl, u);
     const uint32_t jl = jc;
-    const uint32_t l0 = rl->tpos[0], l1 = rl->tpos[1], l2 = rl->tpos[2];
+    const uint32_t l0 = rl->tpost[0], l1 = rl->tpost[1], l2 = rl->tpost[2];
     float acc[kMaxOut * 4];
 #pragma unroll
     for (int i = 0; i < kMaxOut * 4; ++i) acc[i] = 0.f;
@@ -731,18 +830,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       // statistics (covering the read latency), then pull the group just read back through the
       // round.  A round's statistics are flushed in the next round's first slot.
       CP<QRound> rl = rounds + (R - 1);
-      round_adj_all(sr, si, rl, gtab, F, slots, wave, lane);
+      round_adj_all<NS>(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
-        Offs wo = load_offs(rl->woff);
-        XLane x = xsetup<N>(rounds + (R - 2), xb + (R - 1), u, pbase, jc);
+        Offs wo = load_offs(rl->woffp);
+        jc = to_pre<NS>(jc, rl, u);
+        XLane x = xsetup<N>(rl[-1].tpost, xb + (R - 1), u, pbase, jc);
         xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
-        float q[9];
+        constexpr int NQ = 3 * (3 + NS);
+        float q[NQ];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) q[i] = 0.f;
-        RoundCoef Rq = load_round<true>(rl, gtab, F);   // gate ids of the round whose q is pending
+        for (int i = 0; i < NQ; ++i) q[i] = 0.f;
+        RoundCoef Rq = load_round<true, NS>(rl, gtab, F);   // gate ids of the round whose q is pending
         for (int k = R - 1; k >= 1; --k) {
           CP<QRound> rp = rounds + (k - 1);
-          const RoundCoef Rp = load_round<true>(rp, gtab, F);
+          const RoundCoef Rp = load_round<true, NS>(rp, gtab, F);
           const Offs ro = load_offs(xb[k].roff);
           const bool sg = xb[k].nterms != 0;
           __syncthreads();
@@ -750,45 +851,49 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           xwrite<T, 1, 5, 2>(sr, si, buf, wo, x.wb);
           if (k < R - 1) {                             // finish the previous round's statistics
             stat_accum<3>(sr, si, q);
-            round_stat_flush(Rq, slots, q, F, wave, lane);
+            round_stat_flush<NS>(Rq, slots, q, F, wave, lane);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) q[i] = 0.f;
+            for (int i = 0; i < NQ; ++i) q[i] = 0.f;
           }
-          round_adj<0>(sr, si, Rp);
-          pin_sv<0>(sr, si); pin_sv<4>(sr, si); pin_q(q);
+          round_adj<0, NS>(sr, si, Rp, q);
+          pin_sv<0>(sr, si); pin_sv<4>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 1, 5, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 2, 6, 0>(sr, si, buf, wo, x.wb);
           stat_accum<0>(sr, si, q);
-          round_adj<1>(sr, si, Rp);
-          pin_sv<1>(sr, si); pin_sv<5>(sr, si); pin_q(q);
+          round_adj<1, NS>(sr, si, Rp, q);
+          pin_sv<1>(sr, si); pin_sv<5>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 2, 6, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 3, 7, 2>(sr, si, buf, wo, x.wb);
           stat_accum<1>(sr, si, q);
-          round_adj<2>(sr, si, Rp);
-          pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q(q);
+          round_adj<2, NS>(sr, si, Rp, q);
+          pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 3, 7, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           stat_accum<2>(sr, si, q);
           if (k > 1) {
-            wo = load_offs(rp->woff);
-            x = xsetup<N>(rounds + (k - 2), xb + (k - 1), u, pbase, jc);
+            wo = load_offs(rp->woffp);
+            jc = to_pre<NS>(jc, rp, u);
+            x = xsetup<N>(rp[-1].tpost, xb + (k - 1), u, pbase, jc);
             xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
           }
-          round_adj<3>(sr, si, Rp);
-          pin_sv<3>(sr, si); pin_sv<7>(sr, si); pin_q(q);
+          round_adj<3, NS>(sr, si, Rp, q);
+          pin_sv<3>(sr, si); pin_sv<7>(sr, si); pin_q<NQ>(q);
           Rq = Rp;
         }
         stat_accum<3>(sr, si, q);                      // round 0's last group
-        round_stat_flush(Rq, slots, q, F, wave, lane);
+        round_stat_flush<NS>(Rq, slots, q, F, wave, lane);
         __syncthreads();
       }
     } else {
       for (int k = R - 1; k >= 0; --k) {
         CP<QRound> rk = rounds + k;
-        round_adj_all(sr, si, rk, gtab, F, slots, wave, lane);
-        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk, rk - 1, xb + k, u, pbase, jc);
+        round_adj_all<NS>(sr, si, rk, gtab, F, slots, wave, lane);
+        if (k > 0) {
+          jc = to_pre<NS>(jc, rk, u);
+          exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, rk[-1].tpost, xb + k, u, pbase, jc);
+        }
       }
     }
   }

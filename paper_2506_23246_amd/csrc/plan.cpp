@@ -91,16 +91,24 @@ uint32_t qform(const std::vector<std::pair<uint32_t, uint32_t>>& terms, uint32_t
   return s;
 }
 
-// Thread-bit order for a round: register bits first, then the remaining positions chosen so
-// that each group of four consecutive lane bits lands on distinct position residues mod 4
-// (the LDS swizzle folds higher nibbles into the low four bits).
-void make_tpos(int n, const int reg[3], int32_t* tpos) {
+// Thread-bit order for a round: register bits first, then any fixed thread-bit placements
+// (qubits of the swap slots), then the remaining positions chosen so that each group of four
+// consecutive lane bits lands on distinct position residues mod 4 (the LDS swizzle folds higher
+// nibbles into the low four bits).  fixed[k] >= 0 pins thread position k (k >= 3).
+void make_tpos(int n, const int reg[3], const int* fixed, int32_t* tpos) {
   bool used[16] = {false};
+  for (int k = 0; k < 16; ++k) tpos[k] = -1;
   for (int i = 0; i < 3; ++i) { tpos[i] = reg[i]; used[reg[i]] = true; }
-  int k = 3;
+  for (int k = 3; k < n; ++k)
+    if (fixed && fixed[k] >= 0) { tpos[k] = fixed[k]; used[fixed[k]] = true; }
   int group_mask = 0;
-  while (k < n) {
-    if (((k - 3) & 3) == 0) group_mask = 0;
+  for (int k = 3; k < n; ++k) {
+    if (((k - 3) & 3) == 0) {
+      group_mask = 0;
+      for (int j = k; j < k + 4 && j < n; ++j)
+        if (tpos[j] >= 0) group_mask |= 1 << (tpos[j] & 3);
+    }
+    if (tpos[k] >= 0) continue;
     int pick = -1;
     for (int p = 0; p < n; ++p)
       if (!used[p] && !((group_mask >> (p & 3)) & 1)) { pick = p; break; }
@@ -109,9 +117,9 @@ void make_tpos(int n, const int reg[3], int32_t* tpos) {
         if (!used[p]) { pick = p; break; }
     used[pick] = true;
     group_mask |= 1 << (pick & 3);
-    tpos[k++] = pick;
+    tpos[k] = pick;
   }
-  for (; k < 16; ++k) tpos[k] = 0;
+  for (int k = n; k < 16; ++k) tpos[k] = 0;
 }
 
 uint32_t jr_of(const int32_t* tpos, int r) {
@@ -370,16 +378,34 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   Affine pending;
   pending.init(n);
   bool have_pending = false;
-  auto push_round = [&](const int* gate_ids, const int* reg) {
+  const int nsw = swap_slots(n);
+  auto push_round = [&](const int* gate_ids, const int* reg, const int* sgate_ids, const int* spos) {
     QRound R{};
     for (int i = 0; i < 3; ++i) R.gate[i] = gate_ids[i];
-    make_tpos(n, reg, R.tpos);
-    for (int r = 0; r < 8; ++r) R.woff[r] = 8u * lds_swizzle(jr_of(R.tpos, r));   // complex64 bytes
+    int fixed[16];
+    for (int k = 0; k < 16; ++k) fixed[k] = -1;
+    for (int i = 0; i < 2; ++i) {
+      R.sgate[i] = i < nsw ? sgate_ids[i] : -1;
+      if (i < nsw) fixed[3 + 4 + i] = spos[i];
+    }
+    make_tpos(n, reg, fixed, R.tpos);
+    for (int k = 0; k < 16; ++k) R.tpost[k] = R.tpos[k];
+    for (int i = 0; i < nsw; ++i) std::swap(R.tpost[i], R.tpost[3 + 4 + i]);
+    for (int r = 0; r < 8; ++r) {
+      R.woff[r] = 8u * lds_swizzle(jr_of(R.tpost, r));    // complex64 bytes
+      R.woffp[r] = 8u * lds_swizzle(jr_of(R.tpos, r));
+    }
     hp->rounds.push_back(R);
     round_ent.push_back(pending);
     round_has_ent.push_back(have_pending);
     pending.init(n);
     have_pending = false;
+  };
+  // any nsw distinct positions other than reg[] (for rounds whose swap slots carry no gate)
+  auto free_spos = [&](const int* reg, int* spos) {
+    int c = 0;
+    for (int p = 0; p < n && c < nsw; ++p)
+      if (p != reg[0] && p != reg[1] && p != reg[2]) spos[c++] = p;
   };
   for (auto& s : stages) {
     if (!s.rot) {
@@ -404,48 +430,60 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
       continue;
     }
     if (have_pending && hp->rounds.empty()) {   // leading entangler: empty round first
-      int none[3] = {-1, -1, -1};
-      int reg[3] = {0, 1, 2};
+      int none[3] = {-1, -1, -1}, snone[2] = {-1, -1};
+      int reg[3] = {0, 1, 2}, spos[2] = {0, 0};
+      free_spos(reg, spos);
       Affine keep = pending;
       bool hk = have_pending;
       pending.init(n);
       have_pending = false;
-      push_round(none, reg);
+      push_round(none, reg, snone, spos);
       pending = keep;
       have_pending = hk;
     }
-    // fused gates of the stage sorted by qubit, in chunks of three
+    // fused gates of the stage sorted by qubit, in chunks of 3 + nsw: three on the register bits,
+    // the rest on the swap slots
     std::vector<int> ids;
     for (auto& kv : s.fused_of_qubit) ids.push_back(kv.second);
     std::sort(ids.begin(), ids.end(), [&](int a, int b) { return hp->fused[a].qubit < hp->fused[b].qubit; });
-    for (size_t c0 = 0; c0 < ids.size(); c0 += 3) {
-      int gid[3] = {-1, -1, -1}, reg[3] = {-1, -1, -1};
+    const size_t cap = 3 + (size_t)nsw;
+    for (size_t c0 = 0; c0 < ids.size(); c0 += cap) {
+      int gid[3] = {-1, -1, -1}, reg[3] = {-1, -1, -1}, sgid[2] = {-1, -1}, spos[2] = {-1, -1};
       bool used[16] = {false};
       int cnt = 0;
-      for (size_t i = c0; i < ids.size() && i < c0 + 3; ++i) {
-        gid[cnt] = ids[i];
-        reg[cnt] = n - 1 - hp->fused[ids[i]].qubit;
-        used[reg[cnt]] = true;
-        cnt++;
+      for (size_t i = c0; i < ids.size() && i < c0 + cap; ++i, ++cnt) {
+        const int pos = n - 1 - hp->fused[ids[i]].qubit;
+        if (cnt < 3) { gid[cnt] = ids[i]; reg[cnt] = pos; } else { sgid[cnt - 3] = ids[i]; spos[cnt - 3] = pos; }
+        used[pos] = true;
       }
-      for (int i = cnt; i < 3; ++i) {   // pad with unused positions near the used ones
-        int best = -1;
-        for (int p = 0; p < n && best < 0; ++p)
-          if (!used[p]) best = p;
-        reg[i] = best;
-        used[best] = true;
-      }
-      push_round(gid, reg);
+      for (int i = 0; i < 3; ++i)   // pad with unused positions
+        if (reg[i] < 0) {
+          int best = -1;
+          for (int p = 0; p < n && best < 0; ++p)
+            if (!used[p]) best = p;
+          reg[i] = best;
+          used[best] = true;
+        }
+      for (int i = 0; i < nsw; ++i)
+        if (spos[i] < 0) {
+          int best = -1;
+          for (int p = 0; p < n && best < 0; ++p)
+            if (!used[p]) best = p;
+          spos[i] = best;
+          used[best] = true;
+        }
+      push_round(gid, reg, sgid, spos);
     }
   }
   if (hp->rounds.empty()) {   // no rotations at all: one empty round
-    int none[3] = {-1, -1, -1};
-    int reg[3] = {0, 1, 2};
+    int none[3] = {-1, -1, -1}, snone[2] = {-1, -1};
+    int reg[3] = {0, 1, 2}, spos[2] = {0, 0};
+    free_spos(reg, spos);
     Affine keep = pending;
     bool hk = have_pending;
     pending.init(n);
     have_pending = false;
-    push_round(none, reg);
+    push_round(none, reg, snone, spos);
     pending = keep;
     have_pending = hk;
   }
@@ -475,7 +513,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     fill_xchg(&hp->xf[k], n, a.acol, a, false, hp->rounds[k].tpos);
     uint32_t inv[16];
     if (!gf2_inverse(a.acol, n, inv)) { *status = QP_EINVAL; return "singular entangler map"; }
-    fill_xchg(&hp->xb[k], n, inv, a, true, hp->rounds[k - 1].tpos);
+    fill_xchg(&hp->xb[k], n, inv, a, true, hp->rounds[k - 1].tpost);
     hp->n_exchanges++;
   }
 

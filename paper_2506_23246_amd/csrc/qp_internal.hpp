@@ -36,13 +36,24 @@ constexpr int kGS = 4;
 // adjoint reads its coefficients as they are used.
 constexpr int kGT = 16;
 
-struct alignas(16) QRound {
-  int32_t gate[3];    // fused-gate id applied on register bit b (-1: none)
-  int32_t pad0;
-  int32_t tpos[16];   // logical index-bit position of physical bit k
-  uint32_t woff[8];   // 8 * lds_swizzle of register r's logical offset: byte offset, writer side
-};
+// Swap slots of a round: after its three register-bit gates, register bit i (i < swap_slots(n))
+// trades places with thread bit 4 + i (lane bit 4 or 5 of the wave, by a cross-lane swap of
+// register pairs), and gate sgate[i] acts on the qubit brought in.  They are used where they turn
+// a rotation stage into rounds without identity slots (8 qubits: 4 + 4; 10 qubits: 5 + 5 instead
+// of 3 + 3 + 3 + 1).  Where a stage already fills three-gate rounds (6, 9, 12 qubits) or would
+// still leave an empty slot (11), saving an exchange does not pay for the swaps (measured at 12).
+QP_HD inline constexpr int swap_slots(int n) { return n == 10 ? 2 : (n == 8 ? 1 : 0); }
 
+struct alignas(16) QRound {
+  int32_t gate[3];    // fused-gate id applied on register bit b in the round's input mapping (-1: none)
+  int32_t pad0;
+  int32_t sgate[2];   // fused-gate id applied on register bit i after swap slot i (-1: none)
+  int32_t pad1[2];
+  int32_t tpos[16];   // input mapping: logical index-bit position of physical bit k
+  int32_t tpost[16];  // output mapping (tpos with the swap slots applied)
+  uint32_t woff[8];   // 8 * lds_swizzle of register r's offset in the output mapping (forward writer)
+  uint32_t woffp[8];  // the same in the input mapping (writer of the reverse exchange)
+};
 // One direction of the register exchange that precedes a round.  Reader thread (u, r) in the
 // read mapping holds logical index jn = base(u) ^ jr(r); it takes the amplitude stored at
 // src = A jn (A over GF(2), given by its columns), times (-1)^Q(x), where x = jn (sign in the
@@ -63,7 +74,7 @@ struct alignas(16) QXchg {
   uint32_t roff[8];   // 8 * lds_swizzle of register r's uniform source offset: byte offset, reader side
 };
 static_assert(sizeof(QXchg) == 432, "QXchg layout");
-static_assert(sizeof(QRound) == 112, "QRound layout");
+static_assert(sizeof(QRound) == 224, "QRound layout");
 
 // Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).
 struct alignas(16) QFused {

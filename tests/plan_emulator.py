@@ -20,12 +20,13 @@ HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused",
                 ("coord", "<i4", 16), ("zmask", "<u4", 8), ("off_rounds", "<i4"), ("off_xf", "<i4"),
                 ("off_xb", "<i4"), ("off_fused", "<i4"), ("off_csr_ptr", "<i4"), ("off_csr_idx", "<i4"),
                 ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4")])
-ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("tpos", "<i4", 16), ("woff", "<u4", 8)])
+ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("sgate", "<i4", 2), ("pad1", "<i4", 2),
+                  ("tpos", "<i4", 16), ("tpost", "<i4", 16), ("woff", "<u4", 8), ("woffp", "<u4", 8)])
 XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("qv", "<u4", 32), ("ue", "<u4", 3),
                  ("ve", "<u4", 3), ("nterms", "<u4"), ("sign_at_src", "<u4"), ("qsign_r", "<u4"), ("identity", "<u4"),
                  ("pad1", "<u4", 2), ("roff", "<u4", 8)])
 FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3)])
-assert ROUND.itemsize == 112 and XCHG.itemsize == 432 and FUSED.itemsize == 32
+assert ROUND.itemsize == 224 and XCHG.itemsize == 432 and FUSED.itemsize == 32
 
 
 def plan_image(circ):
@@ -84,20 +85,38 @@ def _fused_matrix(f, params):
     return U
 
 
-def _exchange(regs, wr, rd, X, n, TP):
-    """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point)."""
+def _swap_slots(n):
+    return 2 if n == 10 else (1 if n == 8 else 0)
+
+
+def _swap(regs, i):
+    """Swap slot i: register bit i trades places with thread bit 4 + i (a relabelling)."""
+    out = np.empty_like(regs)
+    TP = regs.shape[1]
+    for u in range(TP):
+        for r in range(8):
+            rb, ub = (r >> i) & 1, (u >> (4 + i)) & 1
+            u2 = (u & ~(1 << (4 + i))) | (rb << (4 + i))
+            r2 = (r & ~(1 << i)) | (ub << i)
+            out[:, u2, r2] = regs[:, u, r]
+    return out
+
+
+def _exchange(regs, wpos, rpos, X, n, TP):
+    """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point); wpos/rpos are
+    the writer's and reader's physical-to-logical bit maps."""
     S = regs.shape[0]
     buf = np.zeros((S, 1 << n), complex)
     for u in range(TP):
-        jw = _deposit(u, wr["tpos"], n)
+        jw = _deposit(u, wpos, n)
         for r in range(8):
-            buf[:, jw ^ _regoff(r, wr["tpos"])] = regs[:, u, r]
+            buf[:, jw ^ _regoff(r, wpos)] = regs[:, u, r]
     out = np.zeros_like(regs)
     for u in range(TP):
-        jn = _deposit(u, rd["tpos"], n)
+        jn = _deposit(u, rpos, n)
         if X["identity"]:
             sb = jn
-            srcr = [_regoff(r, rd["tpos"]) for r in range(8)]
+            srcr = [_regoff(r, rpos) for r in range(8)]
             sg = [0] * 8
         else:
             sb = 0
@@ -179,14 +198,20 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
                 amp = amp * e
             regs[0, u, r] = amp
             regs[1:4, u, r] = der
+    nsw = _swap_slots(n)
     for k in range(R):
         if k > 0:
-            regs[:4] = _exchange(regs[:4], rounds[k - 1], rounds[k], xf[k], n, TP)
+            regs[:4] = _exchange(regs[:4], rounds[k - 1]["tpost"], rounds[k]["tpos"], xf[k], n, TP)
         for b in range(3):
             g = int(rounds[k]["gate"][b])
             if g >= 0:
                 _apply(regs, slice(0, 4), b, Us[g])
-    tl = rounds[R - 1]["tpos"]
+        for i in range(nsw):
+            regs[:4] = _swap(regs[:4], i)
+            g = int(rounds[k]["sgate"][i])
+            if g >= 0:
+                _apply(regs, slice(0, 4), i, Us[g])
+    tl = rounds[R - 1]["tpost"]
     f = np.zeros(m)
     gg = np.zeros((m, 3))
     z = np.zeros((m, TP, 8))
@@ -210,6 +235,25 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
     M = np.zeros((len(fused), 2, 2), complex)
     S = np.zeros((len(fused), 3))
     for k in range(R - 1, -1, -1):
+        for i in reversed(range(nsw)):   # swap-slot gates, then undo the swaps
+            g = int(rounds[k]["sgate"][i])
+            if g >= 0:
+                Ud = Us[g].conj().T
+                _apply(regs, slice(0, 4), i, Ud)
+                for r in range(8):
+                    if r & (1 << i):
+                        continue
+                    r1 = r | (1 << i)
+                    for sv in range(4):
+                        x0, x1 = regs[4 + sv, :, r], regs[4 + sv, :, r1]
+                        y0, y1 = regs[sv, :, r], regs[sv, :, r1]
+                        M[g, 0, 0] += np.sum(np.conj(x0) * y0)
+                        M[g, 0, 1] += np.sum(np.conj(x0) * y1)
+                        M[g, 1, 0] += np.sum(np.conj(x1) * y0)
+                        M[g, 1, 1] += np.sum(np.conj(x1) * y1)
+                _apply(regs, slice(4, 8), i, Ud)
+                _stats(regs, i, S[g])
+            regs = _swap(regs, i)
         for b in (2, 1, 0):
             g = int(rounds[k]["gate"][b])
             if g < 0:
@@ -236,7 +280,7 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
                 if g >= 0:
                     _stats(regs, b, S[g])
         if k > 0:
-            regs = _exchange(regs, rounds[k], rounds[k - 1], xb[k], n, TP)
+            regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], n, TP)
     return f, gg, M, S
 
 

@@ -50,13 +50,15 @@ def test_emulated_plan_matches_oracle_on_configs(k):
     _run(w.circuit, np.asarray(w.params, np.float64), np.asarray(w.points, np.float64))
 
 
-@pytest.mark.parametrize("n", [3, 4, 5, 7])
+@pytest.mark.parametrize("n", [3, 4, 5, 7, 9, 10, 12])
 def test_emulated_plan_mixed_entanglers(n):
+    """Mixed CNOT/CZ rings of several strides; 10 qubits exercise two swap slots per round."""
     rng = np.random.default_rng(n)
     rings = [W.ring(n, W.CNOT, 1) + W.ring(n, W.CZ, 2), W.ring(n, W.CZ, 1), W.ring(n, W.CNOT, 2)]
-    circ = W.layered(n, 3, "xyz", lambda l: rings[l], out_qubits=[0, n - 1, n // 2])
+    layers = 3 if n <= 10 else 2
+    circ = W.layered(n, layers, "xyz", lambda l: rings[l], out_qubits=[0, n - 1, n // 2])
     params = rng.uniform(0, 2 * math.pi, circ.n_params)
-    pts = rng.uniform(-1, 1, (2, 3))
+    pts = rng.uniform(-1, 1, (2 if n <= 10 else 1, 3))
     _run(circ, params, pts)
 
 
@@ -67,20 +69,43 @@ def _swz(i):
 @pytest.mark.parametrize("k", [1, 2, 4])
 def test_plan_lds_offset_tables(k):
     """The planner's swizzled LDS byte offsets: writer side woff[r] = 8 swz(register offset of r in
-    the round's mapping); reader side roff[r] = 8 swz(uniform source offset), which for an identity
-    exchange is the reader round's own register offset.  swz must also be linear over GF(2),
-    which the kernel's address arithmetic relies on."""
+    the round's output mapping) and woffp[r] the same in its input mapping; reader side
+    roff[r] = 8 swz(uniform source offset), which for an identity exchange is the reader's own
+    register offset (forward exchanges read into a round's input mapping, reverse ones into the
+    previous round's output mapping).  swz must also be linear over GF(2), which the kernel's
+    address arithmetic relies on."""
     from tests.plan_emulator import _regoff, plan_image
     plan = plan_image(W.config(k, P=1).circuit)
     rounds = plan["rounds"]
     for rd in rounds:
         for r in range(8):
-            assert int(rd["woff"][r]) == 8 * _swz(_regoff(r, rd["tpos"]))
+            assert int(rd["woff"][r]) == 8 * _swz(_regoff(r, rd["tpost"]))
+            assert int(rd["woffp"][r]) == 8 * _swz(_regoff(r, rd["tpos"]))
     for kk in range(1, len(rounds)):
-        for X, read in ((plan["xf"][kk], rounds[kk]), (plan["xb"][kk], rounds[kk - 1])):
+        for X, read in ((plan["xf"][kk], rounds[kk]["tpos"]), (plan["xb"][kk], rounds[kk - 1]["tpost"])):
             for r in range(8):
-                src = _regoff(r, read["tpos"]) if X["identity"] else int(X["src_r"][r])
+                src = _regoff(r, read) if X["identity"] else int(X["src_r"][r])
                 assert int(X["roff"][r]) == 8 * _swz(src)
     rng = np.random.default_rng(0)
     for a, b in rng.integers(0, 1 << 12, (200, 2)):
         assert _swz(int(a) ^ int(b)) == _swz(int(a)) ^ _swz(int(b))
+
+
+@pytest.mark.parametrize("n", [8, 9, 10, 11, 12])
+def test_plan_swap_slots(n):
+    """Rounds of a full rotation stage fill the register bits and the swap slots: n = 8, 9, 10, 11, 12
+    need 2, 3, 2, 4, 4 rounds per layer (swap slots at 8 and 10 qubits only); the output mapping
+    is the input mapping with register bit i and thread bit 4 + i exchanged for every swap slot."""
+    from tests.plan_emulator import _swap_slots, plan_image
+    circ = W.layered(n, 2, "xyz", lambda l: W.ring(n, W.CNOT, 1), out_qubits=[0, 1, 2])
+    plan = plan_image(circ)
+    rounds = plan["rounds"]
+    per_layer = {8: 2, 9: 3, 10: 2, 11: 4, 12: 4}[n]
+    assert len(rounds) == 2 * per_layer
+    nsw = _swap_slots(n)
+    for rd in rounds:
+        t, tp = list(rd["tpos"][:n]), list(rd["tpost"][:n])
+        assert sorted(t) == list(range(n))
+        for i in range(nsw):
+            t[i], t[7 + i] = t[7 + i], t[i]
+        assert t == tp
