@@ -42,12 +42,14 @@ def flops_per_point(n_fused: int, n: int) -> float:
     return float(n_fused) * (2 ** n) * 256
 
 
-def executed_flops_per_point(n_fused: int, n: int) -> float:
+def executed_flops_per_point(n_fused: int, n: int, n_folded: int = 0) -> float:
     """Flops the kernel executes for the same work with mul = 1 and fma = 2: 14 per amplitude
     per statevector and gate (1 mul + 3 fma per real part), and the gate statistic
     S_k = Im <lambda|sigma_k|psi> at 4 statevector pairs x 3 components x 4 fma x 2 per pair =
-    48 per amplitude: (4 x 14 + 8 x 14 + 48) = 216 per amplitude per gate."""
-    return float(n_fused) * (2 ** n) * 216
+    48 per amplitude: (4 x 14 + 8 x 14 + 48) = 216 per amplitude per gate.  The n_folded gates of
+    an opening rotation stage are folded into the product-state encoding: they are neither applied
+    nor pulled back (only their statistic, 48, remains)."""
+    return (2 ** n) * (float(n_fused) * 216 - float(n_folded) * 168)
 
 
 def sources_digest() -> str:
@@ -161,7 +163,11 @@ def main():
         arr, bufs = batch.io([w.params for w in ws_list], [w.points for w in ws_list])
         P_total = sum(len(w.points) for w in ws_list)
         flops = sum(flops_per_point(w.circuit.n_params // 3, w.circuit.n) * len(w.points) for w in ws_list)
-        flops_x = sum(executed_flops_per_point(w.circuit.n_params // 3, w.circuit.n) * len(w.points) for w in ws_list)
+        flops_x = 0.0
+        for w in ws_list:
+            cq = Circuit(ctx, w.circuit)
+            flops_x += executed_flops_per_point(cq.info(3), w.circuit.n, cq.info(12)) * len(w.points)
+            cq.close()
 
         def step():
             batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), flags=0)
@@ -182,7 +188,7 @@ def main():
                 "grad": torch.empty(w.circuit.n_params, dtype=torch.float32, device=dev)}
         F = c.info(3)
         flops = flops_per_point(F, w.circuit.n) * P_total
-        flops_x = executed_flops_per_point(F, w.circuit.n) * P_total
+        flops_x = executed_flops_per_point(F, w.circuit.n, c.info(12)) * P_total
 
         def step():
             c.maxwell(prm, pts, w.loss, bufs=bufs)
@@ -190,6 +196,7 @@ def main():
             c.maxwell(prm, pts, w.loss, bufs=bufs, flags=L.QP_FLAG_TUNE)
         cfg = {"workload": w.name, "n_qubits": w.circuit.n, "layers": w.circuit.n_params // (3 * w.circuit.n),
                "points": P_total, "params": w.circuit.n_params, "fused_gates": F, "rounds": c.info(4),
+               "rounds_folded_into_encoding": c.info(11),
                "threads_per_wg": c.info(6), "points_per_tile": c.info(7), "lds_exchange_planes": c.info(8),
                "wg_per_cu": c.info(9), "loss": {0: "vacuum", 1: "dielectric split", 2: "dielectric intuitive"}[w.loss.kind]}
 

@@ -136,7 +136,9 @@ qp_status qp_circuit_compile(qp_ctx* ctx, const qp_circuit_desc* desc, qp_circui
 void qp_circuit_destroy(qp_circuit* c);
 /* what: 0 n_qubits, 1 n_params, 2 n_out, 3 fused gates, 4 rounds, 5 register-exchange count,
  *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile,
- *       8 LDS exchange planes, 9 persistent workgroups per CU, 10 dense 2^5 blocks        */
+ *       8 LDS exchange planes, 9 persistent workgroups per CU, 10 dense 2^5 blocks,
+ *       11 leading rounds folded into the encoding (an opening rotation stage acts on the
+ *       product state), 12 fused gates in those rounds.  -1 for an unknown code.            */
 int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
 
 /* Launch shape of the fused kernel for this circuit (what the autotuner sets): exchange_planes

@@ -184,6 +184,13 @@ extern "C" int64_t qp_circuit_info(const qp_circuit* c, int32_t what) {
     case 8: return c->exs;
     case 9: return c->wg_per_cu;
     case 10: return c->hp.dense_ok ? (int64_t)c->hp.dgroups.size() : 0;
+    case 11: return c->hp.fused_ok ? c->hp.n_head : 0;
+    case 12: {
+      int64_t h = 0;
+      if (c->hp.fused_ok)
+        for (const auto& f : c->hp.fused) h += f.stat_out ? 1 : 0;
+      return h;
+    }
     default: return -1;
   }
 }

@@ -148,6 +148,11 @@ struct XLane {
 template <typename V>
 __device__ __forceinline__ void pin_sgpr(V& v) { asm volatile("" : "+s"(v)); }
 
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
 // Marks statevector S as computed at this point of the instruction stream: keeps the compiler
 // from sinking a group's gate arithmetic past the following barrier, which would undo the
 // overlap of that group's arithmetic with another group's LDS traffic.
@@ -409,22 +414,25 @@ __device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __re
 // Adjoint of a round on the pair (C, 4 + C), starting in the round's output mapping: the swap-slot
 // gates are pulled back first, each gate's statistic taken right after its pull-back (q[9 + 3i]),
 // the swaps undone, then the three register-bit gates pulled back (their statistics follow in
-// stat_accum, at the round input).
-template <int C, int NS>
+// stat_accum, at the round input).  PULL = false (a round of the leading stage): nothing is pulled
+// back; every statistic is taken at the stage output, where the stage's gates all commute.
+template <int C, int NS, bool PULL = true>
 __device__ __forceinline__ void round_adj(float (&sr)[8][8], float (&si)[8][8], const RoundCoef& R, float* q) {
   if (NS > 1) {
-    apply_gate<1, C, 1>(sr, si, R.c + 32); apply_gate<1, 4 + C, 1>(sr, si, R.c + 32);
+    if (PULL) { apply_gate<1, C, 1>(sr, si, R.c + 32); apply_gate<1, 4 + C, 1>(sr, si, R.c + 32); }
     accum_s1<1, C>(sr, si, q + 12);
     swap_slot<1, C, 1>(sr, si); swap_slot<1, 4 + C, 1>(sr, si);
   }
   if (NS > 0) {
-    apply_gate<0, C, 1>(sr, si, R.c + 24); apply_gate<0, 4 + C, 1>(sr, si, R.c + 24);
+    if (PULL) { apply_gate<0, C, 1>(sr, si, R.c + 24); apply_gate<0, 4 + C, 1>(sr, si, R.c + 24); }
     accum_s1<0, C>(sr, si, q + 9);
     swap_slot<0, C, 1>(sr, si); swap_slot<0, 4 + C, 1>(sr, si);
   }
-  apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16);
-  apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);
-  apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);
+  if (PULL) {
+    apply_gate<2, C, 1>(sr, si, R.c + 16); apply_gate<2, 4 + C, 1>(sr, si, R.c + 16);
+    apply_gate<1, C, 1>(sr, si, R.c + 8);  apply_gate<1, 4 + C, 1>(sr, si, R.c + 8);
+    apply_gate<0, C, 1>(sr, si, R.c);      apply_gate<0, 4 + C, 1>(sr, si, R.c);
+  }
 }
 
 // The pair's share of the round's three register-bit gate statistics, q[3 b + k] += S_k(bit b).
@@ -444,18 +452,21 @@ __device__ __forceinline__ void pin_q(float* q) {
   for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(q[i]));
 }
 
-// One gate of round_adj_all: all eight statevectors <- U^H on register bit B, its statistic
-// flushed at once.
-template <int B>
+// One gate of round_adj_all: all eight statevectors <- U^H on register bit B (unless PULL is
+// false: a gate of the leading stage), its statistic flushed at once.
+template <int B, bool PULL>
 __device__ __forceinline__ void adj_gate_all(float (&sr)[8][8], float (&si)[8][8], int gsrc, CP<float> gtab, int F,
                                              float* __restrict__ slots, int wave, int lane) {
-  const int gid = gsrc >= 0 ? gsrc : F;
-  float d[8], q6[6];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
+  float q6[6];
 #pragma unroll
   for (int e = 0; e < 6; ++e) q6[e] = 0.f;
-  apply_gate<B, 0, 8>(sr, si, d);
+  if (PULL) {
+    const int gid = gsrc >= 0 ? gsrc : F;
+    float d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
+    apply_gate<B, 0, 8>(sr, si, d);
+  }
   accum_s<B>(sr, si, q6);
   const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
   const float v = wave_reduce_scatter4(v4);
@@ -465,32 +476,34 @@ __device__ __forceinline__ void adj_gate_all(float (&sr)[8][8], float (&si)[8][8
 // Adjoint of round rk on all four pairs, gate by gate (where no pipelining separates the pairs;
 // keeps one gate's values live at a time): swap-slot gates and swaps in reverse, then the
 // register-bit gates.
-template <int NS>
+template <int NS, bool PULL>
 __device__ __forceinline__ void round_adj_all(float (&sr)[8][8], float (&si)[8][8], CP<QRound> rk, CP<float> gtab,
                                               int F, float* __restrict__ slots, int wave, int lane) {
   if (NS > 1) {
-    adj_gate_all<1>(sr, si, rk->sgate[1], gtab, F, slots, wave, lane);
+    adj_gate_all<1, PULL>(sr, si, rk->sgate[1], gtab, F, slots, wave, lane);
     swap_slot<1, 0, 8>(sr, si);
   }
   if (NS > 0) {
-    adj_gate_all<0>(sr, si, rk->sgate[0], gtab, F, slots, wave, lane);
+    adj_gate_all<0, PULL>(sr, si, rk->sgate[0], gtab, F, slots, wave, lane);
     swap_slot<0, 0, 8>(sr, si);
   }
-  adj_gate_all<2>(sr, si, rk->gate[2], gtab, F, slots, wave, lane);
-  adj_gate_all<1>(sr, si, rk->gate[1], gtab, F, slots, wave, lane);
-  adj_gate_all<0>(sr, si, rk->gate[0], gtab, F, slots, wave, lane);
+  adj_gate_all<2, PULL>(sr, si, rk->gate[2], gtab, F, slots, wave, lane);
+  adj_gate_all<1, PULL>(sr, si, rk->gate[1], gtab, F, slots, wave, lane);
+  adj_gate_all<0, PULL>(sr, si, rk->gate[0], gtab, F, slots, wave, lane);
 }
 
 // ---- angle encoding of one qubit ------------------------------------------------------------
 // Embedded single-qubit state e(b) (b = 0, 1) and its angle derivative d(b) for qubit q, with the
-// Jacobian d theta_q / d(t, x, y).  RY: e = (cos, sin), RX: e = (cos, -i sin), of theta/2.
+// Jacobian d theta_q / d(t, x, y).  RY: e = (cos, sin), RX: e = (cos, -i sin), of theta/2.  When the
+// circuit opens with a rotation stage, the qubit's gate U of that stage is applied here (e <- U e,
+// d <- U d): the stage acts on the product state, so the state after it is still a product.
 struct QEnc {
-  float e0, e1r, e1i, d0, d1r, d1i, j[3];
+  float e0r, e0i, e1r, e1i, d0r, d0i, d1r, d1i, j[3];
 };
 
 template <int N>
-__device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, const FusedArgs& a, long long pt, bool valid,
-                                             const float* p3, int q) {
+__device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, CP<float> gtab, const FusedArgs& a, long long pt,
+                                             bool valid, const float* p3, int q) {
   float c, s, j0 = 0.f, j1 = 0.f, j2 = 0.f;
   if (plan->enc_kind == QP_ENC_CYCLE) {
     const int cc = plan->coord_of_qubit[q];
@@ -527,12 +540,26 @@ __device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, const FusedArgs&
     sincosf(0.5f * th, &s, &c);
   }
   QEnc E;
-  E.e0 = c;
-  E.d0 = -0.5f * s;
+  E.e0r = c; E.e0i = 0.f;
+  E.d0r = -0.5f * s; E.d0i = 0.f;
   if (plan->enc_gate == QP_ENC_RY) {
     E.e1r = s; E.e1i = 0.f; E.d1r = 0.5f * c; E.d1i = 0.f;
   } else {   // RX|0> = (cos, -i sin)
     E.e1r = 0.f; E.e1i = -s; E.d1r = 0.f; E.d1i = -0.5f * c;
+  }
+  const int hg = plan->head_gate[q];
+  if (hg >= 0) {
+    CP<float> g = gtab + hg * kGT;   // U: u00r, u00i, u01r, u01i, u10r, u10i, u11r, u11i
+    const float xr = E.e0r, xi = E.e0i, yr = E.e1r, yi = E.e1i;
+    E.e0r = g[0] * xr - g[1] * xi + g[2] * yr - g[3] * yi;
+    E.e0i = g[0] * xi + g[1] * xr + g[2] * yi + g[3] * yr;
+    E.e1r = g[4] * xr - g[5] * xi + g[6] * yr - g[7] * yi;
+    E.e1i = g[4] * xi + g[5] * xr + g[6] * yi + g[7] * yr;
+    const float ar = E.d0r, ai = E.d0i, br = E.d1r, bi = E.d1i;
+    E.d0r = g[0] * ar - g[1] * ai + g[2] * br - g[3] * bi;
+    E.d0i = g[0] * ai + g[1] * ar + g[2] * bi + g[3] * br;
+    E.d1r = g[4] * ar - g[5] * ai + g[6] * br - g[7] * bi;
+    E.d1i = g[4] * ai + g[5] * ar + g[6] * bi + g[7] * br;
   }
   E.j[0] = j0; E.j[1] = j1; E.j[2] = j2;
   return E;
@@ -577,9 +604,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     const long long pt = (long long)tile * PPW + ps;
     const bool valid = pt < a.P;
 
-    // ---------------- encoding and product state in round 0's mapping ---------------------
-    // Each qubit's embedded amplitudes are formed where they are used (qubit index uniform
-    // across the workgroup), so no per-qubit arrays are indexed at run time.
+    // ---------------- encoding and product state -------------------------------------------
+    // The leading rotation stage (rounds 0 .. H-1) is folded into the product state, which is
+    // then formed in round H-1's output mapping (round 0's input mapping if H = 0).  Each qubit's
+    // embedded amplitudes are formed where they are used (qubit index uniform across the
+    // workgroup), so no per-qubit arrays are indexed at run time.
+    const int H = plan->n_head;
     float p3[3] = {0.f, 0.f, 0.f};
     if (valid && a.points && plan->enc_kind != QP_ENC_ANGLES) {
       p3[0] = a.points[pt * 3 + 0];
@@ -587,16 +617,16 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       p3[2] = a.points[pt * 3 + 2];
     }
     {
-      CP<QRound> r0 = rounds;
+      CP<int32_t> emap = H > 0 ? rounds[H - 1].tpost : rounds[0].tpos;
       // thread part: (P, D_c) by the product rule over the thread qubits
       float Pr = valid ? 1.f : 0.f, Pi = 0.f;
       float Dr[3] = {0.f, 0.f, 0.f}, Di[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int k = 3; k < N; ++k) {
-        const QEnc E = encode_qubit<N>(plan, a, pt, valid, p3, N - 1 - r0->tpos[k]);
+        const QEnc E = encode_qubit<N>(plan, gtab, a, pt, valid, p3, N - 1 - emap[k]);
         const bool bit = (u >> (k - 3)) & 1u;
-        const float er = bit ? E.e1r : E.e0, ei = bit ? E.e1i : 0.f;
-        const float dr = bit ? E.d1r : E.d0, di = bit ? E.d1i : 0.f;
+        const float er = bit ? E.e1r : E.e0r, ei = bit ? E.e1i : E.e0i;
+        const float dr = bit ? E.d1r : E.d0r, di = bit ? E.d1i : E.d0i;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const float nr = Dr[c] * er - Di[c] * ei + E.j[c] * (Pr * dr - Pi * di);
@@ -608,15 +638,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
       QEnc Q[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) Q[i] = encode_qubit<N>(plan, a, pt, valid, p3, N - 1 - r0->tpos[i]);
+      for (int i = 0; i < 3; ++i) Q[i] = encode_qubit<N>(plan, gtab, a, pt, valid, p3, N - 1 - emap[i]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         float pr = Pr, pi = Pi, dr[3] = {Dr[0], Dr[1], Dr[2]}, di[3] = {Di[0], Di[1], Di[2]};
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           const bool b = (r >> i) & 1;
-          const float er = b ? Q[i].e1r : Q[i].e0, ei = b ? Q[i].e1i : 0.f;
-          const float ddr = b ? Q[i].d1r : Q[i].d0, ddi = b ? Q[i].d1i : 0.f;
+          const float er = b ? Q[i].e1r : Q[i].e0r, ei = b ? Q[i].e1i : Q[i].e0i;
+          const float ddr = b ? Q[i].d1r : Q[i].d0r, ddi = b ? Q[i].d1i : Q[i].d0i;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const float nr = dr[c] * er - di[c] * ei + Q[i].j[c] * (pr * ddr - pi * ddi);
@@ -633,29 +663,38 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- forward rounds -------------------------------------------------------
     constexpr int NS = swap_slots(N);
-    uint32_t jc = deposit_thread<N>(u, rounds[0].tpos);   // thread bits in the current mapping
+    // thread bits in the current mapping (round max(H - 1, 0)'s input map; to_post moves it to the
+    // output map, where the encoding left the statevectors when H > 0)
+    uint32_t jc = deposit_thread<N>(u, rounds[H > 0 ? H - 1 : 0].tpos);
     if constexpr (EXS == 4) {
       // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
       // (planes 2, 3).  Each slot reads one group, finishes the other group's round (its bit-2
       // gate and swap slots) and writes it, then runs the bit-0/1 gates of the group just read:
       // the finishing work covers the read latency and the writes drain under the following
       // gates.  Every barrier separates a plane pair's reads from its next writes.
-      RoundCoef Rc = load_round<false, NS>(rounds, gtab, F);
-      round_fwd<0, NS>(sr, si, Rc);
-      gates01<2>(sr, si, Rc);
-      if (R > 1) {
-        Offs wo = load_offs(rounds[0].woff);
-        jc = to_post<NS>(jc, rounds, u);
-        XLane x = xsetup<N>(rounds[1].tpos, xf + 1, u, pbase, jc);
+      // pend: group B still has the rest of round k - 1 to do (not so after the encoding).
+      int k0 = H;
+      bool pend = false;
+      RoundCoef Rc = load_round<false, NS>(rounds + (H > 0 ? H - 1 : 0), gtab, F);
+      if (k0 == 0) {
+        round_fwd<0, NS>(sr, si, Rc);
+        gates01<2>(sr, si, Rc);
+        pend = true;
+        k0 = 1;
+      }
+      if (k0 < R) {
+        Offs wo = load_offs(rounds[k0 - 1].woff);
+        jc = to_post<NS>(jc, rounds + (k0 - 1), u);
+        XLane x = xsetup<N>(rounds[k0].tpos, xf + k0, u, pbase, jc);
         xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
-        for (int k = 1; k < R; ++k) {
+        for (int k = k0; k < R; ++k) {
           CP<QRound> rk = rounds + k;
           const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
           const Offs ro = load_offs(xf[k].roff);
           const bool sg = xf[k].nterms != 0;
           __syncthreads();
           xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          finish<2, NS>(sr, si, Rc);                   // group B finishes round k - 1
+          if (pend) finish<2, NS>(sr, si, Rc);         // group B finishes round k - 1
           xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
           gates01<0>(sr, si, Rk);
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
@@ -671,12 +710,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           gates01<2>(sr, si, Rk);
           pin_sv<2>(sr, si); pin_sv<3>(sr, si);
           Rc = Rk;
+          pend = true;
         }
         __syncthreads();
       }
-      finish<2, NS>(sr, si, Rc);                       // group B finishes the last round
+      if (pend) finish<2, NS>(sr, si, Rc);             // group B finishes the last round
     } else {
-      for (int k = 0; k < R; ++k) {
+      for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
         if (k > 0) {
           jc = to_post<NS>(jc, rk - 1, u);
@@ -829,8 +869,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       // Each slot: read one pair group and write the next, add the previous group's gate
       // statistics (covering the read latency), then pull the group just read back through the
       // round.  A round's statistics are flushed in the next round's first slot.
+      // The last round is pulled back first, gate by gate (H < R: it is never a leading-stage round).
       CP<QRound> rl = rounds + (R - 1);
-      round_adj_all<NS>(sr, si, rl, gtab, F, slots, wave, lane);
+      round_adj_all<NS, true>(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
         Offs wo = load_offs(rl->woffp);
         jc = to_pre<NS>(jc, rl, u);
@@ -841,7 +882,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
 #pragma unroll
         for (int i = 0; i < NQ; ++i) q[i] = 0.f;
         RoundCoef Rq = load_round<true, NS>(rl, gtab, F);   // gate ids of the round whose q is pending
-        for (int k = R - 1; k >= 1; --k) {
+        // Iteration k moves the state from round k's input mapping to round k - 1's output mapping
+        // and pulls round k - 1 back (PULL), or, for a round of the leading stage, only takes its
+        // statistics.  Two loops instead of a branch inside one keep the register allocation of
+        // the pulling loop unchanged.
+        auto iter = [&](int k, auto pull) {
+          constexpr bool PULL = decltype(pull)::value;
           CP<QRound> rp = rounds + (k - 1);
           const RoundCoef Rp = load_round<true, NS>(rp, gtab, F);
           const Offs ro = load_offs(xb[k].roff);
@@ -855,19 +901,19 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
 #pragma unroll
             for (int i = 0; i < NQ; ++i) q[i] = 0.f;
           }
-          round_adj<0, NS>(sr, si, Rp, q);
+          round_adj<0, NS, PULL>(sr, si, Rp, q);
           pin_sv<0>(sr, si); pin_sv<4>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 1, 5, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 2, 6, 0>(sr, si, buf, wo, x.wb);
           stat_accum<0>(sr, si, q);
-          round_adj<1, NS>(sr, si, Rp, q);
+          round_adj<1, NS, PULL>(sr, si, Rp, q);
           pin_sv<1>(sr, si); pin_sv<5>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 2, 6, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
           xwrite<T, 3, 7, 2>(sr, si, buf, wo, x.wb);
           stat_accum<1>(sr, si, q);
-          round_adj<2, NS>(sr, si, Rp, q);
+          round_adj<2, NS, PULL>(sr, si, Rp, q);
           pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q<NQ>(q);
           __syncthreads();
           xread<T, 3, 7, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
@@ -878,18 +924,28 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
             x = xsetup<N>(rp[-1].tpost, xb + (k - 1), u, pbase, jc);
             xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
           }
-          round_adj<3, NS>(sr, si, Rp, q);
+          round_adj<3, NS, PULL>(sr, si, Rp, q);
           pin_sv<3>(sr, si); pin_sv<7>(sr, si); pin_q<NQ>(q);
           Rq = Rp;
-        }
+        };
+        for (int k = R - 1; k > H; --k) iter(k, BoolC<true>{});
+        for (int k = H; k >= 1; --k) iter(k, BoolC<false>{});
         stat_accum<3>(sr, si, q);                      // round 0's last group
         round_stat_flush<NS>(Rq, slots, q, F, wave, lane);
         __syncthreads();
       }
     } else {
-      for (int k = R - 1; k >= 0; --k) {
+      for (int k = R - 1; k >= H; --k) {
         CP<QRound> rk = rounds + k;
-        round_adj_all<NS>(sr, si, rk, gtab, F, slots, wave, lane);
+        round_adj_all<NS, true>(sr, si, rk, gtab, F, slots, wave, lane);
+        if (k > 0) {
+          jc = to_pre<NS>(jc, rk, u);
+          exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, rk[-1].tpost, xb + k, u, pbase, jc);
+        }
+      }
+      for (int k = H - 1; k >= 0; --k) {   // the leading stage: statistics only
+        CP<QRound> rk = rounds + k;
+        round_adj_all<NS, false>(sr, si, rk, gtab, F, slots, wave, lane);
         if (k > 0) {
           jc = to_pre<NS>(jc, rk, u);
           exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, rk[-1].tpost, xb + k, u, pbase, jc);

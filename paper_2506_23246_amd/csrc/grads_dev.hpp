@@ -4,7 +4,10 @@
 // With lambda and psi both taken before the gate,
 //   d L / d theta_c = 2 Re <lambda_after| dU |psi> = Im <lambda|G_c|psi> = sum_k n_k S_k,
 // where G_c = n_x X + n_y Y + n_z Z and S_k = Im <lambda|sigma_k|psi> is what the adjoint sweep
-// accumulates per gate.
+// accumulates per gate.  A gate of the leading stage has its statistic taken after the gate
+// (lambda_after, psi_after = U psi); the same derivative is then Im <lambda_after|G'_c|psi_after>
+// with G'_c = U G_c U^H = V P_c V^H, V = R_{n-1} ... R_{c+1} the components after c (R_c
+// commutes with P_c).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -16,6 +19,28 @@ namespace qp {
 
 // Axis (n_x, n_y, n_z) of G_c for component ci of fused gate fu.
 __host__ __device__ inline void generator_axis(const QFused& fu, const float* __restrict__ params, int ci, double* nvec) {
+  if (fu.stat_out) {
+    double v[8];
+    set_identity(v);
+    for (int c = ci + 1; c < fu.ncomp; ++c) {
+      double s, co;
+      sincos(0.5 * (double)params[fu.param[c]], &s, &co);
+      left_mul_rot<double>(fu.kind[c], co, s, v);
+    }
+    // a = (-i/2) P V^H, so P V^H = 2i a
+    double a[8] = {v[0], -v[1], v[4], -v[5], v[2], -v[3], v[6], -v[7]};
+    left_mul_mhalf_i_pauli<double>(fu.kind[ci], a);
+    double b[8];
+    for (int e = 0; e < 4; ++e) { b[2 * e] = -2.0 * a[2 * e + 1]; b[2 * e + 1] = 2.0 * a[2 * e]; }
+    // G' = V b: G'00 = V00 b00 + V01 b10, G'10 = V10 b00 + V11 b10
+    const double g00r = v[0] * b[0] - v[1] * b[1] + v[2] * b[4] - v[3] * b[5];
+    const double g10r = v[4] * b[0] - v[5] * b[1] + v[6] * b[4] - v[7] * b[5];
+    const double g10i = v[4] * b[1] + v[5] * b[0] + v[6] * b[5] + v[7] * b[4];
+    nvec[0] = g10r;
+    nvec[1] = g10i;
+    nvec[2] = g00r;
+    return;
+  }
   double w[8];
   set_identity(w);
   for (int c = 0; c < ci; ++c) {

@@ -407,7 +407,11 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     for (int p = 0; p < n && c < nsw; ++p)
       if (p != reg[0] && p != reg[1] && p != reg[2]) spos[c++] = p;
   };
-  for (auto& s : stages) {
+  hp->n_head = 0;
+  for (int q = 0; q < 16; ++q) hp->head_gate[q] = -1;
+  int stage0_rounds = 0;   // rounds of an opening rotation stage (nothing before it)
+  for (size_t si = 0; si < stages.size(); ++si) {
+    Stage& s = stages[si];
     if (!s.rot) {
       // compose: pending then s.aff  ->  psi(j) = sP(j') ... apply s after pending
       if (!have_pending) { pending = s.aff; have_pending = true; continue; }
@@ -474,6 +478,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
         }
       push_round(gid, reg, sgid, spos);
     }
+    if (si == 0) stage0_rounds = (int)hp->rounds.size();
   }
   if (hp->rounds.empty()) {   // no rotations at all: one empty round
     int none[3] = {-1, -1, -1}, snone[2] = {-1, -1};
@@ -486,6 +491,19 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     push_round(none, reg, snone, spos);
     pending = keep;
     have_pending = hk;
+  }
+  // An opening rotation stage acts on the product state: one fused gate per qubit, all commuting.
+  // Its rounds are folded into the encoding and their gates take their statistics at the stage
+  // output.  The last round is never folded (the adjoint sweep starts by pulling it back).
+  hp->n_head = std::min(stage0_rounds, (int)hp->rounds.size() - 1);
+  for (int k = 0; k < hp->n_head; ++k) {
+    const QRound& rd = hp->rounds[k];
+    for (int b = 0; b < 5; ++b) {
+      const int fid = b < 3 ? rd.gate[b] : rd.sgate[b - 3];
+      if (fid < 0) continue;
+      hp->fused[fid].stat_out = 1;
+      hp->head_gate[hp->fused[fid].qubit] = fid;
+    }
   }
   // trailing entangler -> readout masks: z_i(pi j), pi = A^{-1}
   {
@@ -528,6 +546,8 @@ image:
   h.n_out = hp->m;
   h.n_fused = (int)hp->fused.size();
   h.n_rounds = R;
+  h.n_head = hp->fused_ok ? hp->n_head : 0;
+  for (int q = 0; q < 16; ++q) h.head_gate[q] = hp->fused_ok ? hp->head_gate[q] : -1;
   h.enc_kind = hp->enc_kind;
   h.enc_gate = hp->enc_gate;
   h.enc_scale = hp->enc_scale;

@@ -27,6 +27,8 @@ struct HostPlan {
   uint32_t zmask[kMaxOut] = {0};
   std::vector<int32_t> csr_ptr, csr_idx;
   int n_exchanges = 0;                 // exchanges that move data
+  int n_head = 0;                      // leading rounds folded into the encoding
+  int32_t head_gate[16];               // per qubit: its leading-stage fused gate, or -1
   // dense-block plan (MFMA path)
   bool dense_ok = false;
   std::vector<QDenseGroup> dgroups;

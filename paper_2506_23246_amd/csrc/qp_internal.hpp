@@ -76,13 +76,17 @@ struct alignas(16) QXchg {
 static_assert(sizeof(QXchg) == 432, "QXchg layout");
 static_assert(sizeof(QRound) == 224, "QRound layout");
 
-// Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).
+// Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).  stat_out: the
+// gate belongs to the leading rotation stage, which acts on the product state and is folded into
+// the encoding; its statistic is taken at the gate output instead of the input.
 struct alignas(16) QFused {
   int32_t qubit;
   int32_t ncomp;
   int32_t kind[3];
   int32_t param[3];
+  int32_t stat_out;
 };
+static_assert(sizeof(QFused) == 48, "QFused layout");
 
 enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2 };
 
@@ -120,6 +124,8 @@ struct alignas(16) QPlanDev {
   int32_t off_dcsr_ptr;             // int32[n_params+1] over the occurrences
   int32_t off_dcsr_idx;             // int32[n_docc]
   uint32_t zplain[kMaxOut];         // readout parity mask of output i without folding
+  int32_t n_head;                   // leading rounds folded into the encoding (rounds 0 .. n_head-1; < n_rounds)
+  int32_t head_gate[16];            // per qubit: fused gate of the leading stage, -1 if none
 };
 
 }  // namespace qp

@@ -19,14 +19,18 @@ HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused",
                 ("enc_kind", "<i4"), ("enc_gate", "<i4"), ("enc_scale", "<i4"), ("n_feat", "<i4"),
                 ("coord", "<i4", 16), ("zmask", "<u4", 8), ("off_rounds", "<i4"), ("off_xf", "<i4"),
                 ("off_xb", "<i4"), ("off_fused", "<i4"), ("off_csr_ptr", "<i4"), ("off_csr_idx", "<i4"),
-                ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4")])
+                ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4"), ("n_dgroups", "<i4"),
+                ("off_dgroups", "<i4"), ("off_dgates", "<i4"), ("n_docc", "<i4"), ("off_docc", "<i4"),
+                ("off_dcsr_ptr", "<i4"), ("off_dcsr_idx", "<i4"), ("zplain", "<u4", 8), ("n_head", "<i4"),
+                ("head_gate", "<i4", 16)])
 ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("sgate", "<i4", 2), ("pad1", "<i4", 2),
                   ("tpos", "<i4", 16), ("tpost", "<i4", 16), ("woff", "<u4", 8), ("woffp", "<u4", 8)])
 XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("qv", "<u4", 32), ("ue", "<u4", 3),
                  ("ve", "<u4", 3), ("nterms", "<u4"), ("sign_at_src", "<u4"), ("qsign_r", "<u4"), ("identity", "<u4"),
                  ("pad1", "<u4", 2), ("roff", "<u4", 8)])
-FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3)])
-assert ROUND.itemsize == 224 and XCHG.itemsize == 432 and FUSED.itemsize == 32
+FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3), ("stat_out", "<i4"),
+                  ("pad", "<i4", 3)])
+assert ROUND.itemsize == 224 and XCHG.itemsize == 432 and FUSED.itemsize == 48
 
 
 def plan_image(circ):
@@ -183,8 +187,17 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
     c, s = np.cos(theta / 2), np.sin(theta / 2)
     e0, e1 = c.astype(complex), (-1j * s if gate_rx else s.astype(complex))
     d0, d1 = -0.5 * s + 0j, (-0.5j * c if gate_rx else 0.5 * c + 0j)
+    # leading rotation stage (rounds 0 .. H-1): applied to each qubit's factor, product state
+    # formed in round H-1's output mapping
+    H = int(h["n_head"])
+    for q in range(n):
+        g = int(h["head_gate"][q])
+        if g >= 0:
+            U = Us[g]
+            e0[q], e1[q] = U[0, 0] * e0[q] + U[0, 1] * e1[q], U[1, 0] * e0[q] + U[1, 1] * e1[q]
+            d0[q], d1[q] = U[0, 0] * d0[q] + U[0, 1] * d1[q], U[1, 0] * d0[q] + U[1, 1] * d1[q]
     regs = np.zeros((8, TP, 8), complex)
-    t0 = rounds[0]["tpos"]
+    t0 = rounds[H - 1]["tpost"] if H > 0 else rounds[0]["tpos"]
     for u in range(TP):
         for r in range(8):
             j = _deposit(u, t0, n) | _regoff(r, t0)
@@ -199,7 +212,7 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
             regs[0, u, r] = amp
             regs[1:4, u, r] = der
     nsw = _swap_slots(n)
-    for k in range(R):
+    for k in range(H, R):
         if k > 0:
             regs[:4] = _exchange(regs[:4], rounds[k - 1]["tpost"], rounds[k]["tpos"], xf[k], n, TP)
         for b in range(3):
@@ -234,7 +247,39 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
         regs[5 + cc] = D[cc] * regs[0]
     M = np.zeros((len(fused), 2, 2), complex)
     S = np.zeros((len(fused), 3))
+    def head_m(g, b):
+        """M of a leading-stage gate: lambda at the stage output, psi pulled back through this gate
+        only (the stage's other gates act on other qubits and leave the pair sums unchanged)."""
+        tmp = regs.copy()
+        _apply(tmp, slice(0, 4), b, Us[g].conj().T)
+        for r in range(8):
+            if r & (1 << b):
+                continue
+            r1 = r | (1 << b)
+            for sv in range(4):
+                x0, x1 = tmp[4 + sv, :, r], tmp[4 + sv, :, r1]
+                y0, y1 = tmp[sv, :, r], tmp[sv, :, r1]
+                M[g, 0, 0] += np.sum(np.conj(x0) * y0)
+                M[g, 0, 1] += np.sum(np.conj(x0) * y1)
+                M[g, 1, 0] += np.sum(np.conj(x1) * y0)
+                M[g, 1, 1] += np.sum(np.conj(x1) * y1)
+
     for k in range(R - 1, -1, -1):
+        if k < H:   # leading stage: statistics at the stage output, nothing pulled back
+            for i in reversed(range(nsw)):
+                g = int(rounds[k]["sgate"][i])
+                if g >= 0:
+                    head_m(g, i)
+                    _stats(regs, i, S[g])
+                regs = _swap(regs, i)
+            for b in range(3):
+                g = int(rounds[k]["gate"][b])
+                if g >= 0:
+                    head_m(g, b)
+                    _stats(regs, b, S[g])
+            if k > 0:
+                regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], n, TP)
+            continue
         for i in reversed(range(nsw)):   # swap-slot gates, then undo the swaps
             g = int(rounds[k]["sgate"][i])
             if g >= 0:
@@ -305,7 +350,8 @@ def grads_from_m(plan, params, M):
 
 def grads_from_s(plan, params, S):
     """d L / d theta_k = sum over components c driven by theta_k of n(c) . S_gate, where
-    n(c) is the axis of G_c = W^H P_c W, W the product of the gate's components before c."""
+    n(c) is the axis of G_c = W^H P_c W, W the product of the gate's components before c; for a
+    gate of the leading stage (statistic at the gate output) the axis of U G_c U^H."""
     K = int(plan["h"]["n_params"])
     out = np.zeros(K)
     P = {0: np.array([[0, 1], [1, 0]]), 1: np.array([[0, -1j], [1j, 0]]), 2: np.diag([1, -1])}
@@ -318,6 +364,9 @@ def grads_from_s(plan, params, S):
             for c in range(ci):
                 Wm = _rot(int(f["kind"][c]), float(params[int(f["param"][c])])) @ Wm
             G = Wm.conj().T @ P[int(f["kind"][ci])] @ Wm
+            if int(f["stat_out"]):
+                U = _fused_matrix(f, params)
+                G = U @ G @ U.conj().T
             nvec = [0.5 * np.real(np.trace(sk @ G)) for sk in paulis]
             out[k] += float(np.dot(nvec, S[fi]))
     return out

@@ -62,6 +62,73 @@ def test_emulated_plan_mixed_entanglers(n):
     _run(circ, params, pts)
 
 
+def _circ(n, gates, n_params, out_qubits=(0, 1, 2)):
+    return W.Circuit(n=n, gates=list(gates), n_params=n_params, out_qubits=list(out_qubits))
+
+
+def _leading_stage_cases():
+    """Circuits that open in different ways: (name, circuit, expected number of folded rounds)."""
+    cases = []
+    n = 6   # no swap slots: 3 gates per round
+    g = W.ring(n, W.CNOT, 1)
+    c = W.layered(n, 2, "xyz", lambda l: W.ring(n, W.CNOT, 1))
+    cases.append(("rotations first", c, 2))
+    c = _circ(n, g + W.layered(n, 2, "xz", lambda l: W.ring(n, W.CZ, 1)).gates, 4 * n)
+    cases.append(("entangler first", c, 0))
+    # leading stage on qubits 1 and 4 only, then a ring, then a full layer
+    gates = [(W.RY, 1, -1, 0), (W.RZ, 4, -1, 1)] + g + W.layered(n, 1, "xyz").gates
+    gates = [(k, q0, q1, (p + 2) if (p >= 0 and i >= 2 + len(g)) else p) for i, (k, q0, q1, p) in enumerate(gates)]
+    cases.append(("partial leading stage", _circ(n, gates, 2 + 3 * n), 1))
+    # four rotations on qubit 0 split the opening rotations into two stages; only the first folds
+    gates = [(W.RX, 0, -1, 0), (W.RY, 0, -1, 1), (W.RZ, 0, -1, 2), (W.RY, 0, -1, 3), (W.RX, 2, -1, 4)] + g + \
+        [(W.RY, q, -1, 5 + q) for q in range(n)]
+    cases.append(("split opening rotations", _circ(n, gates, 5 + n), 1))
+    # no entangler at all: every round but the last folds
+    cases.append(("no entangler", W.layered(n, 1, "xyz"), 1))
+    # 10 qubits (two swap slots, 5 gates a round) and 8 qubits (one swap slot) with a CZ ring
+    cases.append(("10 qubits", W.layered(10, 2, "rot", lambda l: W.ring(10, W.CZ, 2)), 2))
+    cases.append(("8 qubits", W.layered(8, 2, "xyz", lambda l: W.ring(8, W.CNOT, 3), out_qubits=[0, 7, 3]), 2))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_leading_stage_folding(case):
+    """The planner folds exactly the rounds of an opening rotation stage (one gate per qubit, acting
+    on the product state), except the circuit's last round, into the encoding; those gates take
+    their statistic at the gate output.
+    The emulated kernel, which forms the product state with those gates applied and takes their
+    statistics without pulling anything back, matches the oracle's outputs, tangents and gradient."""
+    from tests.plan_emulator import plan_image
+    name, circ, nh = _leading_stage_cases()[case]
+    plan = plan_image(circ)
+    h = plan["h"]
+    assert int(h["n_head"]) == nh, name
+    head = {int(h["head_gate"][q]) for q in range(circ.n) if int(h["head_gate"][q]) >= 0}
+    in_rounds = set()
+    for k in range(nh):
+        rd = plan["rounds"][k]
+        in_rounds |= {int(x) for x in list(rd["gate"]) + list(rd["sgate"]) if int(x) >= 0}
+    assert head == in_rounds, name
+    for fi, f in enumerate(plan["fused"]):
+        assert int(f["stat_out"]) == (1 if fi in head else 0), name
+        if fi in head:
+            assert int(h["head_gate"][int(f["qubit"])]) == fi
+    rng = np.random.default_rng(100 + case)
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    pts = rng.uniform(-1, 1, (2, 3))
+    _run(circ, params, pts)
+
+
+def test_leading_stage_of_the_twelve_qubit_workload():
+    """12 qubits x 8 layers: the first layer's twelve gates are the four folded rounds."""
+    from tests.plan_emulator import plan_image
+    plan = plan_image(W.config(4, P=1).circuit)
+    h = plan["h"]
+    assert int(h["n_rounds"]) == 32 and int(h["n_head"]) == 4
+    assert sorted(int(x) for x in h["head_gate"][:12]) == list(range(12))
+    assert all(int(x) == -1 for x in h["head_gate"][12:])
+
+
 def _swz(i):
     return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12) ^ (i >> 16)) & 15)
 
