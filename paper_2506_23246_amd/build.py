@@ -20,10 +20,13 @@ LIB = os.path.join(PKG, "libqpinn.so")
 ARCH = os.environ.get("QP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -ffp-contract=on: multiply-adds are fused only within one source expression, as written, so the
+# rounding of every kernel's arithmetic follows the source and not the surrounding code (kernel
+# variants that share per-point code give bitwise-equal results).
 HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wno-unused-command-line-argument",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 CPP_FLAGS = ["-O2", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-variable",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
 
 

@@ -394,7 +394,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
   if (grid > 0) {
     if (ctx->timing) hipEventRecord(ctx->ev0, st);
-    if ((e = launch_fused(n, mode, a, grid, exs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
+    if ((e = launch_fused(n, mode, a, grid, exs, c->hp.has_signs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
     if (ctx->timing) hipEventRecord(ctx->ev1, st);
   }
   if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only

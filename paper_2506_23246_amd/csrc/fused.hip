@@ -35,16 +35,16 @@
 namespace qp {
 
 
-hipError_t launch_fused_3(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_4(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_5(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_6(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_7(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_8(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_9(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_10(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_11(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
-hipError_t launch_fused_12(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
+hipError_t launch_fused_3(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_4(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_5(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_6(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_7(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_8(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_9(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_10(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_11(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
+hipError_t launch_fused_12(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------------
 // Gate table: U = R_{c-1} ... R_0 for every fused gate, R_P(theta) = exp(-i theta P/2).  The table
@@ -177,18 +177,18 @@ size_t fused_lds_bytes(int n, int exs, int n_fused) {
          (size_t)(T / 64) * 40 * sizeof(float);
 }
 
-hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
+hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st) {
   switch (n) {
-    case 3: return launch_fused_3(mode, a, grid, exs, lds, st);
-    case 4: return launch_fused_4(mode, a, grid, exs, lds, st);
-    case 5: return launch_fused_5(mode, a, grid, exs, lds, st);
-    case 6: return launch_fused_6(mode, a, grid, exs, lds, st);
-    case 7: return launch_fused_7(mode, a, grid, exs, lds, st);
-    case 8: return launch_fused_8(mode, a, grid, exs, lds, st);
-    case 9: return launch_fused_9(mode, a, grid, exs, lds, st);
-    case 10: return launch_fused_10(mode, a, grid, exs, lds, st);
-    case 11: return launch_fused_11(mode, a, grid, exs, lds, st);
-    case 12: return launch_fused_12(mode, a, grid, exs, lds, st);
+    case 3: return launch_fused_3(mode, a, grid, exs, signs, lds, st);
+    case 4: return launch_fused_4(mode, a, grid, exs, signs, lds, st);
+    case 5: return launch_fused_5(mode, a, grid, exs, signs, lds, st);
+    case 6: return launch_fused_6(mode, a, grid, exs, signs, lds, st);
+    case 7: return launch_fused_7(mode, a, grid, exs, signs, lds, st);
+    case 8: return launch_fused_8(mode, a, grid, exs, signs, lds, st);
+    case 9: return launch_fused_9(mode, a, grid, exs, signs, lds, st);
+    case 10: return launch_fused_10(mode, a, grid, exs, signs, lds, st);
+    case 11: return launch_fused_11(mode, a, grid, exs, signs, lds, st);
+    case 12: return launch_fused_12(mode, a, grid, exs, signs, lds, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -34,7 +34,7 @@ struct FusedArgs {
 int fused_threads(int n);
 int fused_points_per_tile(int n);
 size_t fused_lds_bytes(int n, int exs, int n_fused);
-hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st);
+hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
 hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, int fp32, hipStream_t st);
 hipError_t launch_rff(const QPlanDev* plan, const float* points, long long P, float* angles, float* jac, hipStream_t st);
 hipError_t launch_count(const float* points, long long P, float x_if, int* counts, hipStream_t st);

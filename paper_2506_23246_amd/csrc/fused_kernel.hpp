@@ -137,7 +137,8 @@ __device__ __forceinline__ float wave_reduce_scatter4(const float* v) {
 // swz(pbase ^ j ^ o) = swz(pbase ^ j) ^ swz(o), and the planner stores 8 swz(o) (byte offsets of
 // complex64 entries) for the eight register offsets (woff for the writer, roff for the reader).
 // Per exchange a lane needs three words: its writer and reader byte bases and the sign bits of
-// its eight reads; each access then costs one XOR.
+// its eight reads (the planner tabulates them per thread of a point: QLane); each access then
+// costs one XOR.
 struct XLane {
   uint32_t wb, rb, sgn;
 };
@@ -196,74 +197,17 @@ __device__ __forceinline__ Offs load_offs(CP<uint32_t> p) {
   return O;
 }
 
-// jc: on entry the thread part of the logical index in the writer's mapping (deposit of u), on
-// exit the same in the reader's mapping rpos (a round's input map tpos or its output map tpost),
-// so consecutive exchanges deposit the thread bits once each.
-template <int N>
-__device__ __forceinline__ XLane xsetup(CP<int32_t> rpos, CP<QXchg> X, uint32_t u, uint32_t pbase, uint32_t& jc) {
+// The lane words of exchange k in direction dir (0 forward, 1 reverse) for thread u of the point
+// whose swizzled base is pb8 = 8 swz(pbase): one 16-byte vector load from the plan's lane table
+// (vector loads use their own wait counter, so a load issued early does not hold up LDS waits).
+__device__ __forceinline__ XLane lane_words(const QLane* __restrict__ lanes, int dir, int R, int k, int TPn,
+                                            uint32_t u, uint32_t pb8) {
+  const QLane L = lanes[((size_t)dir * R + k) * TPn + u];
   XLane x;
-  x.wb = swz(pbase ^ jc) * 8u;
-  const uint32_t jn = deposit_thread<N>(u, rpos);
-  jc = jn;
-  uint32_t sb = jn;
-  x.sgn = 0;   // bit r set: negate amplitude r
-  if (!X->identity) {
-    // sb = A jn with jn = sum of the thread bits placed at rpos[k]: column A e_rpos[k] is
-    // acol[rpos[k]], so only the N - 3 thread bits are visited.
-    sb = 0;
-#pragma unroll
-    for (int k = 3; k < N; ++k) {
-      const uint32_t msk = 0u - ((u >> (k - 3)) & 1u);
-      sb ^= msk & X->acol[rpos[k]];
-    }
-    const int nt = X->nterms;
-    if (nt > 0) {
-      const uint32_t xb = X->sign_at_src ? sb : jn;
-      uint32_t pu = 0, pv = 0;
-      for (int t = 0; t < nt; ++t) {
-        pu |= parity(X->qu[t] & xb) << t;
-        pv |= parity(X->qv[t] & xb) << t;
-      }
-      const uint32_t q0 = parity(pu & pv);
-      const uint32_t b0 = parity((pu & X->ve[0]) ^ (X->ue[0] & pv));
-      const uint32_t b1 = parity((pu & X->ve[1]) ^ (X->ue[1] & pv));
-      const uint32_t b2 = parity((pu & X->ve[2]) ^ (X->ue[2] & pv));
-      const uint32_t qs = X->qsign_r;
-      uint32_t sg = 0;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        uint32_t sr_ = q0 ^ ((qs >> r) & 1u);
-        if (r & 1) sr_ ^= b0;
-        if (r & 2) sr_ ^= b1;
-        if (r & 4) sr_ ^= b2;
-        sg |= sr_ << r;
-      }
-      x.sgn = sg;
-    }
-  }
-  x.rb = swz(pbase ^ sb) * 8u;
+  x.wb = L.wb ^ pb8;
+  x.rb = L.rb ^ pb8;
+  x.sgn = L.sgn;
   return x;
-}
-
-// The carried thread deposit across a round's swap slots: thread bit 4 + i sits at logical position
-// tpos[7 + i] in the input map and at tpos[i] in the output map.
-template <int NS>
-__device__ __forceinline__ uint32_t to_post(uint32_t j, CP<QRound> rk, uint32_t u) {
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const uint32_t b = (u >> (4 + i)) & 1u;
-    j = (j & ~(1u << rk->tpos[7 + i])) | (b << rk->tpos[i]);
-  }
-  return j;
-}
-template <int NS>
-__device__ __forceinline__ uint32_t to_pre(uint32_t j, CP<QRound> rk, uint32_t u) {
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const uint32_t b = (u >> (4 + i)) & 1u;
-    j = (j & ~(1u << rk->tpos[i])) | (b << rk->tpos[7 + i]);
-  }
-  return j;
 }
 
 // Writes statevectors SV0 and SV1 to LDS planes PL and PL + 1 in the writer mapping wr.
@@ -281,35 +225,36 @@ __device__ __forceinline__ void xwrite(const float (&sr)[8][8], const float (&si
   }
 }
 
-// Reads statevectors SV0 and SV1 back from planes PL, PL + 1 through the descriptor X.
-template <int T, int SV0, int SV1, int PL>
+// Reads statevectors SV0 and SV1 back from planes PL, PL + 1 through the descriptor X.  SG = false:
+// the circuit has no CZ stage, so no exchange carries signs and the sign code is left out.
+template <int T, int SV0, int SV1, int PL, bool SG = true>
 __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], const float2* __restrict__ buf,
                                       const Offs& ro, bool signs, uint32_t rb, uint32_t sgn) {
   // SV0 is read completely before SV1, so the gates on SV0 can start while SV1 is in flight.
   constexpr uint32_t PLANE = T * 8 * 8;   // bytes; a power of two above every in-plane offset
   const char* b = reinterpret_cast<const char*>(buf);
   const uint32_t base = rb | (PL * PLANE);   // plane PL folded into the base: one XOR per access
-  if (!signs) {   // no sign terms (identity or a CNOT stage): uniform fast path
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t o = base ^ ro.o[r];
-        const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
-        if (h == 0) { sr[SV0][r] = v.x; si[SV0][r] = v.y; } else { sr[SV1][r] = v.x; si[SV1][r] = v.y; }
-      }
-  } else {
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t o = base ^ ro.o[r];
+      const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
+      if (h == 0) { sr[SV0][r] = v.x; si[SV0][r] = v.y; } else { sr[SV1][r] = v.x; si[SV1][r] = v.y; }
+    }
+  if (SG && signs) {   // a CZ stage: negate the amplitudes whose sign bit is set (uniform branch)
+    // The empty volatile asm keeps this a branch: merged into the unconditional path, the flips
+    // would cost two XORs per amplitude on every exchange and consume the loaded values at once,
+    // which forces the LDS reads to complete before any independent work can cover them.
+    asm volatile("");
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t o = base ^ ro.o[r];
-        const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
-        const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
-        const float vr = __uint_as_float(__float_as_uint(v.x) ^ flip);
-        const float vi = __uint_as_float(__float_as_uint(v.y) ^ flip);
-        if (h == 0) { sr[SV0][r] = vr; si[SV0][r] = vi; } else { sr[SV1][r] = vr; si[SV1][r] = vi; }
-      }
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t flip = ((sgn >> r) & 1u) << 31;   // negate by flipping the sign bits
+      sr[SV0][r] = __uint_as_float(__float_as_uint(sr[SV0][r]) ^ flip);
+      si[SV0][r] = __uint_as_float(__float_as_uint(si[SV0][r]) ^ flip);
+      sr[SV1][r] = __uint_as_float(__float_as_uint(sr[SV1][r]) ^ flip);
+      si[SV1][r] = __uint_as_float(__float_as_uint(si[SV1][r]) ^ flip);
+    }
   }
 }
 
@@ -317,12 +262,10 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
 // holds only two planes per workgroup).
 template <int N, int T, int NSV, int EXS>
 __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         CP<uint32_t> woff, CP<int32_t> rpos, CP<QXchg> X, uint32_t u,
-                                         uint32_t pbase, uint32_t& jc) {
+                                         CP<uint32_t> woff, CP<QXchg> X, const XLane& x) {
   static_assert(EXS == 2, "pairs of planes");
   const Offs wo = load_offs(woff), ro = load_offs(X->roff);
   const bool sg = X->nterms != 0;
-  const XLane x = xsetup<N>(rpos, X, u, pbase, jc);
 #pragma unroll
   for (int g = 0; g < NSV; g += 2) {
     if (g == 0) xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
@@ -397,6 +340,14 @@ __device__ __forceinline__ void round_fwd(float (&sr)[8][8], float (&si)[8][8], 
   finish<S0, NS>(sr, si, R);
 }
 
+// Adds v to a per-wave statistic slot in LDS with an LDS float add that returns nothing, so the
+// wave does not wait for its outstanding LDS operations as a read-modify-write would.  Each slot
+// belongs to one wave and receives one lane's value per flush, in program order, so the sums are
+// those of the read-modify-write, bit for bit.
+__device__ __forceinline__ void slot_add(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Wave-reduces the round's gate statistics (register bits 0..2, then the NS swap slots) and adds
 // them to the per-wave LDS slots.
 template <int NS>
@@ -407,7 +358,7 @@ __device__ __forceinline__ void round_stat_flush(const RoundCoef& R, float* __re
     const int gsrc = R.gid[bb];
     const float v4[4] = {q[3 * bb], q[3 * bb + 1], q[3 * bb + 2], 0.f};
     const float v = wave_reduce_scatter4(v4);
-    if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+    if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slot_add(slots + (wave * F + gsrc) * kGS + (lane >> 4), v);
   }
 }
 
@@ -470,7 +421,7 @@ __device__ __forceinline__ void adj_gate_all(float (&sr)[8][8], float (&si)[8][8
   accum_s<B>(sr, si, q6);
   const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
   const float v = wave_reduce_scatter4(v4);
-  if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slots[(wave * F + gsrc) * kGS + (lane >> 4)] += v;
+  if (gsrc >= 0 && (lane & 15) == 0 && lane < 48) slot_add(slots + (wave * F + gsrc) * kGS + (lane >> 4), v);
 }
 
 // Adjoint of round rk on all four pairs, gate by gate (where no pipelining separates the pairs;
@@ -567,7 +518,7 @@ __device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, CP<float> gtab, 
 
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
-template <int N, int T, int EXS, int MODE>
+template <int N, int T, int EXS, int MODE, bool SG = true>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ red, float& lacc) {
   constexpr int TP = 1 << (N - 3);         // threads per point
@@ -663,9 +614,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- forward rounds -------------------------------------------------------
     constexpr int NS = swap_slots(N);
-    // thread bits in the current mapping (round max(H - 1, 0)'s input map; to_post moves it to the
-    // output map, where the encoding left the statevectors when H > 0)
-    uint32_t jc = deposit_thread<N>(u, rounds[H > 0 ? H - 1 : 0].tpos);
+    const QLane* __restrict__ lanes = reinterpret_cast<const QLane*>(reinterpret_cast<const char*>(a.plan) + plan->off_lanes);
+    const uint32_t pb8 = swz(pbase) * 8u;
     if constexpr (EXS == 4) {
       // Software-pipelined: group A = statevectors {0, 1} (planes 0, 1), group B = {2, 3}
       // (planes 2, 3).  Each slot reads one group, finishes the other group's round (its bit-2
@@ -684,31 +634,32 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
       if (k0 < R) {
         Offs wo = load_offs(rounds[k0 - 1].woff);
-        jc = to_post<NS>(jc, rounds + (k0 - 1), u);
-        XLane x = xsetup<N>(rounds[k0].tpos, xf + k0, u, pbase, jc);
+        XLane x = lane_words(lanes, 0, R, k0, TP, u, pb8);
         xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
         for (int k = k0; k < R; ++k) {
           CP<QRound> rk = rounds + k;
           const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
           const Offs ro = load_offs(xf[k].roff);
           const bool sg = xf[k].nterms != 0;
+          // the next exchange's lane words: a vector load issued a whole round ahead of its use
+          XLane xn = x;
+          if (k + 1 < R) xn = lane_words(lanes, 0, R, k + 1, TP, u, pb8);
           __syncthreads();
-          xread<T, 0, 1, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xread<T, 0, 1, 0, SG>(sr, si, buf, ro, sg, x.rb, x.sgn);
           if (pend) finish<2, NS>(sr, si, Rc);         // group B finishes round k - 1
           xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
           gates01<0>(sr, si, Rk);
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
+          // The next exchange's write offsets, loaded before the barrier: scalar loads share the
+          // wait counter with LDS operations, and waiting here costs nothing.
+          if (k + 1 < R) wo = load_offs(rk->woff);
           __syncthreads();
-          xread<T, 2, 3, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xread<T, 2, 3, 2, SG>(sr, si, buf, ro, sg, x.rb, x.sgn);
           finish<0, NS>(sr, si, Rk);                   // group A finishes round k
-          if (k + 1 < R) {
-            wo = load_offs(rk->woff);
-            jc = to_post<NS>(jc, rk, u);
-            x = xsetup<N>(rk[1].tpos, xf + k + 1, u, pbase, jc);
-            xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
-          }
+          if (k + 1 < R) xwrite<T, 0, 1, 0>(sr, si, buf, wo, xn.wb);
           gates01<2>(sr, si, Rk);
           pin_sv<2>(sr, si); pin_sv<3>(sr, si);
+          x = xn;
           Rc = Rk;
           pend = true;
         }
@@ -718,10 +669,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     } else {
       for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
-        if (k > 0) {
-          jc = to_post<NS>(jc, rk - 1, u);
-          exchange<N, T, 4, 2>(sr, si, buf, rk[-1].woff, rk->tpos, xf + k, u, pbase, jc);
-        }
+        if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, rk[-1].woff, xf + k, lane_words(lanes, 0, R, k, TP, u, pb8));
         const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
         round_fwd<0, NS>(sr, si, Rk);
         round_fwd<2, NS>(sr, si, Rk);
@@ -729,8 +677,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     }
     // ---------------- readout ----------------------------------------------------------------
     CP<QRound> rl = rounds + (R - 1);   // the statevectors are in the last round's output mapping
-    jc = to_post<NS>(jc, rl, u);
-    const uint32_t jl = jc;
+    const uint32_t jl = deposit_thread<N>(u, rl->tpost);
     const uint32_t l0 = rl->tpost[0], l1 = rl->tpost[1], l2 = rl->tpost[2];
     float acc[kMaxOut * 4];
 #pragma unroll
@@ -866,17 +813,24 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     // group (its gates and its share of the statistics need no other statevector).
     if constexpr (EXS == 4) {
       // Software-pipelined over the four pair groups with plane pairs {0, 1} and {2, 3} in turn.
-      // Each slot: read one pair group and write the next, add the previous group's gate
-      // statistics (covering the read latency), then pull the group just read back through the
-      // round.  A round's statistics are flushed in the next round's first slot.
+      // Each slot: read one pair group, add the previous group's gate statistics (covering the
+      // read latency), write the next group, then pull the group just read back through the
+      // round.  Writing after the statistics lets every wave's reads drain from the LDS queue
+      // before the writes of the workgroup's waves compete with them.  A round's statistics are
+      // flushed in the next round's first slot.
       // The last round is pulled back first, gate by gate (H < R: it is never a leading-stage round).
       CP<QRound> rl = rounds + (R - 1);
       round_adj_all<NS, true>(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
         Offs wo = load_offs(rl->woffp);
-        jc = to_pre<NS>(jc, rl, u);
-        XLane x = xsetup<N>(rl[-1].tpost, xb + (R - 1), u, pbase, jc);
-        xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
+        // the current exchange's lane words as plain scalars (the loop body below is a lambda that
+        // updates them; an aggregate captured by reference would not stay in registers)
+        uint32_t xwb, xrb, xsg;
+        {
+          const XLane x0 = lane_words(lanes, 1, R, R - 1, TP, u, pb8);
+          xwb = x0.wb; xrb = x0.rb; xsg = x0.sgn;
+        }
+        xwrite<T, 0, 4, 0>(sr, si, buf, wo, xwb);
         constexpr int NQ = 3 * (3 + NS);
         float q[NQ];
 #pragma unroll
@@ -893,39 +847,40 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           const Offs ro = load_offs(xb[k].roff);
           const bool sg = xb[k].nterms != 0;
           __syncthreads();
-          xread<T, 0, 4, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          xwrite<T, 1, 5, 2>(sr, si, buf, wo, x.wb);
+          xread<T, 0, 4, 0, SG>(sr, si, buf, ro, sg, xrb, xsg);
           if (k < R - 1) {                             // finish the previous round's statistics
             stat_accum<3>(sr, si, q);
             round_stat_flush<NS>(Rq, slots, q, F, wave, lane);
 #pragma unroll
             for (int i = 0; i < NQ; ++i) q[i] = 0.f;
           }
+          xwrite<T, 1, 5, 2>(sr, si, buf, wo, xwb);
           round_adj<0, NS, PULL>(sr, si, Rp, q);
           pin_sv<0>(sr, si); pin_sv<4>(sr, si); pin_q<NQ>(q);
           __syncthreads();
-          xread<T, 1, 5, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          xwrite<T, 2, 6, 0>(sr, si, buf, wo, x.wb);
+          xread<T, 1, 5, 2, SG>(sr, si, buf, ro, sg, xrb, xsg);
           stat_accum<0>(sr, si, q);
+          xwrite<T, 2, 6, 0>(sr, si, buf, wo, xwb);
           round_adj<1, NS, PULL>(sr, si, Rp, q);
           pin_sv<1>(sr, si); pin_sv<5>(sr, si); pin_q<NQ>(q);
           __syncthreads();
-          xread<T, 2, 6, 0>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          xwrite<T, 3, 7, 2>(sr, si, buf, wo, x.wb);
+          xread<T, 2, 6, 0, SG>(sr, si, buf, ro, sg, xrb, xsg);
           stat_accum<1>(sr, si, q);
+          xwrite<T, 3, 7, 2>(sr, si, buf, wo, xwb);
           round_adj<2, NS, PULL>(sr, si, Rp, q);
           pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q<NQ>(q);
+          // the next exchange's write offsets (scalar, before the barrier as in the forward sweep)
+          if (k > 1) wo = load_offs(rp->woffp);
           __syncthreads();
-          xread<T, 3, 7, 2>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xread<T, 3, 7, 2, SG>(sr, si, buf, ro, sg, xrb, xsg);
+          // and its lane words: a vector load (its own wait counter), covered by the statistics
+          XLane xn{xwb, xrb, xsg};
+          if (k > 1) xn = lane_words(lanes, 1, R, k - 1, TP, u, pb8);
           stat_accum<2>(sr, si, q);
-          if (k > 1) {
-            wo = load_offs(rp->woffp);
-            jc = to_pre<NS>(jc, rp, u);
-            x = xsetup<N>(rp[-1].tpost, xb + (k - 1), u, pbase, jc);
-            xwrite<T, 0, 4, 0>(sr, si, buf, wo, x.wb);
-          }
+          if (k > 1) xwrite<T, 0, 4, 0>(sr, si, buf, wo, xn.wb);
           round_adj<3, NS, PULL>(sr, si, Rp, q);
           pin_sv<3>(sr, si); pin_sv<7>(sr, si); pin_q<NQ>(q);
+          xwb = xn.wb; xrb = xn.rb; xsg = xn.sgn;
           Rq = Rp;
         };
         for (int k = R - 1; k > H; --k) iter(k, BoolC<true>{});
@@ -938,25 +893,19 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = R - 1; k >= H; --k) {
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, true>(sr, si, rk, gtab, F, slots, wave, lane);
-        if (k > 0) {
-          jc = to_pre<NS>(jc, rk, u);
-          exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, rk[-1].tpost, xb + k, u, pbase, jc);
-        }
+        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
       for (int k = H - 1; k >= 0; --k) {   // the leading stage: statistics only
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, false>(sr, si, rk, gtab, F, slots, wave, lane);
-        if (k > 0) {
-          jc = to_pre<NS>(jc, rk, u);
-          exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, rk[-1].tpost, xb + k, u, pbase, jc);
-        }
+        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
     }
   }
 }
 
 // ---- the fused kernel: a persistent grid walks the tiles ------------------------------------
-template <int N, int T, int EXS, int MODE>
+template <int N, int T, int EXS, int MODE, bool SG>
 __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   constexpr int WAVES = T / 64;
   constexpr int PLANE = T * 8;
@@ -988,7 +937,7 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
     t_step = gridDim.x / kXcd;
   }
   for (int tile = t_begin; tile < t_end; tile += t_step)
-    fused_tile<N, T, EXS, MODE>(a, tile, buf, slots, red, lacc);
+    fused_tile<N, T, EXS, MODE, SG>(a, tile, buf, slots, red, lacc);
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
@@ -1012,10 +961,10 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
 }
 
 
-template <int N, int EXS, int MODE>
+template <int N, int EXS, int MODE, bool SG>
 hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) {
   constexpr int T = (N == 12) ? 512 : 256;
-  auto kern = k_fused<N, T, EXS, MODE>;
+  auto kern = k_fused<N, T, EXS, MODE, SG>;
   // lds counts the static exchange planes and the dynamic part; only the latter is passed.
   const size_t planes = (size_t)EXS * T * 8 * sizeof(float2);
   const size_t dyn = lds > planes ? lds - planes : 0;
@@ -1029,12 +978,21 @@ hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) 
   return hipGetLastError();
 }
 
-// Entry point of one per-N unit.
+// Entry point of one per-N unit.  signs: some exchange of the circuit carries CZ signs (the
+// pipelined kernel has a variant without the sign code for circuits that have none).
 template <int N>
-hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
-  if (mode == kModeFwd) return exs == 2 ? launch_one<N, 2, kModeFwd>(a, grid, lds, st) : launch_one<N, 4, kModeFwd>(a, grid, lds, st);
-  if (mode == kModeMaxwell) return exs == 2 ? launch_one<N, 2, kModeMaxwell>(a, grid, lds, st) : launch_one<N, 4, kModeMaxwell>(a, grid, lds, st);
-  return exs == 2 ? launch_one<N, 2, kModeVjp>(a, grid, lds, st) : launch_one<N, 4, kModeVjp>(a, grid, lds, st);
+hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st) {
+  if (mode == kModeFwd) {
+    if (exs == 2) return launch_one<N, 2, kModeFwd, true>(a, grid, lds, st);
+    return signs ? launch_one<N, 4, kModeFwd, true>(a, grid, lds, st) : launch_one<N, 4, kModeFwd, false>(a, grid, lds, st);
+  }
+  if (mode == kModeMaxwell) {
+    if (exs == 2) return launch_one<N, 2, kModeMaxwell, true>(a, grid, lds, st);
+    return signs ? launch_one<N, 4, kModeMaxwell, true>(a, grid, lds, st)
+                 : launch_one<N, 4, kModeMaxwell, false>(a, grid, lds, st);
+  }
+  if (exs == 2) return launch_one<N, 2, kModeVjp, true>(a, grid, lds, st);
+  return signs ? launch_one<N, 4, kModeVjp, true>(a, grid, lds, st) : launch_one<N, 4, kModeVjp, false>(a, grid, lds, st);
 }
 
 }  // namespace qp

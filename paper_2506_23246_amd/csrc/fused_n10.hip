@@ -2,7 +2,7 @@
 #include "fused_kernel.hpp"
 
 namespace qp {
-hipError_t launch_fused_10(int mode, const FusedArgs& a, int grid, int exs, size_t lds, hipStream_t st) {
-  return launch_fused_n<10>(mode, a, grid, exs, lds, st);
+hipError_t launch_fused_10(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st) {
+  return launch_fused_n<10>(mode, a, grid, exs, signs, lds, st);
 }
 }  // namespace qp

@@ -161,6 +161,29 @@ void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool s
   for (int r = 0; r < 8; ++r) X->roff[r] = 8u * lds_swizzle(ident ? jr_of(read_tpos, r) : X->src_r[r]);
 }
 
+// Thread part of the logical index of thread u in mapping map (thread bit k - 3 at position map[k]).
+uint32_t deposit_host(uint32_t u, const int32_t* map, int n) {
+  uint32_t j = 0;
+  for (int k = 3; k < n; ++k) j |= ((u >> (k - 3)) & 1u) << map[k];
+  return j;
+}
+
+// Lane words of one exchange for thread u: the writer writes register r at wdep ^ jr_w(r); the
+// reader's register r holds the amplitude of logical index j = jn ^ jr_r(r) in its mapping, read
+// from A j and negated where Q(x) = 1, x = A j (sign in source coordinates) or x = j.
+QLane lane_words(int n, const uint32_t* Acols, const Affine& aff, bool sign_at_src, const int32_t* wmap,
+                 const int32_t* rmap, uint32_t u) {
+  QLane L{};
+  const uint32_t wdep = deposit_host(u, wmap, n), jn = deposit_host(u, rmap, n);
+  L.wb = 8u * lds_swizzle(wdep);
+  L.rb = 8u * lds_swizzle(apply_cols(Acols, n, jn));
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t j = jn ^ jr_of(rmap, r);
+    L.sgn |= qform(aff.terms, sign_at_src ? apply_cols(Acols, n, j) : j) << r;
+  }
+  return L;
+}
+
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 }  // namespace
@@ -366,6 +389,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   build_dense(hp);
   if (!hp->fused_ok) {   // no register rounds; the image still carries the dense plan
     hp->rounds.clear();
+    hp->lanes.clear();
     for (int i = 0; i < hp->m; ++i) hp->zmask[i] = 1u << (n - 1 - hp->out_qubits[i]);
     goto image;
   }
@@ -523,9 +547,12 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   }
   // exchanges
   const int R = (int)hp->rounds.size();
+  const int TP = 1 << (n - 3);
   hp->xf.assign(R, QXchg{});
   hp->xb.assign(R, QXchg{});
+  hp->lanes.assign((size_t)2 * R * TP, QLane{});
   hp->n_exchanges = 0;
+  hp->has_signs = false;
   for (int k = 1; k < R; ++k) {
     const Affine& a = round_ent[k];
     fill_xchg(&hp->xf[k], n, a.acol, a, false, hp->rounds[k].tpos);
@@ -533,6 +560,14 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     if (!gf2_inverse(a.acol, n, inv)) { *status = QP_EINVAL; return "singular entangler map"; }
     fill_xchg(&hp->xb[k], n, inv, a, true, hp->rounds[k - 1].tpost);
     hp->n_exchanges++;
+    if (hp->xf[k].nterms != 0 || hp->xb[k].nterms != 0) hp->has_signs = true;
+    // forward: round k-1's output mapping -> round k's input mapping; reverse: the other way
+    for (int u = 0; u < TP; ++u) {
+      hp->lanes[((size_t)0 * R + k) * TP + u] =
+          lane_words(n, a.acol, a, false, hp->rounds[k - 1].tpost, hp->rounds[k].tpos, (uint32_t)u);
+      hp->lanes[((size_t)1 * R + k) * TP + u] =
+          lane_words(n, inv, a, true, hp->rounds[k].tpos, hp->rounds[k - 1].tpost, (uint32_t)u);
+    }
   }
 
   }
@@ -571,6 +606,7 @@ image:
   h.off_docc = (int)off; off = align16(off + sizeof(int32_t) * hp->docc.size());
   h.off_dcsr_ptr = (int)off; off = align16(off + sizeof(int32_t) * hp->dcsr_ptr.size());
   h.off_dcsr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->dcsr_idx.size()));
+  h.off_lanes = (int)off; off = align16(off + sizeof(QLane) * hp->lanes.size());
   h.bytes = (int)off;
   hp->blob.assign(off, 0);
   std::memcpy(hp->blob.data(), &h, sizeof(h));
@@ -589,6 +625,7 @@ image:
   if (!hp->docc.empty()) std::memcpy(hp->blob.data() + h.off_docc, hp->docc.data(), sizeof(int32_t) * hp->docc.size());
   std::memcpy(hp->blob.data() + h.off_dcsr_ptr, hp->dcsr_ptr.data(), sizeof(int32_t) * hp->dcsr_ptr.size());
   if (!hp->dcsr_idx.empty()) std::memcpy(hp->blob.data() + h.off_dcsr_idx, hp->dcsr_idx.data(), sizeof(int32_t) * hp->dcsr_idx.size());
+  if (!hp->lanes.empty()) std::memcpy(hp->blob.data() + h.off_lanes, hp->lanes.data(), sizeof(QLane) * hp->lanes.size());
   return "";
 }
 

@@ -24,9 +24,11 @@ struct HostPlan {
   std::vector<QFused> fused;
   std::vector<QRound> rounds;
   std::vector<QXchg> xf, xb;          // indexed by round (entry 0 unused)
+  std::vector<QLane> lanes;            // [2][rounds][2^(n-3)] per-lane exchange words
   uint32_t zmask[kMaxOut] = {0};
   std::vector<int32_t> csr_ptr, csr_idx;
   int n_exchanges = 0;                 // exchanges that move data
+  bool has_signs = false;              // some exchange carries CZ signs
   int n_head = 0;                      // leading rounds folded into the encoding
   int32_t head_gate[16];               // per qubit: its leading-stage fused gate, or -1
   // dense-block plan (MFMA path)

@@ -74,6 +74,14 @@ struct alignas(16) QXchg {
   uint32_t roff[8];   // 8 * lds_swizzle of register r's uniform source offset: byte offset, reader side
 };
 static_assert(sizeof(QXchg) == 432, "QXchg layout");
+
+// Per-lane words of one exchange for the thread u of a point (u < 2^(n-3)): the writer's and the
+// reader's LDS byte bases 8 swz(thread part of the index) in their mappings (the reader's through
+// the index map A), and bit r set where register r's amplitude changes sign.  A point's base
+// index pbase enters as 8 swz(pbase), XORed into both bases (swz is linear over GF(2)).
+struct alignas(16) QLane {
+  uint32_t wb, rb, sgn, pad;
+};
 static_assert(sizeof(QRound) == 224, "QRound layout");
 
 // Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).  stat_out: the
@@ -126,6 +134,7 @@ struct alignas(16) QPlanDev {
   uint32_t zplain[kMaxOut];         // readout parity mask of output i without folding
   int32_t n_head;                   // leading rounds folded into the encoding (rounds 0 .. n_head-1; < n_rounds)
   int32_t head_gate[16];            // per qubit: fused gate of the leading stage, -1 if none
+  int32_t off_lanes;                // QLane[2][n_rounds][2^(n-3)]: forward (0) and reverse (1) exchanges
 };
 
 }  // namespace qp

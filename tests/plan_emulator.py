@@ -22,7 +22,7 @@ HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused",
                 ("off_rff_B", "<i4"), ("off_rff_W", "<i4"), ("bytes", "<i4"), ("n_dgroups", "<i4"),
                 ("off_dgroups", "<i4"), ("off_dgates", "<i4"), ("n_docc", "<i4"), ("off_docc", "<i4"),
                 ("off_dcsr_ptr", "<i4"), ("off_dcsr_idx", "<i4"), ("zplain", "<u4", 8), ("n_head", "<i4"),
-                ("head_gate", "<i4", 16)])
+                ("head_gate", "<i4", 16), ("off_lanes", "<i4")])
 ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("sgate", "<i4", 2), ("pad1", "<i4", 2),
                   ("tpos", "<i4", 16), ("tpost", "<i4", 16), ("woff", "<u4", 8), ("woffp", "<u4", 8)])
 XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("qv", "<u4", 32), ("ue", "<u4", 3),
@@ -30,6 +30,7 @@ XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("
                  ("pad1", "<u4", 2), ("roff", "<u4", 8)])
 FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3), ("stat_out", "<i4"),
                   ("pad", "<i4", 3)])
+LANE = np.dtype([("wb", "<u4"), ("rb", "<u4"), ("sgn", "<u4"), ("pad", "<u4")])
 assert ROUND.itemsize == 224 and XCHG.itemsize == 432 and FUSED.itemsize == 48
 
 
@@ -51,6 +52,9 @@ def plan_image(circ):
         "xf": np.frombuffer(raw, XCHG, R, int(h["off_xf"])),
         "xb": np.frombuffer(raw, XCHG, R, int(h["off_xb"])),
         "fused": np.frombuffer(raw, FUSED, int(h["n_fused"]), int(h["off_fused"])),
+        # per-lane exchange words [direction][round][thread of the point]
+        "lanes": np.frombuffer(raw, LANE, 2 * R * (1 << (int(h["n"]) - 3)),
+                               int(h["off_lanes"])).reshape(2, R, 1 << (int(h["n"]) - 3)) if R else None,
         "csr_ptr": np.frombuffer(raw, "<i4", int(h["n_params"]) + 1, int(h["off_csr_ptr"])),
     }
     nnz = int(plan["csr_ptr"][-1])
@@ -106,45 +110,58 @@ def _swap(regs, i):
     return out
 
 
-def _exchange(regs, wpos, rpos, X, n, TP):
+def _swz(i):
+    """The LDS index swizzle (an involution, linear over GF(2))."""
+    return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12) ^ (i >> 16)) & 15)
+
+
+def descriptor_words(X, n, rpos, u):
+    """Reader side of an exchange for thread u from the descriptor alone (index map columns and the
+    bilinear split of the sign form): thread part of the source index sb, the eight uniform source
+    offsets and the eight sign bits."""
+    jn = _deposit(u, rpos, n)
+    if X["identity"]:
+        return jn, [_regoff(r, rpos) for r in range(8)], [0] * 8
+    sb = 0
+    for k in range(n):
+        if (jn >> k) & 1:
+            sb ^= int(X["acol"][k])
+    srcr = [int(v) for v in X["src_r"]]
+    sg = [0] * 8
+    nt = int(X["nterms"])
+    if nt:
+        xb = sb if X["sign_at_src"] else jn
+        pu = sum(_par(int(X["qu"][t]) & xb) << t for t in range(nt))
+        pv = sum(_par(int(X["qv"][t]) & xb) << t for t in range(nt))
+        q0 = _par(pu & pv)
+        bs = [_par((pu & int(X["ve"][i])) ^ (int(X["ue"][i]) & pv)) for i in range(3)]
+        for r in range(8):
+            s = q0 ^ ((int(X["qsign_r"]) >> r) & 1)
+            for i in range(3):
+                if (r >> i) & 1:
+                    s ^= bs[i]
+            sg[r] = s
+    return sb, srcr, sg
+
+
+def _exchange(regs, wpos, rpos, X, L, n, TP):
     """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point); wpos/rpos are
-    the writer's and reader's physical-to-logical bit maps."""
+    the writer's and reader's physical-to-logical bit maps, L the plan's lane words of this
+    exchange ([TP]: writer and reader LDS byte bases, sign bits), as the kernel uses them."""
     S = regs.shape[0]
     buf = np.zeros((S, 1 << n), complex)
     for u in range(TP):
-        jw = _deposit(u, wpos, n)
+        jw = _swz(int(L[u]["wb"]) >> 3)
         for r in range(8):
             buf[:, jw ^ _regoff(r, wpos)] = regs[:, u, r]
     out = np.zeros_like(regs)
+    srcr = [_regoff(r, rpos) for r in range(8)] if X["identity"] else [int(v) for v in X["src_r"]]
     for u in range(TP):
-        jn = _deposit(u, rpos, n)
-        if X["identity"]:
-            sb = jn
-            srcr = [_regoff(r, rpos) for r in range(8)]
-            sg = [0] * 8
-        else:
-            sb = 0
-            for k in range(n):
-                if (jn >> k) & 1:
-                    sb ^= int(X["acol"][k])
-            srcr = [int(v) for v in X["src_r"]]
-            sg = [0] * 8
-            nt = int(X["nterms"])
-            if nt:
-                xb = sb if X["sign_at_src"] else jn
-                pu = sum(_par(int(X["qu"][t]) & xb) << t for t in range(nt))
-                pv = sum(_par(int(X["qv"][t]) & xb) << t for t in range(nt))
-                q0 = _par(pu & pv)
-                bs = [_par((pu & int(X["ve"][i])) ^ (int(X["ue"][i]) & pv)) for i in range(3)]
-                for r in range(8):
-                    s = q0 ^ ((int(X["qsign_r"]) >> r) & 1)
-                    for i in range(3):
-                        if (r >> i) & 1:
-                            s ^= bs[i]
-                    sg[r] = s
+        sb = _swz(int(L[u]["rb"]) >> 3)
+        sg = int(L[u]["sgn"])
         for r in range(8):
             v = buf[:, sb ^ srcr[r]]
-            out[:, u, r] = -v if sg[r] else v
+            out[:, u, r] = -v if (sg >> r) & 1 else v
     return out
 
 
@@ -214,7 +231,7 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
     nsw = _swap_slots(n)
     for k in range(H, R):
         if k > 0:
-            regs[:4] = _exchange(regs[:4], rounds[k - 1]["tpost"], rounds[k]["tpos"], xf[k], n, TP)
+            regs[:4] = _exchange(regs[:4], rounds[k - 1]["tpost"], rounds[k]["tpos"], xf[k], plan["lanes"][0, k], n, TP)
         for b in range(3):
             g = int(rounds[k]["gate"][b])
             if g >= 0:
@@ -278,7 +295,7 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
                     head_m(g, b)
                     _stats(regs, b, S[g])
             if k > 0:
-                regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], n, TP)
+                regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], plan["lanes"][1, k], n, TP)
             continue
         for i in reversed(range(nsw)):   # swap-slot gates, then undo the swaps
             g = int(rounds[k]["sgate"][i])
@@ -325,7 +342,7 @@ def emulate_point(plan, params, theta, J, gate_rx, seeds_f=None, seeds_g=None, s
                 if g >= 0:
                     _stats(regs, b, S[g])
         if k > 0:
-            regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], n, TP)
+            regs = _exchange(regs, rounds[k]["tpos"], rounds[k - 1]["tpost"], xb[k], plan["lanes"][1, k], n, TP)
     return f, gg, M, S
 
 

@@ -168,6 +168,21 @@ def test_maxwell_both_exchange_shapes(ctx, n, layers):
     assert rel(res[2], res[4]) < TOL
 
 
+@pytest.mark.parametrize("case", range(7))
+def test_opening_stage_fold(ctx, case):
+    """Circuits that open with rotations (folded into the encoding, statistics at the stage output),
+    with an entangler (nothing folded), with a partial or split opening stage, or without any
+    entangler: forward, tangents, loss and gradient against the oracle, at a ragged point count."""
+    from tests.circuit_cases import opening_stage_cases
+    name, circ, nh = opening_stage_cases()[case]
+    rng = np.random.default_rng(500 + case)
+    w = W.Workload(name, circ, rng.uniform(0, 2 * math.pi, circ.n_params).astype(np.float32),
+                   rng.uniform(-1, 1, (37, 3)).astype(np.float32), W.MaxwellDesc(W.LOSS_VACUUM))
+    c, _ = _check_maxwell(ctx, w, name=name)
+    assert c.info(11) == nh
+    _check_forward(ctx, circ, w.params, w.points, name=name)
+
+
 def test_maxwell_batch_circuits_individually(ctx):
     """Every circuit of the uneven batch through the single-circuit fused path (small P)."""
     for w in W.batch_config(P_cap=40)[:8]:

@@ -8,6 +8,7 @@ import pytest
 
 import workloads as W
 from oracle import qpinn_oracle as O
+from tests.circuit_cases import opening_stage_cases
 
 LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2506_23246_amd",
                    "libqpinn.so")
@@ -62,35 +63,6 @@ def test_emulated_plan_mixed_entanglers(n):
     _run(circ, params, pts)
 
 
-def _circ(n, gates, n_params, out_qubits=(0, 1, 2)):
-    return W.Circuit(n=n, gates=list(gates), n_params=n_params, out_qubits=list(out_qubits))
-
-
-def _leading_stage_cases():
-    """Circuits that open in different ways: (name, circuit, expected number of folded rounds)."""
-    cases = []
-    n = 6   # no swap slots: 3 gates per round
-    g = W.ring(n, W.CNOT, 1)
-    c = W.layered(n, 2, "xyz", lambda l: W.ring(n, W.CNOT, 1))
-    cases.append(("rotations first", c, 2))
-    c = _circ(n, g + W.layered(n, 2, "xz", lambda l: W.ring(n, W.CZ, 1)).gates, 4 * n)
-    cases.append(("entangler first", c, 0))
-    # leading stage on qubits 1 and 4 only, then a ring, then a full layer
-    gates = [(W.RY, 1, -1, 0), (W.RZ, 4, -1, 1)] + g + W.layered(n, 1, "xyz").gates
-    gates = [(k, q0, q1, (p + 2) if (p >= 0 and i >= 2 + len(g)) else p) for i, (k, q0, q1, p) in enumerate(gates)]
-    cases.append(("partial leading stage", _circ(n, gates, 2 + 3 * n), 1))
-    # four rotations on qubit 0 split the opening rotations into two stages; only the first folds
-    gates = [(W.RX, 0, -1, 0), (W.RY, 0, -1, 1), (W.RZ, 0, -1, 2), (W.RY, 0, -1, 3), (W.RX, 2, -1, 4)] + g + \
-        [(W.RY, q, -1, 5 + q) for q in range(n)]
-    cases.append(("split opening rotations", _circ(n, gates, 5 + n), 1))
-    # no entangler at all: every round but the last folds
-    cases.append(("no entangler", W.layered(n, 1, "xyz"), 1))
-    # 10 qubits (two swap slots, 5 gates a round) and 8 qubits (one swap slot) with a CZ ring
-    cases.append(("10 qubits", W.layered(10, 2, "rot", lambda l: W.ring(10, W.CZ, 2)), 2))
-    cases.append(("8 qubits", W.layered(8, 2, "xyz", lambda l: W.ring(8, W.CNOT, 3), out_qubits=[0, 7, 3]), 2))
-    return cases
-
-
 @pytest.mark.parametrize("case", range(7))
 def test_leading_stage_folding(case):
     """The planner folds exactly the rounds of an opening rotation stage (one gate per qubit, acting
@@ -99,7 +71,7 @@ def test_leading_stage_folding(case):
     The emulated kernel, which forms the product state with those gates applied and takes their
     statistics without pulling anything back, matches the oracle's outputs, tangents and gradient."""
     from tests.plan_emulator import plan_image
-    name, circ, nh = _leading_stage_cases()[case]
+    name, circ, nh = opening_stage_cases()[case]
     plan = plan_image(circ)
     h = plan["h"]
     assert int(h["n_head"]) == nh, name
@@ -127,6 +99,41 @@ def test_leading_stage_of_the_twelve_qubit_workload():
     assert int(h["n_rounds"]) == 32 and int(h["n_head"]) == 4
     assert sorted(int(x) for x in h["head_gate"][:12]) == list(range(12))
     assert all(int(x) == -1 for x in h["head_gate"][12:])
+
+
+def _lane_cases():
+    rng_rings = lambda n: [W.ring(n, W.CNOT, 1) + W.ring(n, W.CZ, 2), W.ring(n, W.CZ, 1), W.ring(n, W.CNOT, 2)]
+    out = [W.config(k, P=1).circuit for k in (1, 2, 4)]
+    for n in (3, 5, 8, 10, 11):
+        rings = rng_rings(n)
+        out.append(W.layered(n, 3, "xyz", lambda l, rings=rings: rings[l], out_qubits=[0, n - 1, n // 2]))
+    return out
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_plan_lane_words(case):
+    """The planner's per-lane exchange words (writer base, reader base, sign bits per register),
+    which the kernel loads instead of deriving them, agree for every exchange and thread with the
+    writer's deposit and with the reader side computed from the exchange descriptor alone (GF(2)
+    index-map columns and the bilinear split of the CZ sign form), an independent derivation."""
+    from tests.plan_emulator import _deposit, _swz, descriptor_words, plan_image
+    circ = _lane_cases()[case]
+    plan = plan_image(circ)
+    n, R = circ.n, int(plan["h"]["n_rounds"])
+    TP = 1 << (n - 3)
+    rounds, L = plan["rounds"], plan["lanes"]
+    assert L.shape == (2, R, TP)
+    for k in range(1, R):
+        for d, (wmap, rmap, X) in enumerate([(rounds[k - 1]["tpost"], rounds[k]["tpos"], plan["xf"][k]),
+                                             (rounds[k]["tpos"], rounds[k - 1]["tpost"], plan["xb"][k])]):
+            for u in range(TP):
+                lw = L[d, k, u]
+                assert int(lw["wb"]) == 8 * _swz(_deposit(u, wmap, n)), (case, k, d, u)
+                sb, _, sg = descriptor_words(X, n, rmap, u)
+                assert int(lw["rb"]) == 8 * _swz(sb), (case, k, d, u)
+                assert int(lw["sgn"]) == sum(b << r for r, b in enumerate(sg)), (case, k, d, u)
+    for f in ("wb", "rb", "sgn"):   # round 0 has no exchange
+        assert np.all(L[:, 0][f] == 0)
 
 
 def _swz(i):
