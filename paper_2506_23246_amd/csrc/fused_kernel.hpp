@@ -622,50 +622,60 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       // gate and swap slots) and writes it, then runs the bit-0/1 gates of the group just read:
       // the finishing work covers the read latency and the writes drain under the following
       // gates.  Every barrier separates a plane pair's reads from its next writes.
-      // pend: group B still has the rest of round k - 1 to do (not so after the encoding).
+      // All four statevectors complete in round k0 - 1's output mapping: the encoding leaves them
+      // there when the opening stage is folded (k0 = H); otherwise round 0 runs here (k0 = 1).
       int k0 = H;
-      bool pend = false;
       RoundCoef Rc = load_round<false, NS>(rounds + (H > 0 ? H - 1 : 0), gtab, F);
       if (k0 == 0) {
         round_fwd<0, NS>(sr, si, Rc);
-        gates01<2>(sr, si, Rc);
-        pend = true;
+        round_fwd<2, NS>(sr, si, Rc);
         k0 = 1;
       }
       if (k0 < R) {
         Offs wo = load_offs(rounds[k0 - 1].woff);
-        XLane x = lane_words(lanes, 0, R, k0, TP, u, pb8);
-        xwrite<T, 0, 1, 0>(sr, si, buf, wo, x.wb);
-        for (int k = k0; k < R; ++k) {
+        // lane words of the current exchange as scalars (updated inside the lambda below)
+        uint32_t xwb, xrb, xsg;
+        {
+          const XLane x0 = lane_words(lanes, 0, R, k0, TP, u, pb8);
+          xwb = x0.wb; xrb = x0.rb; xsg = x0.sgn;
+        }
+        xwrite<T, 0, 1, 0>(sr, si, buf, wo, xwb);
+        // Iteration k: group A is read and runs round k; group B lags by half a round (it finishes
+        // round k - 1 while A's read is in flight, except in the first iteration, where it is
+        // complete).  The first iteration is peeled so that neither copy has a branch around
+        // group B's work.
+        auto iter = [&](int k, auto lag) {
+          constexpr bool LAG = decltype(lag)::value;
           CP<QRound> rk = rounds + k;
           const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
           const Offs ro = load_offs(xf[k].roff);
           const bool sg = xf[k].nterms != 0;
           // the next exchange's lane words: a vector load issued a whole round ahead of its use
-          XLane xn = x;
+          XLane xn{xwb, xrb, xsg};
           if (k + 1 < R) xn = lane_words(lanes, 0, R, k + 1, TP, u, pb8);
           __syncthreads();
-          xread<T, 0, 1, 0, SG>(sr, si, buf, ro, sg, x.rb, x.sgn);
-          if (pend) finish<2, NS>(sr, si, Rc);         // group B finishes round k - 1
-          xwrite<T, 2, 3, 2>(sr, si, buf, wo, x.wb);
+          xread<T, 0, 1, 0, SG>(sr, si, buf, ro, sg, xrb, xsg);
+          if (LAG) finish<2, NS>(sr, si, Rc);          // group B finishes round k - 1
+          xwrite<T, 2, 3, 2>(sr, si, buf, wo, xwb);
           gates01<0>(sr, si, Rk);
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
           // The next exchange's write offsets, loaded before the barrier: scalar loads share the
           // wait counter with LDS operations, and waiting here costs nothing.
           if (k + 1 < R) wo = load_offs(rk->woff);
           __syncthreads();
-          xread<T, 2, 3, 2, SG>(sr, si, buf, ro, sg, x.rb, x.sgn);
+          xread<T, 2, 3, 2, SG>(sr, si, buf, ro, sg, xrb, xsg);
           finish<0, NS>(sr, si, Rk);                   // group A finishes round k
           if (k + 1 < R) xwrite<T, 0, 1, 0>(sr, si, buf, wo, xn.wb);
           gates01<2>(sr, si, Rk);
           pin_sv<2>(sr, si); pin_sv<3>(sr, si);
-          x = xn;
+          xwb = xn.wb; xrb = xn.rb; xsg = xn.sgn;
           Rc = Rk;
-          pend = true;
-        }
+        };
+        iter(k0, BoolC<false>{});
+        for (int k = k0 + 1; k < R; ++k) iter(k, BoolC<true>{});
         __syncthreads();
+        finish<2, NS>(sr, si, Rc);                     // group B finishes the last round
       }
-      if (pend) finish<2, NS>(sr, si, Rc);             // group B finishes the last round
     } else {
       for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
