@@ -169,7 +169,7 @@ __global__ void k_param_grads(const QPlanDev* __restrict__ plan, const float* __
   grads[k] = (float)param_grad_one(plan, params, m64, k);
 }
 
-int fused_threads(int n) { return n == 12 ? 512 : 256; }
+int fused_threads(int n) { return fused_wg_threads(n); }
 int fused_points_per_tile(int n) { return fused_threads(n) / (1 << (n - 3)); }
 size_t fused_lds_bytes(int n, int exs, int n_fused) {
   const int T = fused_threads(n);

@@ -130,12 +130,14 @@ __device__ __forceinline__ float wave_reduce_scatter4(const float* v) {
 
 // ---- register exchange through LDS ----------------------------------------------------------
 // An exchange moves the statevectors from the writer round's mapping to the reader round's
-// mapping: each thread writes its registers at their logical indices (swizzled) and reads back
-// the amplitudes its registers hold in the new mapping, through the descriptor X (index map A
-// and sign (-1)^Q).  Address arithmetic: pbase is a multiple of 2^N and every index is below
-// 2^N, so pbase + x equals pbase ^ x; the swizzle is linear over GF(2), so
-// swz(pbase ^ j ^ o) = swz(pbase ^ j) ^ swz(o), and the planner stores 8 swz(o) (byte offsets of
-// complex64 entries) for the eight register offsets (woff for the writer, roff for the reader).
+// mapping: each thread writes its registers at their logical indices and reads back the
+// amplitudes its registers hold in the new mapping, through the descriptor X (index map A and
+// sign (-1)^Q).  Logical index j of a point lives at LDS entry swz(pbase ^ M j), M an invertible
+// GF(2) map chosen per exchange for conflict-free banks.  Address arithmetic: pbase is a multiple
+// of 2^N and every index is below 2^N, so pbase + x equals pbase ^ x; M and the swizzle are linear
+// over GF(2), so the entry of j ^ o is the entry of j XOR swz(M o), and the planner stores
+// 8 swz(M o) (byte offsets of complex64 entries) for the eight register offsets (woff for the
+// writer, roff for the reader).
 // Per exchange a lane needs three words: its writer and reader byte bases and the sign bits of
 // its eight reads (the planner tabulates them per thread of a point: QLane); each access then
 // costs one XOR.
@@ -262,9 +264,9 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
 // holds only two planes per workgroup).
 template <int N, int T, int NSV, int EXS>
 __device__ __forceinline__ void exchange(float (&sr)[8][8], float (&si)[8][8], float2* __restrict__ buf,
-                                         CP<uint32_t> woff, CP<QXchg> X, const XLane& x) {
+                                         CP<QXchg> X, const XLane& x) {
   static_assert(EXS == 2, "pairs of planes");
-  const Offs wo = load_offs(woff), ro = load_offs(X->roff);
+  const Offs wo = load_offs(X->woff), ro = load_offs(X->roff);
   const bool sg = X->nterms != 0;
 #pragma unroll
   for (int g = 0; g < NSV; g += 2) {
@@ -632,7 +634,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         k0 = 1;
       }
       if (k0 < R) {
-        Offs wo = load_offs(rounds[k0 - 1].woff);
+        Offs wo = load_offs(xf[k0].woff);
         // lane words of the current exchange as scalars (updated inside the lambda below)
         uint32_t xwb, xrb, xsg;
         {
@@ -661,7 +663,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           pin_sv<0>(sr, si); pin_sv<1>(sr, si);
           // The next exchange's write offsets, loaded before the barrier: scalar loads share the
           // wait counter with LDS operations, and waiting here costs nothing.
-          if (k + 1 < R) wo = load_offs(rk->woff);
+          if (k + 1 < R) wo = load_offs(xf[k + 1].woff);
           __syncthreads();
           xread<T, 2, 3, 2, SG>(sr, si, buf, ro, sg, xrb, xsg);
           finish<0, NS>(sr, si, Rk);                   // group A finishes round k
@@ -679,7 +681,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     } else {
       for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
-        if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, rk[-1].woff, xf + k, lane_words(lanes, 0, R, k, TP, u, pb8));
+        if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, xf + k, lane_words(lanes, 0, R, k, TP, u, pb8));
         const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
         round_fwd<0, NS>(sr, si, Rk);
         round_fwd<2, NS>(sr, si, Rk);
@@ -832,7 +834,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       CP<QRound> rl = rounds + (R - 1);
       round_adj_all<NS, true>(sr, si, rl, gtab, F, slots, wave, lane);
       if (R > 1) {
-        Offs wo = load_offs(rl->woffp);
+        Offs wo = load_offs(xb[R - 1].woff);
         // the current exchange's lane words as plain scalars (the loop body below is a lambda that
         // updates them; an aggregate captured by reference would not stay in registers)
         uint32_t xwb, xrb, xsg;
@@ -880,7 +882,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           round_adj<2, NS, PULL>(sr, si, Rp, q);
           pin_sv<2>(sr, si); pin_sv<6>(sr, si); pin_q<NQ>(q);
           // the next exchange's write offsets (scalar, before the barrier as in the forward sweep)
-          if (k > 1) wo = load_offs(rp->woffp);
+          if (k > 1) wo = load_offs(xb[k - 1].woff);
           __syncthreads();
           xread<T, 3, 7, 2, SG>(sr, si, buf, ro, sg, xrb, xsg);
           // and its lane words: a vector load (its own wait counter), covered by the statistics
@@ -903,12 +905,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = R - 1; k >= H; --k) {
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, true>(sr, si, rk, gtab, F, slots, wave, lane);
-        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
+        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
       for (int k = H - 1; k >= 0; --k) {   // the leading stage: statistics only
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, false>(sr, si, rk, gtab, F, slots, wave, lane);
-        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, rk->woffp, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
+        if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
     }
   }
@@ -973,7 +975,7 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
 
 template <int N, int EXS, int MODE, bool SG>
 hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) {
-  constexpr int T = (N == 12) ? 512 : 256;
+  constexpr int T = fused_wg_threads(N);
   auto kern = k_fused<N, T, EXS, MODE, SG>;
   // lds counts the static exchange planes and the dynamic part; only the latter is passed.
   const size_t planes = (size_t)EXS * T * 8 * sizeof(float2);

@@ -158,7 +158,6 @@ void fill_xchg(QXchg* X, int n, const uint32_t* Acols, const Affine& aff, bool s
   bool ident = aff.terms.empty();
   for (int k = 0; k < n; ++k) ident = ident && (Acols[k] == (1u << k));
   X->identity = ident ? 1u : 0u;
-  for (int r = 0; r < 8; ++r) X->roff[r] = 8u * lds_swizzle(ident ? jr_of(read_tpos, r) : X->src_r[r]);
 }
 
 // Thread part of the logical index of thread u in mapping map (thread bit k - 3 at position map[k]).
@@ -168,15 +167,105 @@ uint32_t deposit_host(uint32_t u, const int32_t* map, int n) {
   return j;
 }
 
+// ---- LDS layout of one exchange --------------------------------------------------------------
+// Logical index j is stored at entry swz(pbase ^ M j).  The 64-bit accesses of a group of 16 lanes
+// are served without bank conflicts when the low four bits of their entries are distinct (the
+// model the measured conflict counters support; a 32-lane, five-bit criterion raised them 4.6x).
+// Each access of a register r adds a uniform offset, which does not change distinctness, so what
+// matters is the thread part: the writer's deposit of the thread id and the reader's source index
+// A jn.  The planner picks M per exchange: the identity if it already gives distinct banks, else
+// the best of a deterministic sequence of candidates (bit permutations, some with extra XORs of
+// low bits), keeping M invertible.
+struct MapSearch {
+  uint32_t state = 0x9E3779B9u;
+  uint32_t next() {   // xorshift32
+    state ^= state << 13; state ^= state >> 17; state ^= state << 5;
+    return state;
+  }
+};
+
+bool gf2_invertible(const uint32_t* cols, int n) {
+  uint32_t inv[16];
+  return gf2_inverse(cols, n, inv);
+}
+
+// Sum and minimum over the 16-lane groups of a workgroup of the number of distinct banks (low four
+// bits of the entry), writer side and reader side.
+void bank_score(int n, int T, const uint32_t* M, const std::vector<uint32_t>& wj,
+                const std::vector<uint32_t>& rj, int* minv, int* sum) {
+  const int TP = 1 << (n - 3);
+  *minv = 64;
+  *sum = 0;
+  for (int side = 0; side < 2; ++side) {
+    const std::vector<uint32_t>& J = side ? rj : wj;
+    for (int h0 = 0; h0 < T; h0 += 16) {
+      uint32_t seen = 0;
+      for (int t = h0; t < h0 + 16 && t < T; ++t) {
+        const uint32_t pbase = (uint32_t)(t / TP) << n;
+        seen |= 1u << (lds_swizzle(pbase ^ apply_cols(M, n, J[t % TP])) & 15u);
+      }
+      const int d = __builtin_popcount(seen);
+      *minv = std::min(*minv, d);
+      *sum += d;
+    }
+  }
+}
+
+void choose_index_map(int n, int T, const int32_t* wmap, const int32_t* rmap, const uint32_t* Acols, int salt,
+                      uint32_t* M) {
+  const int TP = 1 << (n - 3);
+  std::vector<uint32_t> wj(TP), rj(TP);
+  for (int u = 0; u < TP; ++u) {
+    wj[u] = deposit_host((uint32_t)u, wmap, n);
+    rj[u] = apply_cols(Acols, n, deposit_host((uint32_t)u, rmap, n));
+  }
+  const int target = std::min(16, T);
+  uint32_t best[16];
+  for (int k = 0; k < 16; ++k) best[k] = k < n ? (1u << k) : 0u;
+  int bmin, bsum;
+  bank_score(n, T, best, wj, rj, &bmin, &bsum);
+  MapSearch rng;
+  rng.state ^= (uint32_t)salt * 0x85EBCA6Bu;
+  for (int it = 0; it < 400 && bmin < target; ++it) {
+    uint32_t cand[16];
+    int perm[16];
+    for (int k = 0; k < n; ++k) perm[k] = k;
+    for (int k = n - 1; k > 0; --k) std::swap(perm[k], perm[rng.next() % (uint32_t)(k + 1)]);
+    for (int k = 0; k < 16; ++k) cand[k] = k < n ? (1u << perm[k]) : 0u;
+    if (it & 1) {   // add low-bit XORs to some columns
+      for (int k = 0; k < n; ++k)
+        if ((rng.next() & 3u) == 0) cand[k] ^= rng.next() & 15u & ((1u << n) - 1u);
+      if (!gf2_invertible(cand, n)) continue;
+    }
+    int cmin, csum;
+    bank_score(n, T, cand, wj, rj, &cmin, &csum);
+    if (cmin > bmin || (cmin == bmin && csum > bsum)) {
+      bmin = cmin;
+      bsum = csum;
+      for (int k = 0; k < 16; ++k) best[k] = cand[k];
+    }
+  }
+  for (int k = 0; k < 16; ++k) M[k] = best[k];
+}
+
+// Register offsets of both sides in the exchange's LDS layout.
+void set_lds_layout(QXchg* X, int n, const uint32_t* M, const int32_t* wmap, const int32_t* rmap, const uint32_t* Acols) {
+  for (int k = 0; k < 16; ++k) X->mcol[k] = M[k];
+  for (int r = 0; r < 8; ++r) {
+    X->woff[r] = 8u * lds_swizzle(apply_cols(M, n, jr_of(wmap, r)));
+    X->roff[r] = 8u * lds_swizzle(apply_cols(M, n, apply_cols(Acols, n, jr_of(rmap, r))));
+  }
+}
+
 // Lane words of one exchange for thread u: the writer writes register r at wdep ^ jr_w(r); the
 // reader's register r holds the amplitude of logical index j = jn ^ jr_r(r) in its mapping, read
 // from A j and negated where Q(x) = 1, x = A j (sign in source coordinates) or x = j.
 QLane lane_words(int n, const uint32_t* Acols, const Affine& aff, bool sign_at_src, const int32_t* wmap,
-                 const int32_t* rmap, uint32_t u) {
+                 const int32_t* rmap, const uint32_t* M, uint32_t u) {
   QLane L{};
   const uint32_t wdep = deposit_host(u, wmap, n), jn = deposit_host(u, rmap, n);
-  L.wb = 8u * lds_swizzle(wdep);
-  L.rb = 8u * lds_swizzle(apply_cols(Acols, n, jn));
+  L.wb = 8u * lds_swizzle(apply_cols(M, n, wdep));
+  L.rb = 8u * lds_swizzle(apply_cols(M, n, apply_cols(Acols, n, jn)));
   for (int r = 0; r < 8; ++r) {
     const uint32_t j = jn ^ jr_of(rmap, r);
     L.sgn |= qform(aff.terms, sign_at_src ? apply_cols(Acols, n, j) : j) << r;
@@ -415,10 +504,6 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     make_tpos(n, reg, fixed, R.tpos);
     for (int k = 0; k < 16; ++k) R.tpost[k] = R.tpos[k];
     for (int i = 0; i < nsw; ++i) std::swap(R.tpost[i], R.tpost[3 + 4 + i]);
-    for (int r = 0; r < 8; ++r) {
-      R.woff[r] = 8u * lds_swizzle(jr_of(R.tpost, r));    // complex64 bytes
-      R.woffp[r] = 8u * lds_swizzle(jr_of(R.tpos, r));
-    }
     hp->rounds.push_back(R);
     round_ent.push_back(pending);
     round_has_ent.push_back(have_pending);
@@ -562,11 +647,17 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     hp->n_exchanges++;
     if (hp->xf[k].nterms != 0 || hp->xb[k].nterms != 0) hp->has_signs = true;
     // forward: round k-1's output mapping -> round k's input mapping; reverse: the other way
+    const int T = fused_wg_threads(n);
+    uint32_t Mf[16], Mb[16];
+    choose_index_map(n, T, hp->rounds[k - 1].tpost, hp->rounds[k].tpos, a.acol, 2 * k, Mf);
+    choose_index_map(n, T, hp->rounds[k].tpos, hp->rounds[k - 1].tpost, inv, 2 * k + 1, Mb);
+    set_lds_layout(&hp->xf[k], n, Mf, hp->rounds[k - 1].tpost, hp->rounds[k].tpos, a.acol);
+    set_lds_layout(&hp->xb[k], n, Mb, hp->rounds[k].tpos, hp->rounds[k - 1].tpost, inv);
     for (int u = 0; u < TP; ++u) {
       hp->lanes[((size_t)0 * R + k) * TP + u] =
-          lane_words(n, a.acol, a, false, hp->rounds[k - 1].tpost, hp->rounds[k].tpos, (uint32_t)u);
+          lane_words(n, a.acol, a, false, hp->rounds[k - 1].tpost, hp->rounds[k].tpos, Mf, (uint32_t)u);
       hp->lanes[((size_t)1 * R + k) * TP + u] =
-          lane_words(n, inv, a, true, hp->rounds[k].tpos, hp->rounds[k - 1].tpost, (uint32_t)u);
+          lane_words(n, inv, a, true, hp->rounds[k].tpos, hp->rounds[k - 1].tpost, Mb, (uint32_t)u);
     }
   }
 

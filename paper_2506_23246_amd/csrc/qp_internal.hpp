@@ -44,6 +44,9 @@ constexpr int kGT = 16;
 // still leave an empty slot (11), saving an exchange does not pay for the swaps (measured at 12).
 QP_HD inline constexpr int swap_slots(int n) { return n == 10 ? 2 : (n == 8 ? 1 : 0); }
 
+// Threads per workgroup of the fused kernels (a thread holds 8 amplitudes of each statevector).
+QP_HD inline constexpr int fused_wg_threads(int n) { return n == 12 ? 512 : 256; }
+
 struct alignas(16) QRound {
   int32_t gate[3];    // fused-gate id applied on register bit b in the round's input mapping (-1: none)
   int32_t pad0;
@@ -51,8 +54,6 @@ struct alignas(16) QRound {
   int32_t pad1[2];
   int32_t tpos[16];   // input mapping: logical index-bit position of physical bit k
   int32_t tpost[16];  // output mapping (tpos with the swap slots applied)
-  uint32_t woff[8];   // 8 * lds_swizzle of register r's offset in the output mapping (forward writer)
-  uint32_t woffp[8];  // the same in the input mapping (writer of the reverse exchange)
 };
 // One direction of the register exchange that precedes a round.  Reader thread (u, r) in the
 // read mapping holds logical index jn = base(u) ^ jr(r); it takes the amplitude stored at
@@ -71,9 +72,14 @@ struct alignas(16) QXchg {
   uint32_t qsign_r;   // bit r: Q(x_r) for the uniform part x_r
   uint32_t identity;  // A = I and no sign terms
   uint32_t pad1[2];
-  uint32_t roff[8];   // 8 * lds_swizzle of register r's uniform source offset: byte offset, reader side
+  // LDS layout of the exchange: logical index j sits at entry swz(pbase ^ M j), M an invertible
+  // GF(2) map of the n index bits (columns mcol) that the planner chooses per exchange so that
+  // every group of 16 lanes hits 16 distinct banks when writing and when reading.
+  uint32_t roff[8];   // 8 swz(M A jr(r)): register r's uniform source offset in bytes, reader side
+  uint32_t woff[8];   // 8 swz(M jr(r)): register r's offset in the writer's mapping, in bytes
+  uint32_t mcol[16];
 };
-static_assert(sizeof(QXchg) == 432, "QXchg layout");
+static_assert(sizeof(QXchg) == 528, "QXchg layout");
 
 // Per-lane words of one exchange for the thread u of a point (u < 2^(n-3)): the writer's and the
 // reader's LDS byte bases 8 swz(thread part of the index) in their mappings (the reader's through
@@ -82,7 +88,7 @@ static_assert(sizeof(QXchg) == 432, "QXchg layout");
 struct alignas(16) QLane {
   uint32_t wb, rb, sgn, pad;
 };
-static_assert(sizeof(QRound) == 224, "QRound layout");
+static_assert(sizeof(QRound) == 160, "QRound layout");
 
 // Fused single-qubit gate: U = R_{c-1} ... R_1 R_0 (component 0 acts first).  stat_out: the
 // gate belongs to the leading rotation stage, which acts on the product state and is folded into

@@ -24,14 +24,14 @@ HDR = np.dtype([("n", "<i4"), ("n_params", "<i4"), ("n_out", "<i4"), ("n_fused",
                 ("off_dcsr_ptr", "<i4"), ("off_dcsr_idx", "<i4"), ("zplain", "<u4", 8), ("n_head", "<i4"),
                 ("head_gate", "<i4", 16), ("off_lanes", "<i4")])
 ROUND = np.dtype([("gate", "<i4", 3), ("pad0", "<i4"), ("sgate", "<i4", 2), ("pad1", "<i4", 2),
-                  ("tpos", "<i4", 16), ("tpost", "<i4", 16), ("woff", "<u4", 8), ("woffp", "<u4", 8)])
+                  ("tpos", "<i4", 16), ("tpost", "<i4", 16)])
 XCHG = np.dtype([("acol", "<u4", 16), ("src_r", "<u4", 8), ("qu", "<u4", 32), ("qv", "<u4", 32), ("ue", "<u4", 3),
                  ("ve", "<u4", 3), ("nterms", "<u4"), ("sign_at_src", "<u4"), ("qsign_r", "<u4"), ("identity", "<u4"),
-                 ("pad1", "<u4", 2), ("roff", "<u4", 8)])
+                 ("pad1", "<u4", 2), ("roff", "<u4", 8), ("woff", "<u4", 8), ("mcol", "<u4", 16)])
 FUSED = np.dtype([("qubit", "<i4"), ("ncomp", "<i4"), ("kind", "<i4", 3), ("param", "<i4", 3), ("stat_out", "<i4"),
                   ("pad", "<i4", 3)])
 LANE = np.dtype([("wb", "<u4"), ("rb", "<u4"), ("sgn", "<u4"), ("pad", "<u4")])
-assert ROUND.itemsize == 224 and XCHG.itemsize == 432 and FUSED.itemsize == 48
+assert ROUND.itemsize == 160 and XCHG.itemsize == 528 and FUSED.itemsize == 48
 
 
 def plan_image(circ):
@@ -145,22 +145,24 @@ def descriptor_words(X, n, rpos, u):
 
 
 def _exchange(regs, wpos, rpos, X, L, n, TP):
-    """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point); wpos/rpos are
-    the writer's and reader's physical-to-logical bit maps, L the plan's lane words of this
-    exchange ([TP]: writer and reader LDS byte bases, sign bits), as the kernel uses them."""
+    """regs: [S][TP][8] complex -> new regs (the kernel's exchange, for one point at pbase = 0);
+    wpos/rpos are the writer's and reader's physical-to-logical bit maps (unused: the emulation
+    goes through the kernel's own address tables), L the plan's lane words of this exchange
+    ([TP]: writer and reader LDS byte bases, sign bits).  Every thread writes register r at byte
+    wb ^ woff[r] and reads register r from rb ^ roff[r], negated where its sign bit is set."""
     S = regs.shape[0]
-    buf = np.zeros((S, 1 << n), complex)
+    buf = {}
     for u in range(TP):
-        jw = _swz(int(L[u]["wb"]) >> 3)
         for r in range(8):
-            buf[:, jw ^ _regoff(r, wpos)] = regs[:, u, r]
+            addr = int(L[u]["wb"]) ^ int(X["woff"][r])
+            assert addr not in buf, "two writes to one LDS entry"
+            buf[addr] = regs[:, u, r]
+    assert len(buf) == 8 * TP
     out = np.zeros_like(regs)
-    srcr = [_regoff(r, rpos) for r in range(8)] if X["identity"] else [int(v) for v in X["src_r"]]
     for u in range(TP):
-        sb = _swz(int(L[u]["rb"]) >> 3)
         sg = int(L[u]["sgn"])
         for r in range(8):
-            v = buf[:, sb ^ srcr[r]]
+            v = buf[int(L[u]["rb"]) ^ int(X["roff"][r])]
             out[:, u, r] = -v if (sg >> r) & 1 else v
     return out
 

@@ -115,7 +115,8 @@ def test_plan_lane_words(case):
     """The planner's per-lane exchange words (writer base, reader base, sign bits per register),
     which the kernel loads instead of deriving them, agree for every exchange and thread with the
     writer's deposit and with the reader side computed from the exchange descriptor alone (GF(2)
-    index-map columns and the bilinear split of the CZ sign form), an independent derivation."""
+    index-map columns and the bilinear split of the CZ sign form), an independent derivation; both
+    bases through the exchange's LDS layout map M."""
     from tests.plan_emulator import _deposit, _swz, descriptor_words, plan_image
     circ = _lane_cases()[case]
     plan = plan_image(circ)
@@ -126,11 +127,12 @@ def test_plan_lane_words(case):
     for k in range(1, R):
         for d, (wmap, rmap, X) in enumerate([(rounds[k - 1]["tpost"], rounds[k]["tpos"], plan["xf"][k]),
                                              (rounds[k]["tpos"], rounds[k - 1]["tpost"], plan["xb"][k])]):
+            M = [int(c) for c in X["mcol"][:n]]
             for u in range(TP):
                 lw = L[d, k, u]
-                assert int(lw["wb"]) == 8 * _swz(_deposit(u, wmap, n)), (case, k, d, u)
+                assert int(lw["wb"]) == 8 * _swz(_apply_cols(M, _deposit(u, wmap, n))), (case, k, d, u)
                 sb, _, sg = descriptor_words(X, n, rmap, u)
-                assert int(lw["rb"]) == 8 * _swz(sb), (case, k, d, u)
+                assert int(lw["rb"]) == 8 * _swz(_apply_cols(M, sb)), (case, k, d, u)
                 assert int(lw["sgn"]) == sum(b << r for r, b in enumerate(sg)), (case, k, d, u)
     for f in ("wb", "rb", "sgn"):   # round 0 has no exchange
         assert np.all(L[:, 0][f] == 0)
@@ -142,27 +144,71 @@ def _swz(i):
 
 @pytest.mark.parametrize("k", [1, 2, 4])
 def test_plan_lds_offset_tables(k):
-    """The planner's swizzled LDS byte offsets: writer side woff[r] = 8 swz(register offset of r in
-    the round's output mapping) and woffp[r] the same in its input mapping; reader side
-    roff[r] = 8 swz(uniform source offset), which for an identity exchange is the reader's own
-    register offset (forward exchanges read into a round's input mapping, reverse ones into the
-    previous round's output mapping).  swz must also be linear over GF(2), which the kernel's
-    address arithmetic relies on."""
-    from tests.plan_emulator import _regoff, plan_image
-    plan = plan_image(W.config(k, P=1).circuit)
+    """The planner's LDS layout per exchange: logical index j at entry swz(pbase ^ M j) with M
+    invertible over GF(2); writer offsets woff[r] = 8 swz(M jr(r)) in the writer's mapping and
+    reader offsets roff[r] = 8 swz(M A jr(r)) in the reader's mapping (forward exchanges read into
+    a round's input mapping, reverse ones into the previous round's output mapping).  swz must be
+    linear over GF(2), which the kernel's address arithmetic relies on, and the layout must give
+    every group of 16 lanes distinct banks (low four entry bits) on both sides of every exchange at
+    8 and 12 qubits, which is what M is chosen for, and never fewer than the plain swizzle."""
+    from tests.plan_emulator import _deposit, _regoff, plan_image
+    circ = W.config(k, P=1).circuit
+    plan = plan_image(circ)
+    n = circ.n
     rounds = plan["rounds"]
-    for rd in rounds:
-        for r in range(8):
-            assert int(rd["woff"][r]) == 8 * _swz(_regoff(r, rd["tpost"]))
-            assert int(rd["woffp"][r]) == 8 * _swz(_regoff(r, rd["tpos"]))
-    for kk in range(1, len(rounds)):
-        for X, read in ((plan["xf"][kk], rounds[kk]["tpos"]), (plan["xb"][kk], rounds[kk - 1]["tpost"])):
+    R = len(rounds)
+    T = 512 if n == 12 else 256
+    TP = 1 << (n - 3)
+    distinct, plain = [], []
+    for kk in range(1, R):
+        for X, wmap, rmap in ((plan["xf"][kk], rounds[kk - 1]["tpost"], rounds[kk]["tpos"]),
+                              (plan["xb"][kk], rounds[kk]["tpos"], rounds[kk - 1]["tpost"])):
+            M = [int(c) for c in X["mcol"][:n]]
+            A = [int(c) for c in X["acol"][:n]]
+            assert _gf2_rank(M) == n
             for r in range(8):
-                src = _regoff(r, read) if X["identity"] else int(X["src_r"][r])
-                assert int(X["roff"][r]) == 8 * _swz(src)
+                assert int(X["woff"][r]) == 8 * _swz(_apply_cols(M, _regoff(r, wmap)))
+                assert int(X["roff"][r]) == 8 * _swz(_apply_cols(M, _apply_cols(A, _regoff(r, rmap))))
+            for side in range(2):
+                for h0 in range(0, T, 16):
+                    banks, banks0 = set(), set()
+                    for t in range(h0, h0 + 16):
+                        ps, u = divmod(t, TP)
+                        j = _deposit(u, wmap, n) if side == 0 else _apply_cols(A, _deposit(u, rmap, n))
+                        banks.add(_swz((ps << n) ^ _apply_cols(M, j)) & 15)
+                        banks0.add(_swz((ps << n) ^ j) & 15)
+                    distinct.append(len(banks))
+                    plain.append(len(banks0))
+    assert np.mean(distinct) >= np.mean(plain)
+    if n >= 8:
+        assert np.mean(distinct) == 16.0, np.mean(distinct)
     rng = np.random.default_rng(0)
     for a, b in rng.integers(0, 1 << 12, (200, 2)):
         assert _swz(int(a) ^ int(b)) == _swz(int(a)) ^ _swz(int(b))
+
+
+def _apply_cols(cols, x):
+    y, k = 0, 0
+    while x:
+        if x & 1:
+            y ^= cols[k]
+        x >>= 1
+        k += 1
+    return y
+
+
+def _gf2_rank(cols):
+    rows, r = list(cols), 0
+    for bit in range(32):
+        piv = next((i for i in range(r, len(rows)) if (rows[i] >> bit) & 1), None)
+        if piv is None:
+            continue
+        rows[r], rows[piv] = rows[piv], rows[r]
+        for i in range(len(rows)):
+            if i != r and (rows[i] >> bit) & 1:
+                rows[i] ^= rows[r]
+        r += 1
+    return r
 
 
 @pytest.mark.parametrize("n", [8, 9, 10, 11, 12])
