@@ -39,10 +39,11 @@ constexpr int kGT = 16;
 // Swap slots of a round: after its three register-bit gates, register bit i (i < swap_slots(n))
 // trades places with thread bit 4 + i (lane bit 4 or 5 of the wave, by a cross-lane swap of
 // register pairs), and gate sgate[i] acts on the qubit brought in.  They are used where they turn
-// a rotation stage into rounds without identity slots (8 qubits: 4 + 4; 10 qubits: 5 + 5 instead
-// of 3 + 3 + 3 + 1).  Where a stage already fills three-gate rounds (6, 9, 12 qubits) or would
-// still leave an empty slot (11), saving an exchange does not pay for the swaps (measured at 12).
-QP_HD inline constexpr int swap_slots(int n) { return n == 10 ? 2 : (n == 8 ? 1 : 0); }
+// a rotation stage into fewer rounds without identity slots (8 qubits: 4 + 4; 10 qubits: 5 + 5
+// instead of 3 + 3 + 3 + 1; 12 qubits: 4 + 4 + 4 instead of 3 + 3 + 3 + 3).  At 6 and 9 qubits
+// three-gate rounds are already full and at 11 a slot would stay empty; at 12, two swap slots
+// (5 + 5 + 2) were slower than none.
+QP_HD inline constexpr int swap_slots(int n) { return n == 10 ? 2 : ((n == 8 || n == 12) ? 1 : 0); }
 
 // Threads per workgroup of the fused kernels (a thread holds 8 amplitudes of each statevector).
 QP_HD inline constexpr int fused_wg_threads(int n) { return n == 12 ? 512 : 256; }

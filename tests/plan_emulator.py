@@ -1,8 +1,10 @@
 """CPU emulation of the fused kernel's register/LDS algorithm, driven by the planner's own
 device image (qp_plan_image).  complex128, one point at a time, every thread of the point's
-thread group emulated explicitly: registers [thread][8], exchanges through a logical-index
-buffer with the descriptor's index map and signs, readout with the plan's parity masks, and
-the adjoint sweep with uncompute and per-gate M accumulation.
+thread group emulated explicitly: registers [thread][8]; the opening rotation stage folded into
+the product state; exchanges through the kernel's own LDS byte addresses (per-lane words and
+per-exchange register offsets) and sign bits; readout with the plan's parity masks; the adjoint
+sweep with uncompute and per-gate M accumulation, the folded stage taking its statistics at its
+output.
 
 This checks the planner (fusion, GF(2) entangler maps, sign forms, round mappings, readout
 folding, gradient map) and the algorithm independently of the GPU; the oracle is the
@@ -94,7 +96,7 @@ def _fused_matrix(f, params):
 
 
 def _swap_slots(n):
-    return 2 if n == 10 else (1 if n == 8 else 0)
+    return 2 if n == 10 else (1 if n in (8, 12) else 0)
 
 
 def _swap(regs, i):

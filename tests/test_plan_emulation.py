@@ -214,13 +214,13 @@ def _gf2_rank(cols):
 @pytest.mark.parametrize("n", [8, 9, 10, 11, 12])
 def test_plan_swap_slots(n):
     """Rounds of a full rotation stage fill the register bits and the swap slots: n = 8, 9, 10, 11, 12
-    need 2, 3, 2, 4, 4 rounds per layer (swap slots at 8 and 10 qubits only); the output mapping
+    need 2, 3, 2, 4, 3 rounds per layer (one swap slot at 8 and 12 qubits, two at 10); the output mapping
     is the input mapping with register bit i and thread bit 4 + i exchanged for every swap slot."""
     from tests.plan_emulator import _swap_slots, plan_image
     circ = W.layered(n, 2, "xyz", lambda l: W.ring(n, W.CNOT, 1), out_qubits=[0, 1, 2])
     plan = plan_image(circ)
     rounds = plan["rounds"]
-    per_layer = {8: 2, 9: 3, 10: 2, 11: 4, 12: 4}[n]
+    per_layer = {8: 2, 9: 3, 10: 2, 11: 4, 12: 3}[n]
     assert len(rounds) == 2 * per_layer
     nsw = _swap_slots(n)
     for rd in rounds:
