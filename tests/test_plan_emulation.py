@@ -92,11 +92,12 @@ def test_leading_stage_folding(case):
 
 
 def test_leading_stage_of_the_twelve_qubit_workload():
-    """12 qubits x 8 layers: the first layer's twelve gates are the four folded rounds."""
+    """12 qubits x 8 layers: three rounds of four gates per layer (one swap slot), and the first
+    layer's twelve gates are the three folded rounds."""
     from tests.plan_emulator import plan_image
     plan = plan_image(W.config(4, P=1).circuit)
     h = plan["h"]
-    assert int(h["n_rounds"]) == 32 and int(h["n_head"]) == 4
+    assert int(h["n_rounds"]) == 24 and int(h["n_head"]) == 3
     assert sorted(int(x) for x in h["head_gate"][:12]) == list(range(12))
     assert all(int(x) == -1 for x in h["head_gate"][12:])
 
