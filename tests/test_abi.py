@@ -41,7 +41,7 @@ def test_error_path_without_device_is_a_status_code():
     """With no usable GPU, creating a context must fail with a status, not crash."""
     import torch
     if torch.cuda.is_available():
-        pytest.skip("GPU present; covered by the GPU error-path tests")
+        pytest.skip("GPU present; covered by tests/test_gpu_errors.py")
     from paper_2506_23246_amd import _lib
     h = ctypes.c_void_p()
     st = _lib.qp_ctx_create(0, None, ctypes.byref(h))

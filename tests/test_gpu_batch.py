@@ -61,6 +61,29 @@ def test_batch_matches_single_circuit_path(env):
         assert rel(t2n(bufs[i]["loss"]), t2n(singles[i]["loss"])) < 1e-6
 
 
+def test_batch_autotuned_grid_matches_oracle(env):
+    """QP_FLAG_TUNE times a few persistent grid sizes once; the tuned batch still matches the
+    oracle per circuit."""
+    import torch
+    from paper_2506_23246_amd import _lib as L
+    ctx, s = env
+    ws = W.batch_config(P_cap=64)
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc(), flags=L.QP_FLAG_TUNE)
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    for i in range(1, len(ws), 4):
+        w = ws[i]
+        f, g, Lo, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+        e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
+                 loss=rel(t2n(bufs[i]["loss"]), [Lo]), grad=rel(t2n(bufs[i]["grad"]), grad))
+        report(f"tuned batch {w.name} grid={b.info(2)}", **e)
+        for k, v in e.items():
+            assert v < TOL, (w.name, k, v)
+
+
 def test_batch_graph_replays_match_eager(env):
     """Capture once, replay several times with new parameters written in place and eager work
     and synchronisations between the replays; every replay equals an eager run."""

@@ -183,6 +183,28 @@ def test_opening_stage_fold(ctx, case):
     _check_forward(ctx, circ, w.params, w.points, name=name)
 
 
+@pytest.mark.parametrize("k,P", [(1, 3000), (2, 700), (4, 5)])
+def test_autotuned_launch_keeps_parity(ctx, k, P):
+    """QP_FLAG_TUNE times the legal launch shapes (exchange planes, workgroups per CU) on first use
+    and keeps the fastest: the tuned step matches the oracle, the chosen shape is a legal one, and
+    later untuned calls reuse it with bitwise-equal per-point results."""
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import Circuit
+    w = W.config(k, P=P)
+    c = Circuit(ctx, w.circuit)
+    r = c.maxwell(w.params, w.points, w.loss, flags=L.QP_FLAG_TUNE)
+    f, g, Lo, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+    errs = dict(f=rel(t2n(r["out"]), f), g=rel(t2n(r["tan"]), g), loss=rel(t2n(r["loss"]), [Lo]),
+                grad=rel(t2n(r["grad"]), grad))
+    report(f"tuned maxwell {w.name} exchange planes={c.info(8)} wg/CU={c.info(9)}", **errs)
+    for key, v in errs.items():
+        assert v < TOL, (key, v)
+    assert c.info(8) in (2, 4) and 1 <= c.info(9) <= 4
+    out0, tan0 = t2n(r["out"]).copy(), t2n(r["tan"]).copy()
+    r2 = c.maxwell(w.params, w.points, w.loss)
+    assert np.array_equal(t2n(r2["out"]), out0) and np.array_equal(t2n(r2["tan"]), tan0)
+
+
 def test_maxwell_batch_circuits_individually(ctx):
     """Every circuit of the uneven batch through the single-circuit fused path (small P)."""
     for w in W.batch_config(P_cap=40)[:8]:
