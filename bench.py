@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--no-paper-context", action="store_true",
                     help="skip the run of the paper's own circuit shape at its grid sizes")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip timing the batched circuits as separate calls (uneven-batch workload only)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the step captured in a HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -331,6 +333,42 @@ def main():
             "algorithmic_mfma_tflops": round(flops_d / t_d / 1e12, 2),
             "modelled_hbm_gbs": round(bytes_d / t_d / 1e9, 1)}
         log(f"bench: dense {line['dense_mfma']}")
+
+    if k == 3 and not args.no_separate:
+        # The same circuits, each run as its own fused Maxwell call (own plan, own launches and
+        # reductions) back to back on one stream: what the one-launch uneven batch replaces.
+        sep = []
+        for wi in ws_list:
+            ci = Circuit(ctx, wi.circuit)
+            pi = torch.tensor(wi.params, device=dev)
+            xi = torch.tensor(wi.points, device=dev)
+            bi = {"out": torch.empty((len(wi.points), 3), dtype=torch.float32, device=dev),
+                  "tan": torch.empty((len(wi.points), 3, 3), dtype=torch.float32, device=dev),
+                  "loss": torch.empty(1, dtype=torch.float64, device=dev),
+                  "grad": torch.empty(wi.circuit.n_params, dtype=torch.float32, device=dev)}
+            sep.append((ci, pi, xi, bi))
+        vac = W.MaxwellDesc(W.LOSS_VACUUM)
+
+        def run_separate():
+            for ci, pi, xi, bi in sep:
+                ci.maxwell(pi, xi, vac, bufs=bi)
+        run_separate()
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run_separate()
+        torch.cuda.synchronize()
+        t_sep = (time.perf_counter() - t0) / reps
+        line["separate_launches"] = {
+            "what": f"the same {len(sep)} circuits and points, one fused Maxwell call per circuit, "
+                    "eager, back to back on one stream",
+            "ms_per_step": round(t_sep * 1e3, 4), "evals_per_s": round(P_total / t_sep, 1),
+            "batch_speedup": round(t_sep / (ms_per_step / 1e3), 3)}
+        log(f"bench: separate {line['separate_launches']}")
+        for ci, _, _, _ in sep:
+            ci.close()
+        del sep
 
     if w is not None and not args.no_paper_context and k == 4:
         # The paper's PQC shape (7 qubits, 4 layers of Rot + CNOT ring, RX(acos a) embedding of 7
