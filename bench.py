@@ -45,8 +45,8 @@ def flops_per_point(n_fused: int, n: int) -> float:
 def executed_flops_per_point(n_fused: int, n: int, n_folded: int = 0) -> float:
     """Flops the kernel executes for the same work with mul = 1 and fma = 2: 14 per amplitude
     per statevector and gate (1 mul + 3 fma per real part), and the gate statistic
-    S_k = Im <lambda|sigma_k|psi> at 4 statevector pairs x 3 components x 4 fma x 2 per pair =
-    48 per amplitude: (4 x 14 + 8 x 14 + 48) = 216 per amplitude per gate.  The n_folded gates of
+    S_k = Im <lambda|sigma_k|psi> at 4 statevector pairs x 3 components x 4 fma x 2 = 96 per
+    amplitude pair, 48 per amplitude: (4 x 14 + 8 x 14 + 48) = 216 per amplitude per gate.  The n_folded gates of
     an opening rotation stage are folded into the product-state encoding: they are neither applied
     nor pulled back (only their statistic, 48, remains)."""
     return (2 ** n) * (float(n_fused) * 216 - float(n_folded) * 168)
