@@ -15,7 +15,10 @@
 namespace qp {
 
 constexpr int kBT = 256;   // threads per workgroup (all batch circuits have n <= 11)
-constexpr int kBEXS = 4;
+// Two exchange planes: the function holds every qubit count's tile code under one 256-VGPR cap;
+// with four planes it spills 292 bytes per lane, whose scratch (38 MB over 2048 waves) overflows
+// the L2 and nearly doubles the kernel's HBM traffic, at the same speed as two planes (128 bytes).
+constexpr int kBEXS = 2;
 
 __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGate* __restrict__ gates, int ngates,
                               int* __restrict__ counter) {
