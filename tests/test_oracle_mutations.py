@@ -1,0 +1,166 @@
+"""Planted mistakes in the CPU oracle must fail at least one of its pins (no GPU).
+
+Each case swaps one oracle function for a copy carrying a plausible slip (a wrong sign, a dropped
+factor or term, swapped operands or indices) and runs the fast pins of test_oracle_pins against
+it.  A slip that no pin notices would mean the oracle is not pinned where the slip sits.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import qpinn_oracle as O
+import test_oracle_pins as pins
+
+# the fast pins (each well under a second); the slow parameter-shift and 12-qubit cases are
+# covered by the pin suite itself
+FAST_PINS = [
+    ("ry_embedding", pins.test_ry_embedding_closed_form, ()),
+    ("rx_scaling_golden", pins.test_rx_scaling_identities_golden, ()),
+    ("rx_embedding_phase", pins.test_rx_embedding_phase_closed_form, ()),
+    ("scale_derivatives_fd", pins.test_scale_derivatives_match_finite_differences, ()),
+    ("bloch_xyz", pins.test_product_state_matches_bloch_rotations, ("xyz", 3, 3)),
+    ("bloch_rot", pins.test_product_state_matches_bloch_rotations, ("rot", 4, 2)),
+    ("bell", pins.test_bell_state, ()),
+    ("ghz_cnot_direction", pins.test_ghz_state_and_cnot_direction, ()),
+    ("bitwise_sim_0", pins.test_kron_oracle_matches_bitwise_simulator, (0,)),
+    ("bitwise_sim_1", pins.test_kron_oracle_matches_bitwise_simulator, (1,)),
+    ("cz_sign_function", pins.test_cz_stride_ring_sign_function, ()),
+    ("unitary_norm", pins.test_operators_unitary_and_norm_preserved, ()),
+    ("init_zeros", pins.test_init_zeros_gives_unit_outputs, ()),
+    ("trace_identity", pins.test_trace_identity_over_basis_encodings, ()),
+    ("tangents_fd", pins.test_tangents_match_fd_and_encoding_shift, (1,)),
+    ("rff_jacobian", pins.test_rff_jacobian_matches_fd, ()),
+    ("param_shift_mixed", pins.test_reverse_mode_equals_parameter_shift, ("mixed",)),
+    ("two_pi", pins.test_two_pi_periodicity, ()),
+    ("plane_wave", pins.test_plane_wave_is_an_exact_zero_of_every_residual, ()),
+    ("dielectric_weights", pins.test_dielectric_split_weights, ()),
+    ("seeds_gradient", pins.test_seeds_are_the_gradient_of_the_loss_in_g, ()),
+]
+
+_rotation = O.rotation
+_full_operator = O.full_operator
+_z_diagonal = O.z_diagonal
+_readout = O.readout
+_scale_derivative = O.scale_derivative
+_embed_vectors = O._embed_vectors
+_initial_states = O.initial_states
+_maxwell_terms = O.maxwell_terms
+_maxwell_seeds = O.maxwell_seeds
+_grad_reverse = O.grad_reverse
+
+
+def rotation_sign(kind, theta):                       # exp(+i theta P / 2)
+    return math.cos(theta / 2) * O.I2 + 1j * math.sin(theta / 2) * O.PAULI[kind]
+
+
+def rotation_full_angle(kind, theta):                 # half angle dropped
+    return math.cos(theta) * O.I2 - 1j * math.sin(theta) * O.PAULI[kind]
+
+
+def rotation_derivative_no_half(kind, theta):         # -i P R instead of -(i/2) P R
+    return -1j * O.PAULI[kind] @ _rotation(kind, theta)
+
+
+def full_operator_cnot_swapped(n, kind, q0, q1, theta, derivative=False):
+    if kind == O.CNOT:
+        q0, q1 = q1, q0
+    return _full_operator(n, kind, q0, q1, theta, derivative)
+
+
+def full_operator_cz_as_cnot(n, kind, q0, q1, theta, derivative=False):
+    return _full_operator(n, O.CNOT if kind == O.CZ else kind, q0, q1, theta, derivative)
+
+
+def z_diagonal_reversed(n, i):                        # qubit order reversed in the readout
+    return _z_diagonal(n, n - 1 - i)
+
+
+def readout_without_two(circ, psi, dpsi):             # g = Re psi^H Z dpsi (factor 2 dropped)
+    f, g = _readout(circ, psi, dpsi)
+    return f, 0.5 * g
+
+
+def scale_derivative_pi_dropped(kind, a):             # d(pi a)/da taken as 1
+    if kind == O.SCALE_PI:
+        return np.ones_like(a)
+    return _scale_derivative(kind, a)
+
+
+def embed_rx_conjugated(gate, theta):                 # RX(theta)|0> = (cos, +i sin)
+    v, dv = _embed_vectors(gate, theta)
+    if gate != O.ENC_RY:
+        v, dv = np.conj(v), np.conj(dv)
+    return v, dv
+
+
+def initial_states_first_qubit_only(circ, theta, J):  # tangent terms of qubits >= 1 dropped
+    J = np.array(J, copy=True)
+    J[:, 1:, :] = 0.0
+    return _initial_states(circ, theta, J)
+
+
+def maxwell_terms_r3_sign(g, points, desc):           # r3 = dHy/dt + dE/dx
+    r1, r2, r3, eps, w1, w = _maxwell_terms(g, points, desc)
+    return r1, r2, g[:, 2, 0] + g[:, 0, 1], eps, w1, w
+
+
+def maxwell_terms_weights_swapped(g, points, desc):   # 1/N_vac and 1/N_diel exchanged
+    r1, r2, r3, eps, w1, w = _maxwell_terms(g, points, desc)
+    if desc.kind == O.LOSS_DIEL_SPLIT:
+        diel = np.asarray(points)[:, 1] >= desc.x_interface
+        n_d = int(diel.sum())
+        n_v = len(diel) - n_d
+        w1 = np.where(diel, 1.0 / max(n_v, 1), 1.0 / max(n_d, 1))
+    return r1, r2, r3, eps, w1, w
+
+
+def maxwell_seeds_term_dropped(g, points, desc):      # dE/dy's share of r2 left out
+    r1, r2, r3, eps, w1, w = _maxwell_terms(g, points, desc)
+    W = _maxwell_seeds(g, points, desc)
+    W[:, 0, 2] -= 2.0 * w * r2
+    return W
+
+
+def grad_reverse_sign(*a, **k):
+    return -np.asarray(_grad_reverse(*a, **k))
+
+
+MUTATIONS = [
+    ("rotation", rotation_sign),
+    ("rotation", rotation_full_angle),
+    ("rotation_derivative", rotation_derivative_no_half),
+    ("full_operator", full_operator_cnot_swapped),
+    ("full_operator", full_operator_cz_as_cnot),
+    ("z_diagonal", z_diagonal_reversed),
+    ("readout", readout_without_two),
+    ("scale_derivative", scale_derivative_pi_dropped),
+    ("_embed_vectors", embed_rx_conjugated),
+    ("initial_states", initial_states_first_qubit_only),
+    ("maxwell_terms", maxwell_terms_r3_sign),
+    ("maxwell_terms", maxwell_terms_weights_swapped),
+    ("maxwell_seeds", maxwell_seeds_term_dropped),
+    ("grad_reverse", grad_reverse_sign),
+]
+
+
+def _caught(monkeypatch, name, fn):
+    caught = []
+    with monkeypatch.context() as m:
+        m.setattr(O, name, fn)
+        for label, pin, args in FAST_PINS:
+            try:
+                pin(*args)
+            except Exception:
+                caught.append(label)
+    return caught
+
+
+@pytest.mark.parametrize("name,fn", MUTATIONS, ids=[f.__name__ for _, f in MUTATIONS])
+def test_planted_mistake_fails_a_pin(monkeypatch, name, fn):
+    caught = _caught(monkeypatch, name, fn)
+    assert caught, f"no pin notices {fn.__name__} in oracle.{name}"
+
+
+def test_unmutated_oracle_passes_the_fast_pins(monkeypatch):
+    assert _caught(monkeypatch, "rotation", _rotation) == []

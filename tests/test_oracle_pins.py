@@ -55,6 +55,20 @@ def test_rx_scaling_identities_golden():
         np.testing.assert_allclose(f[:, 0], gold[key], atol=1e-12)
 
 
+def test_rx_embedding_phase_closed_form():
+    """The RX embedding is exp(-i theta X/2)|0>, so a following RX(pi/2) turns it into
+    RX(theta + pi/2)|0> with <Z> = cos(theta + pi/2) = -sin(theta) (theta = pi t here); the
+    opposite phase, exp(+i theta X/2)|0>, would give +sin(theta) though <Z> alone cannot tell."""
+    t = np.linspace(-0.95, 0.95, 9)
+    pts = np.stack([t, np.zeros_like(t), np.zeros_like(t)], 1)
+    enc = W.Encoding(kind=W.ENC_CYCLE, gate=W.ENC_RX, scale=W.SCALE_PI, coord_of_qubit=[0])
+    circ = _circ(1, [(W.RX, 0, -1, 0)], 1, enc=enc, out=[0])
+    f, g = O.simulate(circ, [math.pi / 2], pts)
+    np.testing.assert_allclose(f[:, 0], -np.sin(math.pi * t), atol=1e-14)
+    np.testing.assert_allclose(g[:, 0, 0], -math.pi * np.cos(math.pi * t), atol=1e-13)
+    np.testing.assert_allclose(g[:, 0, 1:], 0.0, atol=1e-15)
+
+
 def test_scale_derivatives_match_finite_differences():
     a = np.linspace(-0.9, 0.9, 11)
     h = 1e-6
