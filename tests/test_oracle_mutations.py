@@ -48,6 +48,7 @@ _initial_states = O.initial_states
 _maxwell_terms = O.maxwell_terms
 _maxwell_seeds = O.maxwell_seeds
 _grad_reverse = O.grad_reverse
+_encoding_angles = O.encoding_angles
 
 
 def rotation_sign(kind, theta):                       # exp(+i theta P / 2)
@@ -126,6 +127,23 @@ def grad_reverse_sign(*a, **k):
     return -np.asarray(_grad_reverse(*a, **k))
 
 
+def grad_reverse_tangent_seeds_dropped(circ, params, points, seeds_f, seeds_g, *a, **k):
+    return _grad_reverse(circ, params, points, seeds_f, np.zeros_like(seeds_g), *a, **k)
+
+
+def maxwell_terms_eps_multiplied(g, points, desc):    # eps multiplies the curl instead of dividing
+    r1, r2, r3, eps, w1, w = _maxwell_terms(g, points, desc)
+    curl = g[:, 2, 1] - g[:, 1, 2]
+    return g[:, 0, 0] - curl * eps, r2, r3, eps, w1, w
+
+
+def encoding_angles_rff_jacobian_sign(circ, *a, **k):
+    theta, J = _encoding_angles(circ, *a, **k)
+    if circ.enc.kind == O.ENC_RFF:
+        J = -J
+    return theta, J
+
+
 MUTATIONS = [
     ("rotation", rotation_sign),
     ("rotation", rotation_full_angle),
@@ -141,6 +159,9 @@ MUTATIONS = [
     ("maxwell_terms", maxwell_terms_weights_swapped),
     ("maxwell_seeds", maxwell_seeds_term_dropped),
     ("grad_reverse", grad_reverse_sign),
+    ("grad_reverse", grad_reverse_tangent_seeds_dropped),
+    ("maxwell_terms", maxwell_terms_eps_multiplied),
+    ("encoding_angles", encoding_angles_rff_jacobian_sign),
 ]
 
 
