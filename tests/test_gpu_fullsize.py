@@ -60,3 +60,31 @@ def test_full_size_sampled_outputs_and_additive_gradient(ctx, k):
         # and the mean loss is the summed loss over P
         assert abs(float(t2n(r["loss"])[0]) - lf / P) <= TOL * abs(lf / P)
         assert rel(grad_mean, gf / P) < TOL
+
+
+def test_eight_times_the_full_size(ctx):
+    """The 12-qubit circuit on 2^21 + 37 points (eight times the full-size workload, fresh seeded
+    draw): sampled outputs and tangents against the oracle, and the summed loss and gradient
+    additive over a split of the points."""
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import Circuit
+    w = W.config(4)
+    P = (1 << 21) + 37
+    pts = W.uniform_points(np.random.default_rng(2106), P, np.float32)
+    c = Circuit(ctx, w.circuit)
+    full = c.maxwell(w.params, pts, w.loss, flags=L.QP_FLAG_LOSS_SUM)
+    out, tan = t2n(full["out"]), t2n(full["tan"])
+    idx = np.unique(np.r_[np.linspace(0, P - 1, 8).astype(int), [P - 2]])
+    f, g = O.simulate(w.circuit, w.params, pts[idx])
+    e_f, e_g = rel(out[idx], f), rel(tan[idx], g)
+    report(f"{w.name} P={P} sampled {len(idx)}", f=e_f, g=e_g)
+    assert e_f < TOL and e_g < TOL
+    lf, gf = float(t2n(full["loss"])[0]), t2n(full["grad"]).copy()
+    cut = (1 << 20) + 1
+    a = c.maxwell(w.params, pts[:cut], w.loss, flags=L.QP_FLAG_LOSS_SUM, outputs=False)
+    b = c.maxwell(w.params, pts[cut:], w.loss, flags=L.QP_FLAG_LOSS_SUM, outputs=False)
+    la, lb = float(t2n(a["loss"])[0]), float(t2n(b["loss"])[0])
+    e_l, e_gr = abs(lf - (la + lb)) / abs(lf), rel(gf, t2n(a["grad"]) + t2n(b["grad"]))
+    report(f"{w.name} P={P} additivity", loss=e_l, grad=e_gr)
+    assert np.isfinite(lf) and np.all(np.isfinite(gf))
+    assert e_l < TOL and e_gr < TOL
