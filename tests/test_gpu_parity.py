@@ -75,6 +75,26 @@ def test_forward_every_qubit_count(ctx, n):
     _check_forward(ctx, circ, params, pts, name=f"random n={n}")
 
 
+@pytest.mark.parametrize("outs", [[4], [8, 0, 3, 5, 1, 7, 2, 6]])
+def test_output_count_extremes(ctx, outs):
+    """The fewest (1) and the most (8) read-out qubits, in scrambled order: forward against the
+    oracle, and with 8 outputs the whole Maxwell step (the first three outputs are the fields, the
+    other five are read out only)."""
+    from types import SimpleNamespace
+    rng = np.random.default_rng(400 + len(outs))
+    n = 9
+    rings = [W.ring(n, W.CNOT, 1), W.ring(n, W.CZ, 2)]
+    circ = W.layered(n, 2, "rot", lambda l: rings[l], out_qubits=list(outs))
+    params = rng.uniform(0, 2 * math.pi, circ.n_params).astype(np.float32)
+    P = 2 * (256 // (1 << (n - 3))) + 3      # two whole tiles and a ragged one
+    pts = rng.uniform(-1, 1, (P, 3)).astype(np.float32)
+    _check_forward(ctx, circ, params, pts, name=f"m={len(outs)}")
+    if len(outs) >= 3:
+        w = SimpleNamespace(circuit=circ, params=params, points=pts,
+                            loss=W.MaxwellDesc(W.LOSS_DIEL_INTUITIVE, eps_r=4.0, x_interface=0.2))
+        _check_maxwell(ctx, w, name="m=8")
+
+
 @pytest.mark.parametrize("gate,scale", [(W.ENC_RX, W.SCALE_ACOS), (W.ENC_RX, W.SCALE_ASIN),
                                         (W.ENC_RY, W.SCALE_BIAS), (W.ENC_RY, W.SCALE_NONE),
                                         (W.ENC_RX, W.SCALE_PI)])
