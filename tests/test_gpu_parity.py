@@ -95,6 +95,27 @@ def test_output_count_extremes(ctx, outs):
         _check_maxwell(ctx, w, name="m=8")
 
 
+@pytest.mark.parametrize("case", ["rings5", "empty5", "rings8"])
+def test_parameter_free_circuits(ctx, case):
+    """Circuits with no trainable gate (K = 0: entangler rings only, or nothing after the
+    encoding): the plan has one round of identity slots; outputs, tangents and the Maxwell loss
+    against the oracle, and an empty gradient."""
+    n, gates, outs = {"rings5": (5, W.ring(5, W.CNOT, 1) + W.ring(5, W.CZ, 2), [0, 1, 2]),
+                      "empty5": (5, [], [0, 1, 2]),
+                      "rings8": (8, W.ring(8, W.CZ, 1) + W.ring(8, W.CNOT, 3), [0, 4, 7])}[case]
+    circ = W.Circuit(n=n, gates=gates, n_params=0, out_qubits=outs)
+    params = np.zeros(0, np.float32)
+    pts = np.random.default_rng(500 + n).uniform(-1, 1, (2 * (256 >> (n - 3)) + 3, 3)).astype(np.float32)
+    c = _check_forward(ctx, circ, params, pts, name=f"K=0 {case}")
+    loss = W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=0.1)
+    r = c.maxwell(params, pts, loss)
+    f, g, L, grad = O.maxwell_eval(circ, params, pts, loss)
+    e = dict(f=rel(t2n(r["out"]), f), g=rel(t2n(r["tan"]), g), loss=rel(t2n(r["loss"]), [L]))
+    report(f"maxwell K=0 {case} P={len(pts)}", **e)
+    assert all(v < TOL for v in e.values()), e
+    assert grad.size == 0 and t2n(r["grad"]).size == 0
+
+
 @pytest.mark.parametrize("gate,scale", [(W.ENC_RX, W.SCALE_ACOS), (W.ENC_RX, W.SCALE_ASIN),
                                         (W.ENC_RY, W.SCALE_BIAS), (W.ENC_RY, W.SCALE_NONE),
                                         (W.ENC_RX, W.SCALE_PI)])
