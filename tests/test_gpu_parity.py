@@ -179,6 +179,15 @@ def test_maxwell_loss_kinds(ctx, kind):
     _check_maxwell(ctx, w, name=f"loss kind {kind}")
 
 
+@pytest.mark.parametrize("x_if", [-2.0, 2.0])
+def test_split_loss_with_an_empty_region(ctx, x_if):
+    """Every point on one side of the interface: the empty region's mean contributes nothing (no
+    division by its zero count), the other region is averaged over all points."""
+    w = W.config(1, P=200)
+    w.loss = W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=x_if)
+    _check_maxwell(ctx, w, name=f"split, interface at x = {x_if}")
+
+
 @pytest.mark.parametrize("n,layers", [(3, 1), (4, 3), (8, 3), (11, 2), (12, 2)])
 def test_maxwell_both_exchange_shapes(ctx, n, layers):
     """Whole Maxwell step with the software-pipelined exchange (two plane pairs) and with the

@@ -439,6 +439,20 @@ def test_dielectric_split_weights():
         (nv + nd / 16) / 50)
 
 
+def test_split_loss_with_one_region_empty():
+    """With every point in vacuum the split loss is the vacuum loss; with every point in the
+    dielectric it is the intuitive form (eps_r everywhere, one mean over all points): the empty
+    region's mean contributes nothing."""
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(-1, 1, (40, 3))
+    g = rng.standard_normal((40, 3, 3))
+    vac = O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_VACUUM))
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=2.0)) == pytest.approx(vac)
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=-2.0)) == pytest.approx(
+        O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_INTUITIVE, eps_r=4.0, x_interface=-2.0)))
+    assert O.maxwell_loss(g, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT, eps_r=4.0, x_interface=-2.0)) != pytest.approx(vac)
+
+
 def test_seeds_are_the_gradient_of_the_loss_in_g():
     rng = np.random.default_rng(7)
     pts = rng.uniform(-1, 1, (9, 3))
