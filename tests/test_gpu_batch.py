@@ -43,6 +43,31 @@ def test_batch_matches_oracle_per_circuit(env):
             assert v < TOL, (w.name, k, v)
 
 
+def test_batch_with_an_empty_member(env):
+    """A circuit given no points sits between circuits that have points: it gets no work item,
+    its loss and gradient are the empty sums (zero), and its neighbours match the oracle."""
+    import torch
+    from copy import deepcopy
+    ctx, s = env
+    ws = [deepcopy(w) for w in W.batch_config(P_cap=40)[:4]]
+    ws[1].points = ws[1].points[:0]
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, W.MaxwellDesc())
+    s.synchronize()
+    assert float(t2n(bufs[1]["loss"])[0]) == 0.0
+    assert np.all(t2n(bufs[1]["grad"]) == 0.0)
+    for i in (0, 2, 3):
+        w = ws[i]
+        f, g, L, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
+        e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
+                 loss=rel(t2n(bufs[i]["loss"]), [L]), grad=rel(t2n(bufs[i]["grad"]), grad))
+        report(f"batch with empty member: {w.name}", **e)
+        for k, v in e.items():
+            assert v < TOL, (w.name, k, v)
+
+
 def test_batch_matches_single_circuit_path(env):
     import torch
     from paper_2506_23246_amd.api import Circuit
