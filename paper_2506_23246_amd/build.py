@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqpinn.so")
-ARCH = os.environ.get("QP_OFFLOAD_ARCH", "gfx950")
+ARCH = "gfx950"   # the kernels use gfx950 cross-lane swaps and the CDNA4 LDS layout
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=on: multiply-adds are fused only within one source expression, as written, so the
