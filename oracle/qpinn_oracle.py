@@ -387,19 +387,44 @@ def maxwell_eval(circ, params, points, desc, angles=None, jac=None):
     return f, g, loss, grad
 
 
+def _shifted(circ, params, k, delta, points, angles, jac):
+    p = params.copy()
+    p[k] += delta
+    return simulate(circ, p, points, angles, jac)
+
+
 def grad_param_shift(circ, params, points, seeds_f, seeds_g, angles=None, jac=None):
-    """Same quantity as grad_reverse, by the parameter-shift rule applied to f and g:
-    d f / d theta_k = [f(theta_k + pi/2) - f(theta_k - pi/2)] / 2 (exact for exp(-i theta P/2)),
-    then contracted with the (fixed) seeds.  Valid when each parameter drives one gate."""
+    """Same quantity as grad_reverse, by parameter-shift rules applied to f and g, then
+    contracted with the (fixed) seeds.  Valid when each parameter drives gates of one kind.
+
+    Rotations exp(-i theta P/2) (generator eigenvalues +-1/2, one frequency):
+        d f / d theta = [f(theta + pi/2) - f(theta - pi/2)] / 2.
+    CRZ (generator |1><1| (x) Z/2, eigenvalues 0, 0, +-1/2: frequencies 1/2 and 1), the
+    four-term rule of the general parameter-shift literature:
+        d f / d theta = c1 [f(theta + pi/2) - f(theta - pi/2)] - c2 [f(theta + 3pi/2) - f(theta - 3pi/2)],
+        c1 = (sqrt2 + 1) / (4 sqrt2),  c2 = (sqrt2 - 1) / (4 sqrt2).
+    (The two-term rule is wrong for CRZ: it does not cancel the frequency-1/2 term.)"""
     params = np.asarray(params, np.float64)
     grad = np.zeros(circ.n_params)
+    kinds = {}
+    for kind, q0, q1, pi in circ.gates:
+        if pi >= 0:
+            kinds.setdefault(pi, set()).add(kind == CRZ)
+    c1 = (math.sqrt(2.0) + 1.0) / (4.0 * math.sqrt(2.0))
+    c2 = (math.sqrt(2.0) - 1.0) / (4.0 * math.sqrt(2.0))
     for k in range(circ.n_params):
-        pp, pm = params.copy(), params.copy()
-        pp[k] += math.pi / 2
-        pm[k] -= math.pi / 2
-        fp, gp = simulate(circ, pp, points, angles, jac)
-        fm, gm = simulate(circ, pm, points, angles, jac)
-        df, dg = (fp - fm) / 2.0, (gp - gm) / 2.0
+        ks = kinds.get(k, set())
+        if len(ks) > 1:
+            raise ValueError(f"parameter {k} drives both rotations and CRZ gates")
+        fp, gp = _shifted(circ, params, k, math.pi / 2, points, angles, jac)
+        fm, gm = _shifted(circ, params, k, -math.pi / 2, points, angles, jac)
+        if ks == {True}:
+            fp3, gp3 = _shifted(circ, params, k, 3 * math.pi / 2, points, angles, jac)
+            fm3, gm3 = _shifted(circ, params, k, -3 * math.pi / 2, points, angles, jac)
+            df = c1 * (fp - fm) - c2 * (fp3 - fm3)
+            dg = c1 * (gp - gm) - c2 * (gp3 - gm3)
+        else:
+            df, dg = (fp - fm) / 2.0, (gp - gm) / 2.0
         grad[k] = np.sum(dg * seeds_g)
         if seeds_f is not None:
             grad[k] += np.sum(df * seeds_f)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import qpinn_oracle as O
+import workloads as W
 import test_oracle_pins as pins
 
 # the fast pins (each well under a second); the slow parameter-shift and 12-qubit cases are
@@ -36,6 +37,11 @@ FAST_PINS = [
     ("plane_wave", pins.test_plane_wave_is_an_exact_zero_of_every_residual, ()),
     ("dielectric_weights", pins.test_dielectric_split_weights, ()),
     ("seeds_gradient", pins.test_seeds_are_the_gradient_of_the_loss_in_g, ()),
+    ("bias_none_ry", pins.test_bias_and_none_scalings_closed_form_golden, (W.ENC_RY,)),
+    ("bias_none_rx", pins.test_bias_and_none_scalings_closed_form_golden, (W.ENC_RX,)),
+    ("rff_one_frequency", pins.test_rff_angles_one_frequency_closed_form, ()),
+    ("crz_fd", pins.test_crz_gradient_matches_fd_of_loss, ()),
+    ("crz_four_term_shift", pins.test_crz_gradient_matches_four_term_shift_rule, ()),
 ]
 
 _rotation = O.rotation
@@ -49,6 +55,7 @@ _maxwell_terms = O.maxwell_terms
 _maxwell_seeds = O.maxwell_seeds
 _grad_reverse = O.grad_reverse
 _encoding_angles = O.encoding_angles
+_scale_value = O.scale_value
 
 
 def rotation_sign(kind, theta):                       # exp(+i theta P / 2)
@@ -144,6 +151,64 @@ def encoding_angles_rff_jacobian_sign(circ, *a, **k):
     return theta, J
 
 
+def full_operator_crz_derivative_zero_branch(n, kind, q0, q1, theta, derivative=False):
+    # d CRZ / d theta taken as P0 (x) I + P1 (x) dRZ (the constant branch not dropped)
+    if kind == O.CRZ and derivative:
+        return _full_operator(n, kind, q0, q1, theta, True) + _zero_branch(n, q0)
+    return _full_operator(n, kind, q0, q1, theta, derivative)
+
+
+def _zero_branch(n, q0):
+    return O._kron_list([O.P0 if q == q0 else O.I2 for q in range(n)], n > O.DENSE_MAX_N)
+
+
+def full_operator_crz_rx(n, kind, q0, q1, theta, derivative=False):
+    # the controlled rotation taken about X instead of Z (forward and derivative alike)
+    if kind != O.CRZ:
+        return _full_operator(n, kind, q0, q1, theta, derivative)
+    T = O.rotation_derivative(O.RX, theta) if derivative else O.rotation(O.RX, theta)
+    one = O._kron_list([O.P1 if q == q0 else (T if q == q1 else O.I2) for q in range(n)], n > O.DENSE_MAX_N)
+    return one if derivative else _zero_branch(n, q0) + one
+
+
+def scale_value_bias_offset(kind, a):                 # (a - 1) pi/2: same derivative
+    if kind == O.SCALE_BIAS:
+        return (a - 1.0) * math.pi / 2.0
+    return _scale_value(kind, a)
+
+
+def scale_value_none_offset(kind, a):                 # a + pi/2: same derivative
+    if kind == O.SCALE_NONE:
+        return a + math.pi / 2.0
+    return _scale_value(kind, a)
+
+
+def _rff(circ, points, swap=False, two_pi=False):
+    B = np.asarray(circ.enc.rff_B, np.float64)
+    Wm = np.asarray(circ.enc.rff_W, np.float64)
+    s = 2.0 * math.pi if two_pi else 1.0
+    proj = s * (np.asarray(points, np.float64) @ B.T)
+    a, b = np.cos(proj), np.sin(proj)
+    da, db = -np.sin(proj), np.cos(proj)
+    if swap:
+        a, b, da, db = b, a, db, da
+    phi = np.concatenate([a, b], axis=1)
+    dphi = np.concatenate([da[:, :, None] * s * B[None], db[:, :, None] * s * B[None]], axis=1)
+    return phi @ Wm.T, np.einsum("qf,pfc->pqc", Wm, dphi)
+
+
+def encoding_angles_rff_cos_sin_swapped(circ, points, angles=None, jac=None):
+    if circ.enc.kind == O.ENC_RFF:                    # [sin; cos] with a consistent Jacobian
+        return _rff(circ, points, swap=True)
+    return _encoding_angles(circ, points, angles, jac)
+
+
+def encoding_angles_rff_two_pi(circ, points, angles=None, jac=None):
+    if circ.enc.kind == O.ENC_RFF:                    # cos(2 pi B p) with a consistent Jacobian
+        return _rff(circ, points, two_pi=True)
+    return _encoding_angles(circ, points, angles, jac)
+
+
 MUTATIONS = [
     ("rotation", rotation_sign),
     ("rotation", rotation_full_angle),
@@ -162,6 +227,12 @@ MUTATIONS = [
     ("grad_reverse", grad_reverse_tangent_seeds_dropped),
     ("maxwell_terms", maxwell_terms_eps_multiplied),
     ("encoding_angles", encoding_angles_rff_jacobian_sign),
+    ("full_operator", full_operator_crz_derivative_zero_branch),
+    ("full_operator", full_operator_crz_rx),
+    ("scale_value", scale_value_bias_offset),
+    ("scale_value", scale_value_none_offset),
+    ("encoding_angles", encoding_angles_rff_cos_sin_swapped),
+    ("encoding_angles", encoding_angles_rff_two_pi),
 ]
 
 

@@ -476,3 +476,80 @@ def test_table1_parameter_counts_golden():
     for name, count in gold["quantum_params"].items():
         c = W.paper_context_circuit(name, gold["n_qubits"], gold["n_layers"])
         assert c.n_params == count, name
+
+
+# ------------------------------------------------- bias / none scalings, RFF angles, CRZ --------
+
+@pytest.mark.parametrize("gate", [W.ENC_RY, W.ENC_RX])
+def test_bias_and_none_scalings_closed_form_golden(gate):
+    """Eq. scale's bias scaling (a + 1) pi/2 and the unscaled embedding: <Z> and d<Z>/da against
+    closed forms written as other trig functions (-sin(pi a/2) and cos a), not the oracle's
+    formula; both embedding gates give <Z> = cos(theta)."""
+    gold = json.load(open(os.path.join(GOLDEN, "scaling_identities.json")))
+    a = np.array(gold["a"])
+    pts = np.stack([a, np.zeros_like(a), np.zeros_like(a)], 1)
+    for scale, kz, kd in ((W.SCALE_BIAS, "bias_expect_z", "bias_dz_da"),
+                          (W.SCALE_NONE, "none_expect_z", "none_dz_da")):
+        enc = W.Encoding(kind=W.ENC_CYCLE, gate=gate, scale=scale, coord_of_qubit=[0])
+        f, g = O.simulate(_circ(1, [], 0, enc=enc, out=[0]), [], pts)
+        np.testing.assert_allclose(f[:, 0], gold[kz], atol=1e-14)
+        np.testing.assert_allclose(g[:, 0, 0], gold[kd], atol=1e-13)
+        np.testing.assert_allclose(g[:, 0, 1:], 0.0, atol=1e-15)
+
+
+def test_rff_angles_one_frequency_closed_form():
+    """Random Fourier features with one frequency b and a map W that picks one slot per qubit:
+    theta_0 = 0.5 cos(b.p), theta_1 = 2 sin(b.p) (no 2 pi, cosine half first).  With the RY
+    embedding <Z_q> = cos(theta_q) and d<Z_q>/dc = -sin(theta_q) d theta_q/dc, where
+    d cos(b.p)/dc = -sin(b.p) b_c and d sin(b.p)/dc = cos(b.p) b_c."""
+    b = np.array([0.7, -1.3, 0.4])
+    Wm = np.array([[0.5, 0.0], [0.0, 2.0]])
+    enc = W.Encoding(kind=W.ENC_RFF, gate=W.ENC_RY, scale=W.SCALE_NONE, rff_B=b[None, :], rff_W=Wm)
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(-1, 1, (9, 3))
+    f, g = O.simulate(_circ(2, [], 0, enc=enc, out=[0, 1]), [], pts)
+    bp = pts @ b
+    th0, th1 = 0.5 * np.cos(bp), 2.0 * np.sin(bp)
+    np.testing.assert_allclose(f[:, 0], np.cos(th0), atol=1e-14)
+    np.testing.assert_allclose(f[:, 1], np.cos(th1), atol=1e-14)
+    for c in range(3):
+        np.testing.assert_allclose(g[:, 0, c], -np.sin(th0) * (-0.5 * np.sin(bp) * b[c]), atol=1e-13)
+        np.testing.assert_allclose(g[:, 1, c], -np.sin(th1) * (2.0 * np.cos(bp) * b[c]), atol=1e-13)
+
+
+def _cross_mesh_small():
+    """3-qubit, 2-layer Cross-Mesh circuit (RX per qubit, CRZ on every ordered pair; eq.
+    crz_cross_mesh) with random parameters and points, vacuum Maxwell loss."""
+    circ = W.cross_mesh(3, 2, "xz", W.CRZ)
+    rng = np.random.default_rng(21)
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    pts = rng.uniform(-1, 1, (4, 3))
+    return circ, params, pts, W.MaxwellDesc(W.LOSS_VACUUM)
+
+
+def test_crz_gradient_matches_fd_of_loss():
+    """The CRZ derivative branch and the reverse sweep through CRZ against central finite
+    differences of the loss (which use only the forward operators)."""
+    circ, params, pts, loss = _cross_mesh_small()
+    _, _, _, grad = O.maxwell_eval(circ, params, pts, loss)
+    crz = sorted({g[3] for g in circ.gates if g[0] == W.CRZ})
+    fd = O.grad_fd_loss(circ, params, pts, loss, h=1e-5, idx=crz[:6] + [0, 4])
+    for k, v in fd.items():
+        assert abs(v - grad[k]) <= 1e-8 * max(1.0, abs(grad[k])), (k, v, grad[k])
+    assert np.abs(grad[crz]).max() > 1e-3
+
+
+def test_crz_gradient_matches_four_term_shift_rule():
+    """Reverse mode through CRZ against the four-term shift rule (generator eigenvalues 0,
+    +-1/2), which is exact; the two-term rule is checked to be wrong for CRZ here."""
+    circ, params, pts, loss = _cross_mesh_small()
+    f, g = O.simulate(circ, params, pts)
+    seeds = O.maxwell_seeds(g, pts, loss)
+    rev = O.grad_reverse(circ, params, pts, None, seeds)
+    sh = O.grad_param_shift(circ, params, pts, None, seeds)
+    np.testing.assert_allclose(rev, sh, atol=1e-12 * max(1.0, np.abs(sh).max()))
+    k = next(g[3] for g in circ.gates if g[0] == W.CRZ)
+    fp, gp = O._shifted(circ, np.asarray(params, np.float64), k, math.pi / 2, pts, None, None)
+    fm, gm = O._shifted(circ, np.asarray(params, np.float64), k, -math.pi / 2, pts, None, None)
+    two_term = float(np.sum((gp - gm) / 2.0 * seeds))
+    assert abs(two_term - rev[k]) > 1e-6 * max(1.0, abs(rev[k]))
