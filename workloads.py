@@ -237,6 +237,20 @@ def config(k: int, P: int | None = None) -> Workload | list:
     return Workload(CONFIG_NAMES[k], circ, prm, pts, loss)
 
 
+MULTITILE_P = 2 * 65536 + 4096 + 37
+
+
+def multitile_config(P: int = MULTITILE_P) -> Workload:
+    """A 4-qubit, 2-layer RX/RY/RZ + CNOT-ring circuit (the plain FP64 workload's circuit) in
+    float32 with the vacuum Maxwell loss, at a point count that gives every persistent workgroup
+    of the default launch two or more point tiles and leaves a ragged last tile."""
+    r_pts, r_par = _rngs(10, 2)
+    circ = layered(4, 2, "xyz", lambda l: ring(4, CNOT, 1), name="c1_circuit_f32_multitile",
+                   out_qubits=[0, 1, 2, 3])
+    return Workload(circ.name, circ, uniform_params(r_par, circ.n_params),
+                    uniform_points(r_pts, P), MaxwellDesc(LOSS_VACUUM))
+
+
 def batch_config(P_cap: int | None = None, count: int = 32) -> list:
     """The uneven batch: per circuit n ~ U{4..10}, L ~ U{2..12}, P log-uniform in [1024, 65536],
     one ring type per layer ~ U{CNOT, CZ} (stride 1), RX/RY/RZ blocks, cycled RY encoding,
