@@ -434,23 +434,31 @@ extern "C" qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* param
                    d_params, ws, flags, 0, 0);
 }
 
-extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
-                                      const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld,
-                                      float* out, float* tan, double* loss, float* d_params, void* ws,
-                                      size_t ws_bytes, uint32_t flags) {
-  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_maxwell_fused", flags);
+qp_status qp::maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                            const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
+                            float* tan, double* loss, float* d_params, void* ws, size_t ws_bytes, uint32_t flags,
+                            const char* who) {
+  qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, who, flags);
   if (s != QP_OK) return s;
-  if (!ld) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss descriptor is null");
-  if (ld->kind < QP_LOSS_VACUUM || ld->kind > QP_LOSS_DIEL_INTUITIVE) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: unknown loss kind");
-  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "qp_maxwell_fused: the Maxwell loss needs 3 outputs (E_z, H_x, H_y)");
-  if (ld->kind != QP_LOSS_VACUUM && P > 0 && !points) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: dielectric loss needs points");
-  if (!loss || (c->hp.K > 0 && !d_params)) return fail(ctx, QP_EINVAL, "qp_maxwell_fused: loss/d_params null");
+  if (!ld) return fail(ctx, QP_EINVAL, "%s: loss descriptor is null", who);
+  if (ld->kind < QP_LOSS_VACUUM || ld->kind > QP_LOSS_DIEL_INTUITIVE) return fail(ctx, QP_EINVAL, "%s: unknown loss kind", who);
+  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "%s: the Maxwell loss needs 3 outputs (E_z, H_x, H_y)", who);
+  if (ld->kind != QP_LOSS_VACUUM && P > 0 && !points) return fail(ctx, QP_EINVAL, "%s: dielectric loss needs points", who);
+  if (!loss || (c->hp.K > 0 && !d_params)) return fail(ctx, QP_EINVAL, "%s: loss/d_params null", who);
   if (flags & QP_FLAG_DENSE_MFMA)
     return run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                      ws, flags);
   if ((flags & QP_FLAG_TUNE) && P > 0) tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws);
   return run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                    ws, flags, 0, 0);
+}
+
+extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                                      const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld,
+                                      float* out, float* tan, double* loss, float* d_params, void* ws,
+                                      size_t ws_bytes, uint32_t flags) {
+  return maxwell_entry(ctx, c, params, points, angles, jac, P, ld, out, tan, loss, d_params, ws, ws_bytes, flags,
+                       "qp_maxwell_fused");
 }
 
 // ---------------------------------------------------------------- plain ---------------------

@@ -980,11 +980,16 @@ hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) 
   // lds counts the static exchange planes and the dynamic part; only the latter is passed.
   const size_t planes = (size_t)EXS * T * 8 * sizeof(float2);
   const size_t dyn = lds > planes ? lds - planes : 0;
-  static size_t attr_bytes = 0;
-  if (dyn > 0 && dyn > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  // the attribute is set once per device (and raised when a larger size comes)
+  static size_t attr_bytes[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (dyn > 0 && dyn > attr_bytes[dev]) {
+    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
-    attr_bytes = dyn;
+    attr_bytes[dev] = dyn;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(T), dyn, st, a);
   return hipGetLastError();

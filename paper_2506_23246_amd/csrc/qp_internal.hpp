@@ -25,6 +25,7 @@ QP_HD inline constexpr uint32_t lds_swizzle(uint32_t idx) {
 }
 
 constexpr int kMaxQubits = 12;     // fused register/LDS kernels
+constexpr int kMaxDevices = 64;    // per-device host-side state (launch attributes, scratch addresses)
 constexpr int kMaxQubitsPlain = 14;
 constexpr int kMaxOut = 8;
 constexpr int kMaxTerms = 32;      // sign terms of one entangler stage
