@@ -185,6 +185,15 @@ def _embed_vectors(gate: int, theta):
     return v, dv
 
 
+def _embed_second_derivative(gate: int, theta):
+    """d^2/dtheta^2 of the embedded state: RY (cos, sin)(theta/2) -> -(1/4)(cos, sin);
+    RX (cos, -i sin)(theta/2) -> -(1/4)(cos, -i sin)."""
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    if gate == ENC_RY:
+        return np.stack([-0.25 * c, -0.25 * s], -1).astype(np.complex128)
+    return np.stack([-0.25 * c + 0j, 0.25j * s], -1)
+
+
 def initial_states(circ, theta, J):
     """psi0 = kron_q G(theta_q)|0> and the tangents dpsi0_c = sum_q J_qc kron(.., dG_q|0>, ..).
 
@@ -331,12 +340,24 @@ def maxwell_seeds(g, points, desc):
 
 # --------------------------------------------------------------- gradients --------------------
 
-def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, chunk=None):
+def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, chunk=None,
+                 inputs=False):
     """d/dparams of  sum_p [ sum_i seeds_f[p,i] f_i + sum_ic seeds_g[p,i,c] g_ic ]  by plain
     stored-state reverse mode: every intermediate state is kept, the adjoints are pulled back
     through U^H, and each parametrised gate contributes
         2 Re [ <dU psi_in, lam_out> + sum_c <dU dpsi_c,in, mu_c,out> ].
-    For the Maxwell loss pass seeds_f = 0 and seeds_g = maxwell_seeds(g)."""
+    For the Maxwell loss pass seeds_f = 0 and seeds_g = maxwell_seeds(g).
+
+    inputs=True (angle-given encoding only) also returns the derivatives of the same quantity
+    with respect to the per-point angles [P,n] and Jacobian [P,n,3] (the inputs a classical
+    layer in front of the circuit produces; section "QPINN architecture and ansatz designs",
+    angle embedding): with lam_0, mu_c,0 the adjoints pulled back to the embedded product state,
+        d/d theta_q = 2 Re [ <lam_0, d psi_0/d theta_q> + sum_c <mu_c,0, d dpsi_c,0/d theta_q> ],
+        d/d J_qc    = 2 Re <mu_c,0, d dpsi_c,0/d J_qc>,
+    where psi_0 = kron_q v(theta_q), dpsi_c,0 = sum_q J_qc kron(.., v'(theta_q), ..), so
+    d dpsi_c,0/d J_qc = kron(.., v'(theta_q), ..) and d dpsi_c,0/d theta_q =
+    sum_{q' != q} J_q'c kron(.., v'(theta_q'), .., v'(theta_q), ..) + J_qc kron(.., v''(theta_q), ..),
+    all built by explicit Kronecker products per point."""
     params = np.asarray(params, np.float64)
     theta, J = encoding_angles(circ, points, angles, jac)
     ops = operators(circ, params)
@@ -346,6 +367,11 @@ def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, 
         chunk = max(1, int(1e9 // (max(len(ops), 1) * 4 * 2 ** n * 16)))
     zd = [z_diagonal(n, i)[:, None] for i in circ.out_qubits]
     grad = np.zeros(circ.n_params)
+    if inputs:
+        if circ.enc.kind != ENC_ANGLES:
+            raise ValueError("input gradients need the angle-given encoding")
+        d_theta = np.zeros((P, n))
+        d_J = np.zeros((P, n, 3))
     for s in range(0, P, chunk):
         e = min(P, s + chunk)
         psi, dpsi = initial_states(circ, theta[s:e], J[s:e])
@@ -375,7 +401,33 @@ def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, 
             UH = ops[idx].conj().T
             lam = UH @ lam
             mu = np.stack([UH @ mu[c] for c in range(3)])
+        if inputs:
+            _input_grads(circ, theta[s:e], J[s:e], lam, mu, d_theta[s:e], d_J[s:e])
+    if inputs:
+        return grad, d_theta, d_J
     return grad
+
+
+def _input_grads(circ, theta, J, lam, mu, d_theta, d_J):
+    """Fills d_theta [P,n] and d_J [P,n,3] from the adjoints lam [2^n,P], mu [3,2^n,P] at the
+    embedded product state (see grad_reverse)."""
+    P, n = theta.shape
+    v, dv = _embed_vectors(circ.enc.gate, theta)
+    d2v = _embed_second_derivative(circ.enc.gate, theta)
+    for p in range(P):
+        for q in range(n):
+            # d psi_0 / d theta_q and d dpsi_c,0 / d J_qc: v'(theta_q) in slot q
+            t_q = _kron_list([dv[p, qq] if qq == q else v[p, qq] for qq in range(n)], False)
+            acc = np.vdot(lam[:, p], t_q)
+            for c in range(3):
+                d_J[p, q, c] = 2.0 * np.real(np.vdot(mu[c, :, p], t_q))
+                dd = J[p, q, c] * _kron_list([d2v[p, qq] if qq == q else v[p, qq] for qq in range(n)], False)
+                for q2 in range(n):
+                    if q2 != q and J[p, q2, c] != 0.0:
+                        dd = dd + J[p, q2, c] * _kron_list(
+                            [dv[p, qq] if qq in (q, q2) else v[p, qq] for qq in range(n)], False)
+                acc += np.vdot(mu[c, :, p], dd)
+            d_theta[p, q] = 2.0 * np.real(acc)
 
 
 def maxwell_eval(circ, params, points, desc, angles=None, jac=None):
@@ -429,6 +481,49 @@ def grad_param_shift(circ, params, points, seeds_f, seeds_g, angles=None, jac=No
         if seeds_f is not None:
             grad[k] += np.sum(df * seeds_f)
     return grad
+
+
+def input_grads_param_shift(circ, params, seeds_f, seeds_g, angles, jac):
+    """The input derivatives of grad_reverse(..., inputs=True) by the embedding's shift rule,
+    forward simulations only.  Each angle theta_q enters one rotation exp(-i theta P/2), so
+      d f_i / d theta_q = [f_i(theta_q + pi/2) - f_i(theta_q - pi/2)] / 2,
+      d^2 f_i / d theta_q d theta_q' = [f(++) - f(+-) - f(-+) + f(--)] / 4          (q != q'),
+      d^2 f_i / d theta_q^2 = [f(theta_q + pi) - f(theta_q)] / 2,
+    and the tangents are g_ic = sum_q J_qc d f_i / d theta_q, so
+      d/d J_qc     = sum_i seeds_g[i,c] d f_i / d theta_q,
+      d/d theta_q  = sum_i seeds_f[i] d f_i / d theta_q
+                     + sum_ic seeds_g[i,c] sum_q' J_q'c d^2 f_i / d theta_q d theta_q'."""
+    if circ.enc.kind != ENC_ANGLES:
+        raise ValueError("input gradients need the angle-given encoding")
+    th = np.asarray(angles, np.float64)
+    J = np.asarray(jac, np.float64)
+    P, n = th.shape
+    zeros = np.zeros((P, n, 3))
+
+    def f_at(shifts):
+        t = th.copy()
+        for q, d in shifts:
+            t[:, q] += d
+        return simulate(circ, params, None, t, zeros)[0]      # [P, m]
+
+    h = math.pi / 2
+    f0 = f_at([])
+    df = np.stack([(f_at([(q, h)]) - f_at([(q, -h)])) / 2.0 for q in range(n)], 1)    # [P,n,m]
+    d2f = np.zeros((P, n, n, f0.shape[1]))
+    for q in range(n):
+        d2f[:, q, q] = (f_at([(q, math.pi)]) - f0) / 2.0
+        for q2 in range(q + 1, n):
+            v = (f_at([(q, h), (q2, h)]) - f_at([(q, h), (q2, -h)])
+                 - f_at([(q, -h), (q2, h)]) + f_at([(q, -h), (q2, -h)])) / 4.0
+            d2f[:, q, q2] = v
+            d2f[:, q2, q] = v
+    Wg = np.asarray(seeds_g, np.float64)                       # [P,m,3]
+    d_J = np.einsum("pqi,pic->pqc", df, Wg)
+    dg = np.einsum("pqri,prc->pqic", d2f, J)                   # d g_ic / d theta_q
+    d_theta = np.einsum("pqic,pic->pq", dg, Wg)
+    if seeds_f is not None:
+        d_theta += np.einsum("pqi,pi->pq", df, np.asarray(seeds_f, np.float64))
+    return d_theta, d_J
 
 
 def grad_fd_loss(circ, params, points, desc, h=1e-6, idx=None, angles=None, jac=None):

@@ -42,6 +42,8 @@ FAST_PINS = [
     ("rff_one_frequency", pins.test_rff_angles_one_frequency_closed_form, ()),
     ("crz_fd", pins.test_crz_gradient_matches_fd_of_loss, ()),
     ("crz_four_term_shift", pins.test_crz_gradient_matches_four_term_shift_rule, ()),
+    ("input_grads_fd_ry", pins.test_input_gradients_match_fd, (W.ENC_RY,)),
+    ("input_grads_shift_rx", pins.test_input_gradients_match_embedding_shift_rule, (W.ENC_RX,)),
 ]
 
 _rotation = O.rotation
@@ -56,6 +58,7 @@ _maxwell_seeds = O.maxwell_seeds
 _grad_reverse = O.grad_reverse
 _encoding_angles = O.encoding_angles
 _scale_value = O.scale_value
+_embed_second_derivative = O._embed_second_derivative
 
 
 def rotation_sign(kind, theta):                       # exp(+i theta P / 2)
@@ -209,6 +212,37 @@ def encoding_angles_rff_two_pi(circ, points, angles=None, jac=None):
     return _encoding_angles(circ, points, angles, jac)
 
 
+def embed_second_derivative_sign(gate, theta):      # +(1/4) v instead of -(1/4) v
+    return -_embed_second_derivative(gate, theta)
+
+
+def _input_grads_slipped(circ, theta, J, lam, mu, d_theta, d_J, cross=True, j_factor=2.0):
+    P, n = theta.shape
+    v, dv = O._embed_vectors(circ.enc.gate, theta)
+    d2v = O._embed_second_derivative(circ.enc.gate, theta)
+    for p in range(P):
+        for q in range(n):
+            t_q = O._kron_list([dv[p, qq] if qq == q else v[p, qq] for qq in range(n)], False)
+            acc = np.vdot(lam[:, p], t_q)
+            for c in range(3):
+                d_J[p, q, c] = j_factor * np.real(np.vdot(mu[c, :, p], t_q))
+                dd = J[p, q, c] * O._kron_list([d2v[p, qq] if qq == q else v[p, qq] for qq in range(n)], False)
+                for q2 in range(n):
+                    if cross and q2 != q:
+                        dd = dd + J[p, q2, c] * O._kron_list(
+                            [dv[p, qq] if qq in (q, q2) else v[p, qq] for qq in range(n)], False)
+                acc += np.vdot(mu[c, :, p], dd)
+            d_theta[p, q] = 2.0 * np.real(acc)
+
+
+def input_grads_cross_terms_dropped(*a):            # d dpsi_c / d theta_q: only the q' = q term
+    _input_grads_slipped(*a, cross=False)
+
+
+def input_grads_jac_half(*a):                       # d/dJ = Re <mu, t_q> (factor 2 dropped)
+    _input_grads_slipped(*a, j_factor=1.0)
+
+
 MUTATIONS = [
     ("rotation", rotation_sign),
     ("rotation", rotation_full_angle),
@@ -233,6 +267,9 @@ MUTATIONS = [
     ("scale_value", scale_value_none_offset),
     ("encoding_angles", encoding_angles_rff_cos_sin_swapped),
     ("encoding_angles", encoding_angles_rff_two_pi),
+    ("_embed_second_derivative", embed_second_derivative_sign),
+    ("_input_grads", input_grads_cross_terms_dropped),
+    ("_input_grads", input_grads_jac_half),
 ]
 
 

@@ -553,3 +553,79 @@ def test_crz_gradient_matches_four_term_shift_rule():
     fm, gm = O._shifted(circ, np.asarray(params, np.float64), k, -math.pi / 2, pts, None, None)
     two_term = float(np.sum((gp - gm) / 2.0 * seeds))
     assert abs(two_term - rev[k]) > 1e-6 * max(1.0, abs(rev[k]))
+
+
+def _angles_case(gate, seed=3, P=3, n=3, L=2):
+    """A small angle-given circuit (RX or RY embedding, Rot + CNOT ring), random angles and a
+    dense random Jacobian, and random VJP seeds."""
+    rng = np.random.default_rng(seed)
+    enc = W.Encoding(kind=W.ENC_ANGLES, gate=gate)
+    circ = W.basic_entangling(n, L, "rot", enc=enc)
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    th = rng.uniform(-2.0, 2.0, (P, n))
+    J = rng.standard_normal((P, n, 3))
+    m = len(circ.out_qubits)
+    return circ, params, th, J, rng.standard_normal((P, m)), rng.standard_normal((P, m, 3))
+
+
+def _vjp_objective(circ, params, th, J, sf, sg):
+    f, g = O.simulate(circ, params, None, th, J)
+    return float(np.sum(sf * f) + np.sum(sg * g))
+
+
+@pytest.mark.parametrize("gate", [W.ENC_RY, W.ENC_RX])
+def test_input_gradients_match_fd(gate):
+    """d/d(angles) and d/d(Jacobian) of reverse mode against central finite differences of the
+    objective sum(seeds_f f) + sum(seeds_g g), which uses only the forward simulation."""
+    circ, params, th, J, sf, sg = _angles_case(gate)
+    _, d_th, d_J = O.grad_reverse(circ, params, None, sf, sg, th, J, inputs=True)
+    h = 1e-6
+    for p in range(th.shape[0]):
+        for q in range(th.shape[1]):
+            tp, tm = th.copy(), th.copy()
+            tp[p, q] += h
+            tm[p, q] -= h
+            fd = (_vjp_objective(circ, params, tp, J, sf, sg) - _vjp_objective(circ, params, tm, J, sf, sg)) / (2 * h)
+            assert abs(fd - d_th[p, q]) < 1e-8, (p, q, fd, d_th[p, q])
+            for c in range(3):
+                jp, jm = J.copy(), J.copy()
+                jp[p, q, c] += h
+                jm[p, q, c] -= h
+                fd = (_vjp_objective(circ, params, th, jp, sf, sg) - _vjp_objective(circ, params, th, jm, sf, sg)) / (2 * h)
+                assert abs(fd - d_J[p, q, c]) < 1e-8, (p, q, c, fd, d_J[p, q, c])
+
+
+@pytest.mark.parametrize("gate", [W.ENC_RY, W.ENC_RX])
+def test_input_gradients_match_embedding_shift_rule(gate):
+    """Reverse mode against the embedding's exact shift rules (first and second derivatives of
+    the readouts from shifted forward simulations)."""
+    circ, params, th, J, sf, sg = _angles_case(gate, seed=5, P=4, n=4)
+    _, d_th, d_J = O.grad_reverse(circ, params, None, sf, sg, th, J, inputs=True)
+    s_th, s_J = O.input_grads_param_shift(circ, params, sf, sg, th, J)
+    np.testing.assert_allclose(d_th, s_th, atol=1e-12)
+    np.testing.assert_allclose(d_J, s_J, atol=1e-12)
+    assert np.abs(d_th).max() > 1e-2 and np.abs(d_J).max() > 1e-2
+
+
+def test_input_gradients_of_the_maxwell_loss_match_fd():
+    """The Maxwell loss (quadratic in the tangents) through its seeds: reverse-mode input
+    gradients against central finite differences of the loss itself."""
+    circ, params, th, J, _, _ = _angles_case(W.ENC_RX, seed=9, P=4)
+    pts = np.random.default_rng(2).uniform(-1, 1, (4, 3))
+    desc = W.MaxwellDesc(W.LOSS_DIEL_SPLIT, 4.0, 0.0)
+
+    def loss(t, j):
+        return O.maxwell_loss(O.simulate(circ, params, pts, t, j)[1], pts, desc)
+    _, g = O.simulate(circ, params, pts, th, J)
+    _, d_th, d_J = O.grad_reverse(circ, params, pts, None, O.maxwell_seeds(g, pts, desc), th, J, inputs=True)
+    h = 1e-6
+    for (p, q) in [(0, 0), (1, 2), (3, 1)]:
+        tp, tm = th.copy(), th.copy()
+        tp[p, q] += h
+        tm[p, q] -= h
+        assert abs((loss(tp, J) - loss(tm, J)) / (2 * h) - d_th[p, q]) < 1e-8
+        for c in range(3):
+            jp, jm = J.copy(), J.copy()
+            jp[p, q, c] += h
+            jm[p, q, c] -= h
+            assert abs((loss(th, jp) - loss(th, jm)) / (2 * h) - d_J[p, q, c]) < 1e-8
