@@ -89,28 +89,86 @@ def recorded_traffic(kernel: str, workload: str):
     return None, None
 
 
-def cpu_baseline(w, budget_s: float = 12.0, max_points: int = 512):
-    from oracle import qpinn_oracle as O
+def cpu_baseline(w, sample_points: int | None = None):
+    """The CPU oracle (complex128, explicit Kronecker-product operators, stored-state reverse mode)
+    timed on this host's cores: the same three phases as a full evaluation (forward with tangents
+    per point chunk, loss seeds over the sample, reverse mode per chunk), spread over a process
+    pool of one single-threaded worker per core.  Runs before the process touches the GPU (the
+    pool forks)."""
+    from oracle import parallel as OP
+    n = w.circuit.n
+    workers = OP.host_cores()
+    chunk = OP.default_chunk(n)
+    if sample_points is None:   # about 10-30 s of work: two chunks per worker at 12 qubits
+        sample_points = min(len(w.points), workers * chunk * (2 if n >= 12 else 8))
+    pts = w.points[:sample_points]
+    with OP.Pool(workers) as pool:
+        OP.simulate(pool, w.circuit, w.params, pts[:workers], chunk=1)     # start the workers
+        t0 = time.perf_counter()
+        OP.maxwell_eval(pool, w.circuit, w.params, pts, w.loss, chunk=chunk)
+        dt = time.perf_counter() - t0
     try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
+        from threadpoolctl import threadpool_info
+        blas = sorted({f"{d.get('internal_api')}:{d.get('num_threads')}" for d in threadpool_info()})
     except Exception:  # pragma: no cover
-        lim = None
+        blas = []
+    rate = sample_points / dt
+    return {"value": round(rate, 3), "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "nproc": os.cpu_count(), "blas_threads_per_worker": 1, "blas_in_parent": blas,
+            "sample": f"first {sample_points} points of the same workload in chunks of {chunk} over {workers} "
+                      f"single-threaded worker processes: complex128 Kronecker-product forward with 3 tangents, "
+                      f"Maxwell loss seeds, stored-state reverse-mode gradient; {dt:.1f} s wall",
+            "full_step_s_extrapolated": round(len(w.points) / rate, 1)}
+
+
+def c1_plain_fp64(ctx, dev, reps: int = 20):
+    """Wall time of the plain FP64 method on its 4-qubit, 2-layer workload (1024 points): one
+    kernel per gate on an HBM statevector batch, readout, input tangents by central finite
+    differences (7 forwards).  Launch-latency bound; reported as wall time per evaluation."""
+    import torch
+    import workloads as W
+    from paper_2506_23246_amd.api import Circuit
+    w = W.config(0)
+    c = Circuit(ctx, w.circuit)
+    prm = torch.tensor(w.params, device=dev)
+    pts = torch.tensor(w.points, device=dev)
+    c.plain_eval(prm, pts, precision=64)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done, chunk = 0, 16
-    while done < max_points and time.perf_counter() - t0 < budget_s:
-        pts = w.points[done:done + chunk]
-        f, g = O.simulate(w.circuit, w.params, pts)
-        Wg = O.maxwell_seeds(g, pts, w.loss)
-        O.grad_reverse(w.circuit, w.params, pts, None, Wg)
-        done += len(pts)
-    dt = time.perf_counter() - t0
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
-    return {"value": done / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} points of the same workload: complex128 Kronecker-product forward, "
-                      f"3 tangents, Maxwell seeds and stored-state reverse-mode gradient, {dt:.1f} s "
-                      f"single-threaded"}
+    for _ in range(reps):
+        c.plain_eval(prm, pts, precision=64)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    launches = len(w.circuit.gates) * 7
+    c.close()
+    return {"workload": w.name, "points": len(w.points), "wall_ms": round(dt * 1e3, 4),
+            "evals_per_s": round(len(w.points) / dt, 1),
+            "what": f"FP64 complex statevectors, one kernel per gate ({launches} gate launches: forward + 6 "
+                    f"central-FD forwards, h = 1e-5), eager, mean of {reps} calls"}
+
+
+def parity_vs_stored_oracle(ctx, w, name):
+    """The fused step at the default launch on a stored oracle set (tests/golden): normwise relative
+    errors of outputs, tangents (at the stored indices), loss and gradient (over the whole set)."""
+    import numpy as np
+    from paper_2506_23246_amd.api import Circuit
+    from tests.golden.make_oracle_fixtures import SETS, load
+    ref = load(name)
+    ws = SETS[name]()
+    c = Circuit(ctx, ws.circuit)
+    r = c.maxwell(ws.params, ws.points, ws.loss)
+    idx = ref["idx"]
+
+    def rel(a, b):
+        a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    out = {"set": name, "points": int(ref["P"]),
+           "rel_err_out": rel(r["out"].cpu().numpy()[idx], ref["f"]),
+           "rel_err_tan": rel(r["tan"].cpu().numpy()[idx], ref["g"]),
+           "rel_err_loss": rel(r["loss"].cpu().numpy(), [float(ref["loss"])]),
+           "rel_err_grad": rel(r["grad"].cpu().numpy(), ref["grad"])}
+    c.close()
+    return out
 
 
 def main():
@@ -120,6 +178,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c5", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="points of the CPU oracle sample (default: two chunks per core at 12 qubits)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the plain FP64 4-qubit wall-time leg")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
@@ -148,14 +209,20 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import workloads as W
+    k = {"c2": 1, "c3": 2, "c4": 3, "c5": 4}[args.workload]
+    cpu_line = None
+    if k != 3 and not args.no_cpu_baseline:
+        # the oracle's process pool forks, so it runs before this process initialises the GPU
+        cpu_line = cpu_baseline(W.config(k), args.cpu_sample)
+        log(f"bench: cpu {cpu_line}")
+
+    import torch
     from paper_2506_23246_amd import _lib as L
     from paper_2506_23246_amd.api import Batch, Circuit, Context
 
     ctx = Context(0)
-    k = {"c2": 1, "c3": 2, "c4": 3, "c5": 4}[args.workload]
     dev = torch.device("cuda", 0)
     flags = L.QP_FLAG_TUNE if args.tune else 0
 
@@ -250,14 +317,17 @@ def main():
     ctx.use_stream(torch.cuda.current_stream(dev))   # the extra legs below run on torch's stream
     ctx.kernel_timing(False)
     kms_avg = float(np.mean(kms))
-    achieved = flops / (kms_avg / 1e3) / 1e12
+    # the roofline's work is the arithmetic the kernel's algorithm needs (executed-flop count:
+    # mul = 1, fma = 2, three-component gate statistic, opening stage folded); the larger
+    # 256-flop-per-amplitude model of a gate-by-gate 2x2 product is reported beside it
+    achieved = flops_x / (kms_avg / 1e3) / 1e12
     kname = "k_fused" if k != 3 else "k_batch"
     traffic, traffic_src = recorded_traffic(kname, cfg["workload"])
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
                 "kernel": kname, "kernel_ms": round(kms_avg, 4),
-                "algorithmic_flops_per_launch": flops,
-                "executed_flops_tflops": round(flops_x / (kms_avg / 1e3) / 1e12, 3)}
+                "algorithmic_flops_per_launch": flops_x,
+                "model_256_flops_per_amp_gate_tflops": round(flops / (kms_avg / 1e3) / 1e12, 3)}
     if traffic_src:
         roofline["traffic_record"] = traffic_src
     log(f"bench: main kernel {kms_avg:.3f} ms, {achieved:.2f} TFLOP/s algorithmic")
@@ -274,8 +344,11 @@ def main():
         out = bufs["out"][idx].cpu().numpy()
         tan = bufs["tan"][idx].cpu().numpy()
         rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
-        line["parity"] = {"sampled_points": len(idx), "rel_err_out": rel(out, f), "rel_err_tan": rel(tan, g),
+        line["parity"] = {"timed_run_sampled_points": len(idx), "rel_err_out": rel(out, f), "rel_err_tan": rel(tan, g),
                           "loss": float(bufs["loss"].cpu()[0]), "grad_norm": float(bufs["grad"].norm().cpu())}
+        stored = {4: "c5_first4096", 2: "c3_first16384"}.get(k)
+        if stored:
+            line["parity"]["stored_oracle_subsample"] = parity_vs_stored_oracle(ctx, w, stored)
         log(f"bench: parity {line['parity']}")
 
     if w is not None and not args.no_plain:
@@ -401,9 +474,12 @@ def main():
                            "A100, precision not stated; context only"}
         log(f"bench: paper context {line['paper_context']['ours_evals_per_s']}")
 
-    if w is not None and not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
-        log(f"bench: cpu {line['cpu_baseline']}")
+    if k == 4 and not args.no_c1:
+        line["c1_plain_fp64"] = c1_plain_fp64(ctx, dev)
+        log(f"bench: c1 {line['c1_plain_fp64']}")
+
+    if cpu_line is not None:
+        line["cpu_baseline"] = cpu_line
 
     print(json.dumps(line), flush=True)
 
