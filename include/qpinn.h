@@ -71,7 +71,9 @@ enum { QP_LOSS_VACUUM = 0, QP_LOSS_DIEL_SPLIT = 1, QP_LOSS_DIEL_INTUITIVE = 2 };
 /* Flags (bitwise or). */
 #define QP_FLAG_NO_TANGENTS 0x1u  /* qp_simulate: tangents not needed (tan may be NULL)      */
 #define QP_FLAG_LOSS_SUM    0x2u  /* Maxwell: sum of squared residuals instead of MSE means  */
-#define QP_FLAG_TUNE        0x4u  /* time the candidate launch shapes on first use and cache  */
+#define QP_FLAG_TUNE        0x4u  /* time the candidate launch shapes on first use and cache;
+                                     the first tuned call per point-count bucket waits for the
+                                     stream (HIP events), so it must not run under graph capture */
 #define QP_FLAG_DENSE_MFMA  0x8u  /* force the dense-block MFMA path (where the plan has one) */
 #define QP_FLAG_GATES_FP32  0x10u /* build the 2x2 gate table in FP32 instead of FP64-rounded  */
 
@@ -143,8 +145,10 @@ int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
 
 /* Launch shape of the fused kernel for this circuit (what the autotuner sets): exchange_planes
  * 4 = software-pipelined exchanges over two plane pairs, 2 = one plane pair, unpipelined;
- * wg_per_cu = persistent workgroups per CU.  The choice changes speed, not results beyond
- * rounding order.  QP_EINVAL for other values or a shape whose LDS does not fit a CU.       */
+ * wg_per_cu = persistent workgroups per CU, 1 at 12 qubits, 1..4 below (above 2 the grid runs
+ * in two generations).  The choice changes speed, not results beyond rounding order.
+ * QP_EINVAL for other values or a shape whose LDS does not fit a CU.  Circuit compilation
+ * applies a choice cached by an earlier tuned run (QP_TUNE_CACHE) for the same circuit shape. */
 qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_planes, int32_t wg_per_cu);
 
 /* Host-only introspection: builds the execution plan of `desc` without a device and copies its
@@ -166,21 +170,29 @@ qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params,
                       const float* points, const float* angles, const float* jac, int64_t P,
                       float* out, float* tan, void* ws, size_t ws_bytes, uint32_t flags);
 
-/* Vector-Jacobian product with respect to the parameters:
- *   d_params[k] = sum_p sum_i d_out[p,i] df_i/dtheta_k + sum_ic d_tan[p,i,c] dg_ic/dtheta_k.
- * d_out or d_tan may be NULL (treated as zero).  Recomputes the forward internally.         */
+/* Vector-Jacobian product of the scalar s = sum_p [sum_i d_out[p,i] f_i + sum_ic d_tan[p,i,c] g_ic]:
+ *   d_params[k] = ds/dtheta_k  ([K]);
+ * and, for the angle-given encoding (QP_ENC_ANGLES: the inputs a classical layer in front of the
+ * circuit produces, section "QPINN architecture and ansatz designs", angle embedding),
+ *   d_angles[p][q] = ds/d angles[p][q]  ([P][n], or NULL),
+ *   d_jac[p][q][c] = ds/d jac[p][q][c]  ([P][n][3], or NULL),
+ * so that the gradient flows on into that layer.  d_out or d_tan may be NULL (treated as zero).
+ * Recomputes the forward internally.  d_angles/d_jac with another encoding: QP_EINVAL; with
+ * QP_FLAG_DENSE_MFMA: QP_EUNSUPPORTED.                                                       */
 qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                  const float* angles, const float* jac, int64_t P, const float* d_out,
-                 const float* d_tan, float* d_params, void* ws, size_t ws_bytes,
-                 uint32_t flags);
+                 const float* d_tan, float* d_params, float* d_angles, float* d_jac, void* ws,
+                 size_t ws_bytes, uint32_t flags);
 
 /* Fused Maxwell evaluation: forward + tangents + residual loss + adjoint gradient in one
- * stream-ordered call.  out/tan may be NULL.  loss: one double (device); d_params: [K].     */
+ * stream-ordered call.  out/tan may be NULL.  loss: one double (device); d_params: [K];
+ * d_angles [P][n] / d_jac [P][n][3]: the loss gradient with respect to the per-point angles and
+ * their Jacobian (QP_ENC_ANGLES only, as for qp_vjp), or NULL.                               */
 qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params,
                            const float* points, const float* angles, const float* jac,
                            int64_t P, const qp_maxwell_desc* loss_desc, float* out, float* tan,
-                           double* loss, float* d_params, void* ws, size_t ws_bytes,
-                           uint32_t flags);
+                           double* loss, float* d_params, float* d_angles, float* d_jac, void* ws,
+                           size_t ws_bytes, uint32_t flags);
 
 /* ---- uneven batch: many circuits in one persistent launch ------------------------------
  * qp_batch_compile plans `count` circuits with their point counts P[count] (host), orders the

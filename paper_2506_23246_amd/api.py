@@ -155,21 +155,28 @@ class Circuit:
                               _ptr(tan) if tangents else None, wp, nb, flags), self.ctx.h)
         return out, (tan if tangents else None)
 
-    def vjp(self, params, points=None, d_out=None, d_tan=None, angles=None, jac=None, d_params=None, flags=0):
+    def vjp(self, params, points=None, d_out=None, d_tan=None, angles=None, jac=None, d_params=None, flags=0,
+            input_grads=False):
+        """d_params [K]; with input_grads=True (angle-given encoding) returns (d_params, d_angles [P,n],
+        d_jac [P,n,3])."""
         prm, pts, ang, jc = self._inputs(params, points, angles, jac)
         P = int((pts if pts is not None else ang).shape[0])
         dev = self.ctx.dev
         d_out = _f32(d_out, dev)
         d_tan = _f32(d_tan, dev)
         d_params = d_params if d_params is not None else torch.empty(self.K, dtype=torch.float32, device=dev)
+        d_ang = torch.empty((P, self.n), dtype=torch.float32, device=dev) if input_grads else None
+        d_jac = torch.empty((P, self.n, 3), dtype=torch.float32, device=dev) if input_grads else None
         _, wp, nb = self.workspace(P, flags)
         L.check(L.qp_vjp(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, _ptr(d_out), _ptr(d_tan),
-                         _ptr(d_params), wp, nb, flags), self.ctx.h)
-        return d_params
+                         _ptr(d_params), _ptr(d_ang), _ptr(d_jac), wp, nb, flags), self.ctx.h)
+        return (d_params, d_ang, d_jac) if input_grads else d_params
 
-    def maxwell(self, params, points, loss, angles=None, jac=None, outputs=True, flags=0, bufs=None):
+    def maxwell(self, params, points, loss, angles=None, jac=None, outputs=True, flags=0, bufs=None,
+                input_grads=False):
         """Fused forward + tangents + Maxwell loss + adjoint gradient.  Returns
-        dict(out, tan, loss (float64 [1]), grad (float32 [K]))."""
+        dict(out, tan, loss (float64 [1]), grad (float32 [K])), plus d_angles [P,n] and d_jac [P,n,3]
+        with input_grads=True (angle-given encoding)."""
         prm, pts, ang, jc = self._inputs(params, points, angles, jac)
         P = int((pts if pts is not None else ang).shape[0])
         dev = self.ctx.dev
@@ -180,11 +187,14 @@ class Circuit:
                 "loss": torch.empty(1, dtype=torch.float64, device=dev),
                 "grad": torch.empty(self.K, dtype=torch.float32, device=dev),
             }
+        if input_grads:
+            bufs["d_angles"] = torch.empty((P, self.n), dtype=torch.float32, device=dev)
+            bufs["d_jac"] = torch.empty((P, self.n, 3), dtype=torch.float32, device=dev)
         _, wp, nb = self.workspace(P, flags)
         md = maxwell_desc(loss)
         L.check(L.qp_maxwell_fused(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P, C.byref(md),
                                    _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]), _ptr(bufs["grad"]),
-                                   wp, nb, flags), self.ctx.h)
+                                   _ptr(bufs.get("d_angles")), _ptr(bufs.get("d_jac")), wp, nb, flags), self.ctx.h)
         return bufs
 
     # ---- plain baseline -------------------------------------------------------------------

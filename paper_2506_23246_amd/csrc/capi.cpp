@@ -142,7 +142,7 @@ extern "C" qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_plane
   if (!c->hp.fused_ok) return fail(c->ctx, QP_EUNSUPPORTED, "qp_circuit_set_launch: %s", c->hp.fused_reason.c_str());
   if (exchange_planes != 2 && exchange_planes != 4)
     return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: exchange_planes must be 2 or 4");
-  const int max_wg = fused_threads(c->hp.n) == 512 ? 1 : 2;   // register file: 2 waves per SIMD
+  const int max_wg = fused_max_wg_per_cu(c->hp.n);
   const size_t lds = fused_lds_bytes(c->hp.n, exchange_planes, (int)c->hp.fused.size());
   if (wg_per_cu < 1 || wg_per_cu > max_wg || lds * (size_t)wg_per_cu > 160 * 1024)
     return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: %d workgroups of %zu LDS bytes do not fit a CU", wg_per_cu, lds);
@@ -343,8 +343,8 @@ static qp_status run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const flo
 // Shared launch sequence of the three fused entry points.
 qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                         const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
-                        float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
-                        uint32_t flags, int exs_override, int grid_override) {
+                        float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,
+                        float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override) {
   hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
   const int n = c->hp.n;
@@ -392,6 +392,8 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.counts = counts;
   a.mpart = reinterpret_cast<float*>(w + L.mpart);
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
+  a.d_angles = mode == kModeFwd ? nullptr : d_angles;
+  a.d_jac = mode == kModeFwd ? nullptr : d_jac;
   if (grid > 0) {
     if (ctx->timing) hipEventRecord(ctx->ev0, st);
     if ((e = launch_fused(n, mode, a, grid, exs, c->hp.has_signs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
@@ -418,26 +420,41 @@ extern "C" qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* 
     return run_dense(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
                      (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags);
   return run_fused(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
-                   (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags, 0, 0);
+                   (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   ws, flags, 0, 0);
+}
+
+// Input gradients (dL/d angles, dL/d Jacobian) exist for the angle-given encoding on the fused path.
+static qp_status check_input_grads(qp_ctx* ctx, const qp_circuit* c, float* d_angles, float* d_jac, int64_t P,
+                                   uint32_t flags, const char* who) {
+  if (!d_angles && !d_jac) return QP_OK;
+  if (c->hp.enc_kind != QP_ENC_ANGLES)
+    return fail(ctx, QP_EINVAL, "%s: d_angles/d_jac need the angle-given encoding (QP_ENC_ANGLES)", who);
+  if (flags & QP_FLAG_DENSE_MFMA)
+    return fail(ctx, QP_EUNSUPPORTED, "%s: d_angles/d_jac are not computed by the dense-block path", who);
+  (void)P;
+  return QP_OK;
 }
 
 extern "C" qp_status qp_vjp(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                             const float* angles, const float* jac, int64_t P, const float* d_out, const float* d_tan,
-                            float* d_params, void* ws, size_t ws_bytes, uint32_t flags) {
+                            float* d_params, float* d_angles, float* d_jac, void* ws, size_t ws_bytes,
+                            uint32_t flags) {
   qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, "qp_vjp", flags);
   if (s != QP_OK) return s;
   if (c->hp.K > 0 && !d_params) return fail(ctx, QP_EINVAL, "qp_vjp: d_params is null");
+  if ((s = check_input_grads(ctx, c, d_angles, d_jac, P, flags, "qp_vjp")) != QP_OK) return s;
   if (flags & QP_FLAG_DENSE_MFMA)
     return run_dense(ctx, c, kModeVjp, params, points, angles, jac, P, nullptr, nullptr, nullptr, d_out, d_tan, nullptr,
                      d_params, ws, flags);
   return run_fused(ctx, c, kModeVjp, params, points, angles, jac, P, nullptr, nullptr, nullptr, d_out, d_tan, nullptr,
-                   d_params, ws, flags, 0, 0);
+                   d_params, d_angles, d_jac, ws, flags, 0, 0);
 }
 
 qp_status qp::maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                             const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
-                            float* tan, double* loss, float* d_params, void* ws, size_t ws_bytes, uint32_t flags,
-                            const char* who) {
+                            float* tan, double* loss, float* d_params, float* d_angles, float* d_jac, void* ws,
+                            size_t ws_bytes, uint32_t flags, const char* who) {
   qp_status s = check_common(ctx, c, params, points, angles, jac, P, ws, ws_bytes, who, flags);
   if (s != QP_OK) return s;
   if (!ld) return fail(ctx, QP_EINVAL, "%s: loss descriptor is null", who);
@@ -445,20 +462,21 @@ qp_status qp::maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* param
   if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "%s: the Maxwell loss needs 3 outputs (E_z, H_x, H_y)", who);
   if (ld->kind != QP_LOSS_VACUUM && P > 0 && !points) return fail(ctx, QP_EINVAL, "%s: dielectric loss needs points", who);
   if (!loss || (c->hp.K > 0 && !d_params)) return fail(ctx, QP_EINVAL, "%s: loss/d_params null", who);
+  if ((s = check_input_grads(ctx, c, d_angles, d_jac, P, flags, who)) != QP_OK) return s;
   if (flags & QP_FLAG_DENSE_MFMA)
     return run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                      ws, flags);
   if ((flags & QP_FLAG_TUNE) && P > 0) tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws);
   return run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
-                   ws, flags, 0, 0);
+                   d_angles, d_jac, ws, flags, 0, 0);
 }
 
 extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                                       const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld,
-                                      float* out, float* tan, double* loss, float* d_params, void* ws,
-                                      size_t ws_bytes, uint32_t flags) {
-  return maxwell_entry(ctx, c, params, points, angles, jac, P, ld, out, tan, loss, d_params, ws, ws_bytes, flags,
-                       "qp_maxwell_fused");
+                                      float* out, float* tan, double* loss, float* d_params, float* d_angles,
+                                      float* d_jac, void* ws, size_t ws_bytes, uint32_t flags) {
+  return maxwell_entry(ctx, c, params, points, angles, jac, P, ld, out, tan, loss, d_params, d_angles, d_jac, ws,
+                       ws_bytes, flags, "qp_maxwell_fused");
 }
 
 // ---------------------------------------------------------------- plain ---------------------

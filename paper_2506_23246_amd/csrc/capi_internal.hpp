@@ -43,13 +43,13 @@ int fused_grid(const qp_ctx* ctx, const qp_circuit* c, int64_t P);
 WsLayout fused_layout(const qp_circuit* c, int64_t P, int grid_cap);
 qp_status run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                     const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
-                    float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
-                    uint32_t flags, int exs_override, int grid_override);
+                    float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,
+                    float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override);
 // Argument checks and launch sequence of the fused Maxwell evaluation (who names the entry point
 // in error messages).
 qp_status maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
                         const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
-                        float* tan, double* loss, float* d_params, void* ws, size_t ws_bytes, uint32_t flags,
-                        const char* who);
+                        float* tan, double* loss, float* d_params, float* d_angles, float* d_jac, void* ws,
+                        size_t ws_bytes, uint32_t flags, const char* who);
 
 }  // namespace qp

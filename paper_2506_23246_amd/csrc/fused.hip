@@ -170,6 +170,7 @@ __global__ void k_param_grads(const QPlanDev* __restrict__ plan, const float* __
 }
 
 int fused_threads(int n) { return fused_wg_threads(n); }
+int fused_max_wg_per_cu(int n) { return fused_threads(n) == 512 ? 1 : 4; }
 int fused_points_per_tile(int n) { return fused_threads(n) / (1 << (n - 3)); }
 size_t fused_lds_bytes(int n, int exs, int n_fused) {
   const int T = fused_threads(n);

@@ -29,9 +29,15 @@ struct FusedArgs {
   const int* counts;      // [2]: points with x < x_if, points with x >= x_if
   float* mpart;           // [grid][F][8]
   float* lpart;           // [grid]
+  float* d_angles;        // [P][n] dL/d angles (angle-given encoding) or null
+  float* d_jac;           // [P][n][3] dL/d Jacobian or null
 };
 
 int fused_threads(int n);
+// Largest persistent grid, in workgroups per CU, that a launch may ask for: one 512-thread
+// workgroup (12 qubits) or four 256-thread ones.  About 256 VGPRs per lane keep two waves per
+// SIMD resident, so a grid above two 256-thread workgroups per CU runs in generations.
+int fused_max_wg_per_cu(int n);
 int fused_points_per_tile(int n);
 size_t fused_lds_bytes(int n, int exs, int n_fused);
 hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);

@@ -518,9 +518,166 @@ __device__ __forceinline__ QEnc encode_qubit(CP<QPlanDev> plan, CP<float> gtab, 
   return E;
 }
 
+// ---- gradients with respect to the per-point angles and their Jacobian ------------------------
+// The embedding rotation of qubit q has generator G_q (Y for RY, X for RX): d psi_0/d theta_q =
+// -(i/2) G_q psi_0, and the tangents are dpsi_c,0 = sum_q J_qc (-(i/2) G_q) psi_0, so (the G's of
+// different qubits commute) d dpsi_c,0/d theta_q = -(i/2) G_q dpsi_c,0.  With lambda, mu_c the
+// adjoints pulled back to the embedded state,
+//   dL/d theta_q = Im <lambda|G_q|psi> + sum_c Im <mu_c|G_q|dpsi_c>,   dL/d J_qc = Im <mu_c|G_q|psi>,
+// the same Pauli statistics the adjoint takes for every gate, but per point.  When the circuit's
+// opening rotation stage is folded into the encoding, the sweep ends at that stage's output, and
+// G_q is replaced by U_q G_q U_q^H (U_q the stage's gate on qubit q), which the statistics
+// contract with as an axis (n_x, n_y, n_z).  At the end of the sweep the statevectors sit in round
+// 0's input mapping.  The partner amplitude of a pair (index bit of qubit q flipped) lies in the
+// same thread (register bit) or in another thread of the point (thread bit); it is read back from
+// the LDS planes, where the psi-family is staged two statevectors at a time.
+template <int N, int T>
+__device__ __forceinline__ float enc_pair(float nx, float ny, float nz, float sb, float xr, float xi, float yor,
+                                          float yoi, float2 yp) {
+  const float im_p = xr * yp.y - xi * yp.x;    // Im(conj(x) y_partner)
+  const float re_p = xr * yp.x + xi * yp.y;    // Re(conj(x) y_partner)
+  const float im_o = xr * yoi - xi * yor;      // Im(conj(x) y_own)
+  return nx * im_p + sb * (ny * re_p - nz * im_o);
+}
+
+template <int N, int T, int PASS>
+__device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const float (&si)[8][8],
+                                              float2* __restrict__ buf, CP<QPlanDev> plan, CP<QRound> r0,
+                                              CP<float> gtab, uint32_t jl, float (&at)[N], float (&aj)[N][3]) {
+  constexpr int PLANE = T * 8;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t l0 = r0->tpos[0], l1 = r0->tpos[1], l2 = r0->tpos[2];
+  __syncthreads();   // the planes are free (every wave is past its last read of the sweep)
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t e = tid * 8 + (r ^ (tid & 7));
+    buf[e] = make_float2(sr[2 * PASS][r], si[2 * PASS][r]);
+    buf[PLANE + e] = make_float2(sr[2 * PASS + 1][r], si[2 * PASS + 1][r]);
+  }
+  __syncthreads();
+  const bool rx = plan->enc_gate == QP_ENC_RX;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int pos = N - 1 - q;
+    uint32_t rmask = 0, tmask = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (r0->tpos[k] == pos) {
+        if (k < 3) rmask = 1u << k;
+        else tmask = 1u << (k - 3);
+      }
+    }
+    // axis of U G U^H (U: the opening-stage gate on q, identity if none; G = X or Y)
+    float u[8] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+    const int hg = plan->head_gate[q];
+    if (hg >= 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] = gtab[hg * kGT + i];
+    }
+    // W = U G: X swaps U's columns; Y gives [[i u01, -i u00], [i u11, -i u10]]
+    float w00r, w00i, w01r, w01i, w10r, w10i, w11r, w11i;
+    if (rx) {
+      w00r = u[2]; w00i = u[3]; w01r = u[0]; w01i = u[1];
+      w10r = u[6]; w10i = u[7]; w11r = u[4]; w11i = u[5];
+    } else {
+      w00r = -u[3]; w00i = u[2]; w01r = u[1]; w01i = -u[0];
+      w10r = -u[7]; w10i = u[6]; w11r = u[5]; w11i = -u[4];
+    }
+    // M = W U^H: M00 = W00 conj(u00) + W01 conj(u01), M01 = W00 conj(u10) + W01 conj(u11)
+    const float m00r = w00r * u[0] + w00i * u[1] + w01r * u[2] + w01i * u[3];
+    const float m01r = w00r * u[4] + w00i * u[5] + w01r * u[6] + w01i * u[7];
+    const float m01i = w00i * u[4] - w00r * u[5] + w01i * u[6] - w01r * u[7];
+    const float nx = m01r, ny = -m01i, nz = m00r;
+    const uint32_t ptid = tid ^ tmask;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t j = jl ^ reg_off(r, l0, l1, l2);
+      const float sb = ((j >> pos) & 1u) ? 1.f : -1.f;
+      const uint32_t e = ptid * 8 + (((uint32_t)r ^ rmask) ^ (ptid & 7));
+      const float2 y0 = buf[e];
+      const float2 y1 = buf[PLANE + e];
+      if (PASS == 0) {   // partners of psi and dpsi_t
+        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[4][r], si[4][r], sr[0][r], si[0][r], y0);
+        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[5][r], si[5][r], sr[1][r], si[1][r], y1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          aj[q][c] += enc_pair<N, T>(nx, ny, nz, sb, sr[5 + c][r], si[5 + c][r], sr[0][r], si[0][r], y0);
+      } else {           // partners of dpsi_x and dpsi_y
+        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[6][r], si[6][r], sr[2][r], si[2][r], y0);
+        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[7][r], si[7][r], sr[3][r], si[3][r], y1);
+      }
+    }
+  }
+}
+
+template <int N, int T>
+__device__ __forceinline__ void encoding_grads(const float (&sr)[8][8], const float (&si)[8][8],
+                                               float2* __restrict__ buf, CP<QPlanDev> plan, CP<QRound> r0,
+                                               CP<float> gtab, const FusedArgs& a, long long pt, bool valid,
+                                               uint32_t u) {
+  constexpr int TP = 1 << (N - 3);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const uint32_t jl = deposit_thread<N>(u, r0->tpos);
+  float at[N], aj[N][3];
+#pragma unroll
+  for (int q = 0; q < N; ++q) { at[q] = 0.f; aj[q][0] = aj[q][1] = aj[q][2] = 0.f; }
+  enc_grad_pass<N, T, 0>(sr, si, buf, plan, r0, gtab, jl, at, aj);
+  enc_grad_pass<N, T, 1>(sr, si, buf, plan, r0, gtab, jl, at, aj);
+  // sum over the point's threads
+#pragma unroll
+  for (int off = 1; off < (TP < 64 ? TP : 64); off <<= 1) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      at[q] += __shfl_xor(at[q], off);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) aj[q][c] += __shfl_xor(aj[q][c], off);
+    }
+  }
+  if (TP > 64) {     // the point spans TP / 64 waves: combine them through LDS
+    float* fb = reinterpret_cast<float*>(buf);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        fb[wave * 4 * N + 4 * q] = at[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fb[wave * 4 * N + 4 * q + 1 + c] = aj[q][c];
+      }
+    }
+    __syncthreads();
+    constexpr int WPP = TP / 64;
+    const int w0 = (wave / WPP) * WPP;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+      for (int w = 0; w < WPP; ++w) {
+        s0 += fb[(w0 + w) * 4 * N + 4 * q];
+        s1 += fb[(w0 + w) * 4 * N + 4 * q + 1];
+        s2 += fb[(w0 + w) * 4 * N + 4 * q + 2];
+        s3 += fb[(w0 + w) * 4 * N + 4 * q + 3];
+      }
+      at[q] = s0; aj[q][0] = s1; aj[q][1] = s2; aj[q][2] = s3;
+    }
+  }
+  if (valid && u == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (a.d_angles) a.d_angles[pt * N + q] = at[q];
+      if (a.d_jac) {
+        a.d_jac[(pt * N + q) * 3 + 0] = aj[q][0];
+        a.d_jac[(pt * N + q) * 3 + 1] = aj[q][1];
+        a.d_jac[(pt * N + q) * 3 + 2] = aj[q][2];
+      }
+    }
+  }
+  __syncthreads();   // the next tile's first exchange writes the planes
+}
+
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
-template <int N, int T, int EXS, int MODE, bool SG = true>
+template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ red, float& lacc) {
   constexpr int TP = 1 << (N - 3);         // threads per point
@@ -913,11 +1070,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
     }
+    if constexpr (EG) encoding_grads<N, T>(sr, si, buf, plan, rounds, gtab, a, pt, valid, u);
   }
 }
 
 // ---- the fused kernel: a persistent grid walks the tiles ------------------------------------
-template <int N, int T, int EXS, int MODE, bool SG>
+template <int N, int T, int EXS, int MODE, bool SG, bool EG = false>
 __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   constexpr int WAVES = T / 64;
   constexpr int PLANE = T * 8;
@@ -949,7 +1107,7 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
     t_step = gridDim.x / kXcd;
   }
   for (int tile = t_begin; tile < t_end; tile += t_step)
-    fused_tile<N, T, EXS, MODE, SG>(a, tile, buf, slots, red, lacc);
+    fused_tile<N, T, EXS, MODE, SG, EG>(a, tile, buf, slots, red, lacc);
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
@@ -973,10 +1131,10 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
 }
 
 
-template <int N, int EXS, int MODE, bool SG>
+template <int N, int EXS, int MODE, bool SG, bool EG = false>
 hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) {
   constexpr int T = fused_wg_threads(N);
-  auto kern = k_fused<N, T, EXS, MODE, SG>;
+  auto kern = k_fused<N, T, EXS, MODE, SG, EG>;
   // lds counts the static exchange planes and the dynamic part; only the latter is passed.
   const size_t planes = (size_t)EXS * T * 8 * sizeof(float2);
   const size_t dyn = lds > planes ? lds - planes : 0;
@@ -999,6 +1157,13 @@ hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) 
 // pipelined kernel has a variant without the sign code for circuits that have none).
 template <int N>
 hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st) {
+  if (mode != kModeFwd && (a.d_angles || a.d_jac)) {   // per-point input gradients (angle-given encoding)
+    if (mode == kModeMaxwell)
+      return exs == 2 ? launch_one<N, 2, kModeMaxwell, true, true>(a, grid, lds, st)
+                      : launch_one<N, 4, kModeMaxwell, true, true>(a, grid, lds, st);
+    return exs == 2 ? launch_one<N, 2, kModeVjp, true, true>(a, grid, lds, st)
+                    : launch_one<N, 4, kModeVjp, true, true>(a, grid, lds, st);
+  }
   if (mode == kModeFwd) {
     if (exs == 2) return launch_one<N, 2, kModeFwd, true>(a, grid, lds, st);
     return signs ? launch_one<N, 4, kModeFwd, true>(a, grid, lds, st) : launch_one<N, 4, kModeFwd, false>(a, grid, lds, st);

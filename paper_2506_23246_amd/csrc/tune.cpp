@@ -1,7 +1,9 @@
 // Autotuner: times every legal (exchange depth, workgroups per CU) pair of a circuit's fused
 // Maxwell step with HIP events on the context stream and keeps the fastest.  The key is
-// (arch, n, rounds, fused gates, entangler kinds, point-count bucket); results persist as
-// JSON lines in the file named by QP_TUNE_CACHE (if set).
+// (arch, n, rounds, fused gates, entangler kinds) plus a point-count bucket; results persist as
+// JSON lines in the file named by QP_TUNE_CACHE (if set; later lines override earlier ones).
+// Each tuning also records its choice under the bucket "any", which circuit compilation looks up
+// so that a cached choice applies from the first evaluation on.
 #include "tune.hpp"
 
 #include <cmath>
@@ -93,7 +95,7 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   TuneEntry best{c->exs, c->wg_per_cu, 1e30};
-  const int max_wg = fused_threads(n) == 512 ? 1 : 4;
+  const int max_wg = fused_max_wg_per_cu(n);
   for (int exs : {2, 4}) {
     const size_t lds = fused_lds_bytes(n, exs, F);
     if (lds > cap) continue;
@@ -104,7 +106,7 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
       for (int rep = 0; rep < 3; ++rep) {   // first run warms up; the main kernel only
         hipEventRecord(e0, ctx->stream);
         run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, nullptr, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, ws, 0, exs, grid);
+                  nullptr, nullptr, nullptr, nullptr, ws, 0, exs, grid);
         hipEventRecord(e1, ctx->stream);
         hipEventSynchronize(e1);
         float ms = 0.f;
@@ -119,8 +121,11 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
   c->exs = best.exs;
   c->wg_per_cu = best.wg_per_cu;
   std::lock_guard<std::mutex> lk(g_mu);
+  const std::string any = tune_key(ctx, c) + "/any";
   g_cache[key] = best;
+  g_cache[any] = best;
   append_file(key, best);
+  append_file(any, best);
 }
 
 }  // namespace qp

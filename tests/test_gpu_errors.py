@@ -25,7 +25,8 @@ def _call(ctx, c, prm, pts, P, md, bufs, wp, nb, flags=0):
     from paper_2506_23246_amd import _lib as L
     from paper_2506_23246_amd.api import _ptr
     return L.qp_maxwell_fused(ctx.h, c.h, _ptr(prm), _ptr(pts), None, None, P, C.byref(md) if md is not None else None,
-                              _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]), _ptr(bufs["grad"]), wp, nb, flags)
+                              _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]), _ptr(bufs["grad"]), None, None,
+                              wp, nb, flags)
 
 
 def _setup(ctx, k=1, P=64):

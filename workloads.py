@@ -274,8 +274,15 @@ def batch_config(P_cap: int | None = None, count: int = 32) -> list:
 
 
 def paper_context_circuit(ansatz: str = "basic", n: int = 7, L: int = 4) -> Circuit:
-    """The paper's PQC shape: 7 qubits, 4 layers, RX angle embedding (section "QPINN architecture")."""
+    """The paper's PQC shape: 7 qubits, 4 layers, RX angle embedding, <Z> of every qubit read out
+    (section "QPINN architecture": each qubit acts as a neuron of the layer)."""
     enc = Encoding(kind=ENC_ANGLES, gate=ENC_RX, scale=SCALE_ACOS)
+    circ = _paper_ansatz(ansatz, n, L, enc)
+    circ.out_qubits = list(range(n))
+    return circ
+
+
+def _paper_ansatz(ansatz, n, L, enc):
     if ansatz == "basic":
         return basic_entangling(n, L, "rot", enc=enc)
     if ansatz == "strong":
