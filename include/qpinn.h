@@ -194,6 +194,27 @@ qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params
                            double* loss, float* d_params, float* d_angles, float* d_jac, void* ws,
                            size_t ws_bytes, uint32_t flags);
 
+/* ---- fused Maxwell evaluation without allocation ---------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, checks and
+ * results as qp_maxwell_fused minus the workspace: the per-call scratch (gate table, dielectric
+ * counts, random-Fourier-feature angles, per-workgroup partials, FP64 reductions) lives in a
+ * fixed device array of QP_NOALLOC_SCRATCH_BYTES inside the library, one copy per device, held
+ * until the process ends.  Nothing in it needs to start at zero: every call writes what it reads.
+ * Errors: QP_EWORKSPACE when the call needs more scratch than the array holds
+ * (qp_workspace_bytes(c, P, 0) > QP_NOALLOC_SCRATCH_BYTES; only random-Fourier-feature circuits
+ * grow with P, by 16 n bytes per point), QP_EUNSUPPORTED with QP_FLAG_TUNE or QP_FLAG_DENSE_MFMA
+ * (they need a caller workspace), otherwise as qp_maxwell_fused.  All calls on one device share
+ * the array: calls that overlap on one device (several streams or threads) race and must be
+ * serialised by the caller.  qp_noalloc_scratch_bytes() returns the array size.            */
+#define QP_NOALLOC_SCRATCH_BYTES (16u << 20)
+size_t qp_noalloc_scratch_bytes(void);
+qp_status qp_maxwell_fused_noalloc(qp_ctx* ctx, const qp_circuit* c, const float* params,
+                                   const float* points, const float* angles, const float* jac,
+                                   int64_t P, const qp_maxwell_desc* loss_desc, float* out,
+                                   float* tan, double* loss, float* d_params, float* d_angles,
+                                   float* d_jac, uint32_t flags);
+
 /* ---- uneven batch: many circuits in one persistent launch ------------------------------
  * qp_batch_compile plans `count` circuits with their point counts P[count] (host), orders the
  * (circuit, point-tile) work items longest first and uploads the work list.  qp_batch_run

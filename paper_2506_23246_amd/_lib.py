@@ -64,6 +64,9 @@ _SIGS = {
     "qp_vjp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_size_t, C.c_uint32]),
     "qp_maxwell_fused": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(qp_maxwell_desc), _P, _P, _P,
                                    _P, _P, _P, _P, C.c_size_t, C.c_uint32]),
+    "qp_noalloc_scratch_bytes": (C.c_size_t, []),
+    "qp_maxwell_fused_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(qp_maxwell_desc), _P, _P,
+                                           _P, _P, _P, _P, C.c_uint32]),
     "qp_batch_compile": (C.c_int, [_P, C.c_int32, C.POINTER(qp_circuit_desc), C.POINTER(C.c_int64),
                                    C.POINTER(_P)]),
     "qp_batch_destroy": (None, [_P]),

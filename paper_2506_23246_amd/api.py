@@ -197,6 +197,23 @@ class Circuit:
                                    _ptr(bufs.get("d_angles")), _ptr(bufs.get("d_jac")), wp, nb, flags), self.ctx.h)
         return bufs
 
+    def maxwell_noalloc(self, params, points, loss, angles=None, jac=None, flags=0, bufs=None):
+        """qp_maxwell_fused_noalloc: the same evaluation with the library's fixed scratch array
+        instead of a workspace (the caller still provides inputs and outputs)."""
+        prm, pts, ang, jc = self._inputs(params, points, angles, jac)
+        P = int((pts if pts is not None else ang).shape[0])
+        dev = self.ctx.dev
+        if bufs is None:
+            bufs = {"out": torch.empty((P, self.m), dtype=torch.float32, device=dev),
+                    "tan": torch.empty((P, self.m, 3), dtype=torch.float32, device=dev),
+                    "loss": torch.empty(1, dtype=torch.float64, device=dev),
+                    "grad": torch.empty(self.K, dtype=torch.float32, device=dev)}
+        md = maxwell_desc(loss)
+        L.check(L.qp_maxwell_fused_noalloc(self.ctx.h, self.h, _ptr(prm), _ptr(pts), _ptr(ang), _ptr(jc), P,
+                                           C.byref(md), _ptr(bufs["out"]), _ptr(bufs["tan"]), _ptr(bufs["loss"]),
+                                           _ptr(bufs["grad"]), None, None, flags), self.ctx.h)
+        return bufs
+
     # ---- plain baseline -------------------------------------------------------------------
     def plain_workspace(self, P, precision):
         nb = int(L.qp_plain_workspace_bytes(self.h, int(P), int(precision)))
