@@ -338,6 +338,141 @@ def maxwell_seeds(g, points, desc):
     return W
 
 
+# ------------------------------------------------------- the paper's total loss ---------------
+#
+# L_tot = L_phys + w_ic L_IC + w_sym L_sym + w_energy L_energy (eq. 2D_lossTot, weights 1/10/10/10)
+# over three point sets: the collocation points X (residuals, energy), their mirror images
+# X_mx = (t, -x, y) and X_my = (t, x, -y) (symmetry), and the initial-condition plane X_0 = (0, x, y).
+
+def mirror_points(points, axis: int):
+    """(t, -x, y) for axis 1, (t, x, -y) for axis 2."""
+    out = np.array(points, dtype=np.float64, copy=True)
+    out[:, axis] = -out[:, axis]
+    return out
+
+
+def ic_points(ic_xy):
+    """(t, x, y) = (0, x, y) for the initial-condition plane."""
+    xy = np.asarray(ic_xy, np.float64)
+    return np.concatenate([np.zeros((xy.shape[0], 1)), xy], axis=1)
+
+
+def _eps(points, desc):
+    pts = np.asarray(points, np.float64)
+    if desc.kind == LOSS_VACUUM:
+        return np.ones(pts.shape[0])
+    return np.where(pts[:, 1] >= desc.x_interface, desc.eps_r, 1.0)
+
+
+def energy_residual(f, g, points, desc):
+    """Local Poynting residual (eqs. Poynting_thm, Poynting_value_u, Poynting_value_S, energy_loss)
+    with u = (eps E^2 + Hx^2 + Hy^2)/2, S = (-E Hy, E Hx), J = 0:
+      e = eps E dE/dt + Hx dHx/dt + Hy dHy/dt - (dE/dx Hy + E dHy/dx) + (dE/dy Hx + E dHx/dy)."""
+    eps = _eps(points, desc)
+    E, Hx, Hy = f[:, 0], f[:, 1], f[:, 2]
+    Et, Ex, Ey = g[:, 0, 0], g[:, 0, 1], g[:, 0, 2]
+    Hxt, Hxy = g[:, 1, 0], g[:, 1, 2]
+    Hyt, Hyx = g[:, 2, 0], g[:, 2, 1]
+    return (eps * E * Et + Hx * Hxt + Hy * Hyt) - (Ex * Hy + E * Hyx) + (Ey * Hx + E * Hxy)
+
+
+def ic_target(ic_xy, a):
+    xy = np.asarray(ic_xy, np.float64)
+    return np.exp(-a * (xy[:, 0] ** 2 + xy[:, 1] ** 2))
+
+
+def _sym_terms(f, f_mx, f_my, desc):
+    """Per-point squared parity defects of eq. 2D_symLoss: E even in x and y, H_x even in x and odd
+    in y, H_y odd in x and even in y; the x-mirror terms only for the vacuum loss."""
+    terms = (f[:, 0] - f_my[:, 0]) ** 2 + (f[:, 1] + f_my[:, 1]) ** 2 + (f[:, 2] - f_my[:, 2]) ** 2
+    if desc.phys.kind == LOSS_VACUUM:
+        terms = terms + (f[:, 0] - f_mx[:, 0]) ** 2 + (f[:, 1] - f_mx[:, 1]) ** 2 + (f[:, 2] + f_mx[:, 2]) ** 2
+    return terms
+
+
+def total_loss(f, g, f_mx, f_my, f_ic, points, ic_xy, desc):
+    """The four terms and their weighted sum (eq. 2D_lossTot).  L_IC = mean over the plane of
+    (E - E_0)^2 + Hx^2 + Hy^2 (eq. IC_loss); L_sym = mean over X of the parity defects; L_energy =
+    mean over X of the squared Poynting residual (the paper prints the residual; it is squared and
+    averaged here like every other residual)."""
+    P = f.shape[0]
+    phys = maxwell_loss(g, points, desc.phys)
+    E0 = ic_target(ic_xy, desc.ic_a)
+    ic = float(np.mean((f_ic[:, 0] - E0) ** 2 + f_ic[:, 1] ** 2 + f_ic[:, 2] ** 2)) if len(E0) else 0.0
+    sym = float(np.mean(_sym_terms(f, f_mx, f_my, desc))) if P else 0.0
+    energy = float(np.mean(energy_residual(f, g, points, desc.phys) ** 2)) if P else 0.0
+    total = phys + desc.w_ic * ic + desc.w_sym * sym + desc.w_energy * energy
+    return {"total": total, "phys": phys, "ic": ic, "sym": sym, "energy": energy}
+
+
+def total_loss_seeds(f, g, f_mx, f_my, f_ic, points, ic_xy, desc):
+    """d L_tot / d(f, g) on every set, differentiated by hand from total_loss:
+    returns (Vf [P,m], Wg [P,m,3], V_mx [P,m], V_my [P,m], V_ic [P0,m]); only the first three
+    outputs (E_z, H_x, H_y) carry seeds."""
+    P, m = f.shape
+    Vf = np.zeros((P, m))
+    Wg = maxwell_seeds(g, points, desc.phys)
+    V_mx = np.zeros((P, m))
+    V_my = np.zeros((P, m))
+    # energy: w_energy * mean(e^2)
+    if P:
+        eps = _eps(points, desc.phys)
+        e = energy_residual(f, g, points, desc.phys)
+        k = desc.w_energy * 2.0 * e / P
+        E, Hx, Hy = f[:, 0], f[:, 1], f[:, 2]
+        Et, Ex, Ey = g[:, 0, 0], g[:, 0, 1], g[:, 0, 2]
+        Hxt, Hxy = g[:, 1, 0], g[:, 1, 2]
+        Hyt, Hyx = g[:, 2, 0], g[:, 2, 1]
+        Vf[:, 0] += k * (eps * Et - Hyx + Hxy)
+        Vf[:, 1] += k * (Hxt + Ey)
+        Vf[:, 2] += k * (Hyt - Ex)
+        Wg[:, 0, 0] += k * eps * E
+        Wg[:, 0, 1] += -k * Hy
+        Wg[:, 0, 2] += k * Hx
+        Wg[:, 1, 0] += k * Hx
+        Wg[:, 1, 2] += k * E
+        Wg[:, 2, 0] += k * Hy
+        Wg[:, 2, 1] += -k * E
+        # symmetry: w_sym * mean(defects); d (a - s b)^2 = 2 (a - s b) (da - s db)
+        ks = desc.w_sym * 2.0 / P
+        for i, s in enumerate((1.0, -1.0, 1.0)):          # y-mirror parities of E, Hx, Hy
+            d = f[:, i] - s * f_my[:, i]
+            Vf[:, i] += ks * d
+            V_my[:, i] += -ks * s * d
+        if desc.phys.kind == LOSS_VACUUM:
+            for i, s in enumerate((1.0, 1.0, -1.0)):      # x-mirror parities
+                d = f[:, i] - s * f_mx[:, i]
+                Vf[:, i] += ks * d
+                V_mx[:, i] += -ks * s * d
+    P0 = f_ic.shape[0]
+    V_ic = np.zeros((P0, m))
+    if P0:
+        ki = desc.w_ic * 2.0 / P0
+        V_ic[:, 0] = ki * (f_ic[:, 0] - ic_target(ic_xy, desc.ic_a))
+        V_ic[:, 1] = ki * f_ic[:, 1]
+        V_ic[:, 2] = ki * f_ic[:, 2]
+    return Vf, Wg, V_mx, V_my, V_ic
+
+
+def total_eval(circ, params, points, ic_xy, desc):
+    """Forward on the four sets, the total loss and its parameter gradient (reverse mode on each
+    set with its seeds, summed).  Returns (terms dict, grad)."""
+    pts = np.asarray(points, np.float64)
+    sets = {"x": pts, "mx": mirror_points(pts, 1), "my": mirror_points(pts, 2), "ic": ic_points(ic_xy)}
+    fg = {k: simulate(circ, params, v) for k, v in sets.items()}
+    f, g = fg["x"]
+    terms = total_loss(f, g, fg["mx"][0], fg["my"][0], fg["ic"][0], pts, ic_xy, desc)
+    Vf, Wg, V_mx, V_my, V_ic = total_loss_seeds(f, g, fg["mx"][0], fg["my"][0], fg["ic"][0], pts, ic_xy, desc)
+    grad = grad_reverse(circ, params, sets["x"], Vf, Wg)
+    zero = lambda n: np.zeros((n, len(circ.out_qubits), 3))
+    grad += grad_reverse(circ, params, sets["my"], V_my, zero(len(pts)))
+    if desc.phys.kind == LOSS_VACUUM:
+        grad += grad_reverse(circ, params, sets["mx"], V_mx, zero(len(pts)))
+    if len(sets["ic"]):
+        grad += grad_reverse(circ, params, sets["ic"], V_ic, zero(len(sets["ic"])))
+    return terms, grad
+
+
 # --------------------------------------------------------------- gradients --------------------
 
 def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, chunk=None,

@@ -44,6 +44,11 @@ FAST_PINS = [
     ("crz_four_term_shift", pins.test_crz_gradient_matches_four_term_shift_rule, ()),
     ("input_grads_fd_ry", pins.test_input_gradients_match_fd, (W.ENC_RY,)),
     ("input_grads_shift_rx", pins.test_input_gradients_match_embedding_shift_rule, (W.ENC_RX,)),
+    ("energy_poynting_vac", pins.test_energy_residual_is_the_poynting_balance, (W.LOSS_VACUUM,)),
+    ("energy_poynting_diel", pins.test_energy_residual_is_the_poynting_balance, (W.LOSS_DIEL_SPLIT,)),
+    ("ic_closed_form", pins.test_ic_loss_closed_form, ()),
+    ("symmetry_parities", pins.test_symmetry_loss_parities, ()),
+    ("total_seeds_vac", pins.test_total_loss_seeds_are_its_gradient, (W.LOSS_VACUUM,)),
 ]
 
 _rotation = O.rotation
@@ -59,6 +64,10 @@ _grad_reverse = O.grad_reverse
 _encoding_angles = O.encoding_angles
 _scale_value = O.scale_value
 _embed_second_derivative = O._embed_second_derivative
+_energy_residual = O.energy_residual
+_sym_terms = O._sym_terms
+_ic_target = O.ic_target
+_total_loss_seeds = O.total_loss_seeds
 
 
 def rotation_sign(kind, theta):                       # exp(+i theta P / 2)
@@ -243,6 +252,28 @@ def input_grads_jac_half(*a):                       # d/dJ = Re <mu, t_q> (facto
     _input_grads_slipped(*a, j_factor=1.0)
 
 
+def energy_residual_y_flux_sign(f, g, points, desc):   # + d(E Hx)/dy taken with a minus sign
+    return _energy_residual(f, g, points, desc) - 2.0 * (g[:, 0, 2] * f[:, 1] + f[:, 0] * g[:, 1, 2])
+
+
+def energy_residual_no_eps(f, g, points, desc):        # eps dropped from the electric energy
+    eps = O._eps(points, desc)
+    return _energy_residual(f, g, points, desc) - (eps - 1.0) * f[:, 0] * g[:, 0, 0]
+
+
+def sym_terms_hx_even_in_y(f, f_mx, f_my, desc):       # (Hx - Hx^mirr_y)^2 instead of (Hx + ..)^2
+    return _sym_terms(f, f_mx, f_my, desc) - (f[:, 1] + f_my[:, 1]) ** 2 + (f[:, 1] - f_my[:, 1]) ** 2
+
+
+def ic_target_half_exponent(ic_xy, a):                 # exp(-a r^2 / 2)
+    return _ic_target(ic_xy, a / 2.0)
+
+
+def total_seeds_mirror_x_dropped(*a):                  # the x-mirror images get no seeds
+    Vf, Wg, V_mx, V_my, V_ic = _total_loss_seeds(*a)
+    return Vf, Wg, np.zeros_like(V_mx), V_my, V_ic
+
+
 MUTATIONS = [
     ("rotation", rotation_sign),
     ("rotation", rotation_full_angle),
@@ -270,6 +301,11 @@ MUTATIONS = [
     ("_embed_second_derivative", embed_second_derivative_sign),
     ("_input_grads", input_grads_cross_terms_dropped),
     ("_input_grads", input_grads_jac_half),
+    ("energy_residual", energy_residual_y_flux_sign),
+    ("energy_residual", energy_residual_no_eps),
+    ("_sym_terms", sym_terms_hx_even_in_y),
+    ("ic_target", ic_target_half_exponent),
+    ("total_loss_seeds", total_seeds_mirror_x_dropped),
 ]
 
 

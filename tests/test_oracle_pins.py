@@ -629,3 +629,137 @@ def test_input_gradients_of_the_maxwell_loss_match_fd():
             jp[p, q, c] += h
             jm[p, q, c] -= h
             assert abs((loss(th, jp) - loss(th, jm)) / (2 * h) - d_J[p, q, c]) < 1e-8
+
+
+# ------------------------------------------------------------ the paper's total loss -----------
+
+def _analytic_fields(pts, a=(1.3, -0.7, 0.4), b=(0.9, 1.1, -1.5)):
+    """Smooth fields that solve nothing: E = sin(k.p), Hx = cos(l.p), Hy = sin(k.p) cos(l.p), with
+    their exact derivatives (p = (t, x, y))."""
+    k, l = np.array(a), np.array(b)
+    sk, ck = np.sin(pts @ k), np.cos(pts @ k)
+    sl, cl = np.sin(pts @ l), np.cos(pts @ l)
+    f = np.stack([sk, cl, sk * cl], 1)
+    g = np.zeros((len(pts), 3, 3))
+    g[:, 0, :] = ck[:, None] * k
+    g[:, 1, :] = -sl[:, None] * l
+    g[:, 2, :] = (ck * cl)[:, None] * k - (sk * sl)[:, None] * l
+    return f, g
+
+
+@pytest.mark.parametrize("kind", [W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT])
+def test_energy_residual_is_the_poynting_balance(kind):
+    """e = du/dt + dSx/dx + dSy/dy with u = (eps E^2 + Hx^2 + Hy^2)/2, S = (-E Hy, E Hx) (the
+    Poynting theorem with J = 0), checked by central differences of u and S on analytic fields;
+    and the vacuum plane wave (E, Hx, Hy) = (F(x - t), 0, -F(x - t)) has e = 0."""
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(-1, 1, (16, 3))
+    desc = W.MaxwellDesc(kind, 4.0, 0.0)
+    f, g = _analytic_fields(pts)
+    e = O.energy_residual(f, g, pts, desc)
+    eps = np.where(pts[:, 1] >= 0, 4.0, 1.0) if kind != W.LOSS_VACUUM else np.ones(16)
+
+    def u_s(p):
+        ff, _ = _analytic_fields(p)
+        return 0.5 * (eps * ff[:, 0] ** 2 + ff[:, 1] ** 2 + ff[:, 2] ** 2), -ff[:, 0] * ff[:, 2], ff[:, 0] * ff[:, 1]
+    h = 1e-5
+    fd = np.zeros(16)
+    for c, comp in ((0, 0), (1, 1), (2, 2)):
+        pp, pm = pts.copy(), pts.copy()
+        pp[:, c] += h
+        pm[:, c] -= h
+        fd += (u_s(pp)[comp] - u_s(pm)[comp]) / (2 * h)
+    np.testing.assert_allclose(e, fd, atol=1e-8)
+    F, Fp = np.sin(3 * (pts[:, 1] - pts[:, 0])), 3 * np.cos(3 * (pts[:, 1] - pts[:, 0]))
+    fw = np.stack([F, np.zeros(16), -F], 1)
+    gw = np.zeros((16, 3, 3))
+    gw[:, 0, 0], gw[:, 0, 1] = -Fp, Fp
+    gw[:, 2, 0], gw[:, 2, 1] = Fp, -Fp
+    assert np.abs(O.energy_residual(fw, gw, pts, W.MaxwellDesc())).max() < 1e-14
+
+
+def test_ic_loss_closed_form():
+    """At the IC plane the target is E_0 = exp(-25 (x^2 + y^2)), H = 0 (eqs. pulse_IC_*): the exact
+    pulse gives L_IC = 0, and constant offsets (d, h1, h2) give d^2 + h1^2 + h2^2."""
+    rng = np.random.default_rng(12)
+    xy = rng.uniform(-1, 1, (32, 2))
+    E0 = np.exp(-25 * (xy[:, 0] ** 2 + xy[:, 1] ** 2))
+    desc = W.TotalLossDesc()
+    z = np.zeros((4, 3)), np.zeros((4, 3, 3))
+    pts = rng.uniform(-1, 1, (4, 3))
+    f_ic = np.stack([E0, np.zeros(32), np.zeros(32)], 1)
+    assert O.total_loss(z[0], z[1], z[0], z[0], f_ic, pts, xy, desc)["ic"] < 1e-30
+    f_ic = np.stack([E0 + 0.1, np.full(32, 0.2), np.full(32, -0.3)], 1)
+    assert O.total_loss(z[0], z[1], z[0], z[0], f_ic, pts, xy, desc)["ic"] == pytest.approx(0.14, rel=1e-12)
+
+
+def test_symmetry_loss_parities():
+    """Fields with the parities of eq. 2D_symLoss (E even in x and y, Hx even in x and odd in y,
+    Hy odd in x and even in y) give L_sym = 0; adding c x to E breaks only the x-mirror parity:
+    L_sym = mean((2 c x)^2) for the vacuum and 0 for the dielectric (x-mirror terms left out)."""
+    rng = np.random.default_rng(13)
+    pts = rng.uniform(-1, 1, (40, 3))
+
+    def fields(p, c=0.0):
+        t, x, y = p[:, 0], p[:, 1], p[:, 2]
+        return np.stack([np.cos(2 * x) * np.cos(3 * y) * np.exp(-t) + c * x, np.cos(x) * np.sin(2 * y) * t,
+                         np.sin(3 * x) * np.cos(y) + t * x], 1)
+    mx, my = O.mirror_points(pts, 1), O.mirror_points(pts, 2)
+    g = np.zeros((40, 3, 3))
+    f_ic = np.zeros((0, 3))
+    for kind in (W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT):
+        d = W.TotalLossDesc(phys=W.MaxwellDesc(kind))
+        assert O.total_loss(fields(pts), g, fields(mx), fields(my), f_ic, pts, np.zeros((0, 2)), d)["sym"] < 1e-28
+    c = 0.3
+    t = O.total_loss(fields(pts, c), g, fields(mx, c), fields(my, c), f_ic, pts, np.zeros((0, 2)), W.TotalLossDesc())
+    assert t["sym"] == pytest.approx(np.mean((2 * c * pts[:, 1]) ** 2), rel=1e-12)
+    d = W.TotalLossDesc(phys=W.MaxwellDesc(W.LOSS_DIEL_SPLIT))
+    assert O.total_loss(fields(pts, c), g, fields(mx, c), fields(my, c), f_ic, pts, np.zeros((0, 2)), d)["sym"] < 1e-28
+
+
+@pytest.mark.parametrize("kind", [W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT])
+def test_total_loss_seeds_are_its_gradient(kind):
+    rng = np.random.default_rng(14)
+    P, P0 = 6, 5
+    pts = rng.uniform(-1, 1, (P, 3))
+    xy = rng.uniform(-1, 1, (P0, 2))
+    arrs = [rng.standard_normal((P, 4)), rng.standard_normal((P, 4, 3)), rng.standard_normal((P, 4)),
+            rng.standard_normal((P, 4)), rng.standard_normal((P0, 4))]
+    desc = W.TotalLossDesc(phys=W.MaxwellDesc(kind, 4.0, 0.0), w_ic=3.0, w_sym=5.0, w_energy=7.0)
+    seeds = O.total_loss_seeds(*arrs, pts, xy, desc)
+    order = [0, 1, 2, 3, 4]
+    seed_of = {0: seeds[0], 1: seeds[1], 2: seeds[2], 3: seeds[3], 4: seeds[4]}
+    h = 1e-6
+    for a in order:
+        for idx in np.ndindex(*arrs[a].shape):
+            pp = [x.copy() for x in arrs]
+            pm = [x.copy() for x in arrs]
+            pp[a][idx] += h
+            pm[a][idx] -= h
+            fd = (O.total_loss(*pp, pts, xy, desc)["total"] - O.total_loss(*pm, pts, xy, desc)["total"]) / (2 * h)
+            assert fd == pytest.approx(seed_of[a][idx], abs=1e-7), (a, idx)
+
+
+def test_total_loss_gradient_matches_fd():
+    """Reverse mode over the four point sets with the total-loss seeds against central finite
+    differences of L_tot in the parameters (forward simulations only)."""
+    w = W.config(1, P=5)
+    circ = W.layered(4, 2, "xyz", lambda l: W.ring(4, W.CNOT, 1))
+    rng = np.random.default_rng(15)
+    params = rng.uniform(0, 2 * math.pi, circ.n_params)
+    xy = rng.uniform(-1, 1, (4, 2))
+    for kind in (W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT):
+        desc = W.TotalLossDesc(phys=W.MaxwellDesc(kind, 4.0, 0.0))
+
+        def L(prm):
+            sets = [O.simulate(circ, prm, p)[0] for p in (O.mirror_points(w.points, 1), O.mirror_points(w.points, 2),
+                                                          O.ic_points(xy))]
+            f, g = O.simulate(circ, prm, w.points)
+            return O.total_loss(f, g, sets[0], sets[1], sets[2], w.points, xy, desc)["total"]
+        _, grad = O.total_eval(circ, params, w.points, xy, desc)
+        h = 1e-6
+        for k in (0, 5, 11, 17, 23):
+            pp, pm = params.copy(), params.copy()
+            pp[k] += h
+            pm[k] -= h
+            assert (L(pp) - L(pm)) / (2 * h) == pytest.approx(grad[k], rel=1e-8, abs=1e-8), (kind, k)

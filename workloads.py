@@ -82,6 +82,22 @@ class MaxwellDesc:
 
 
 @dataclass
+class TotalLossDesc:
+    """The paper's total loss (eq. 2D_lossTot): L_phys + w_ic L_IC + w_sym L_sym + w_energy L_energy.
+
+    phys   : the residual loss (vacuum or dielectric) of the collocation points;
+    ic_a   : initial E_z pulse exp(-ic_a (x^2 + y^2)) at t = 0, H = 0 (eqs. pulse_IC_*, IC_loss);
+    L_sym  : mirrored-point parity penalty (eq. 2D_symLoss); the x-mirror terms are left out for
+             the dielectric losses (the dielectric breaks that symmetry);
+    L_energy: mean square of the local Poynting residual (eq. energy_loss)."""
+    phys: MaxwellDesc = field(default_factory=MaxwellDesc)
+    w_ic: float = 10.0
+    w_sym: float = 10.0
+    w_energy: float = 10.0
+    ic_a: float = 25.0
+
+
+@dataclass
 class Workload:
     name: str
     circuit: Circuit
@@ -180,6 +196,11 @@ def _rngs(k: int, count: int):
 
 def uniform_points(rng, P: int, dtype=np.float32) -> np.ndarray:
     return rng.uniform(-1.0, 1.0, size=(P, 3)).astype(dtype)
+
+
+def ic_plane_points(rng, N: int, dtype=np.float32) -> np.ndarray:
+    """(x, y) of initial-condition points, uniform in [-1, 1]^2 (the paper uses a 64 x 64 plane)."""
+    return rng.uniform(-1.0, 1.0, size=(N, 2)).astype(dtype)
 
 
 def uniform_params(rng, K: int, dtype=np.float32) -> np.ndarray:
