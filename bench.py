@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="points of the CPU oracle sample (default: two chunks per core at 12 qubits)")
     ap.add_argument("--no-c1", action="store_true", help="skip the plain FP64 4-qubit wall-time leg")
+    ap.add_argument("--no-total", action="store_true", help="skip the paper's total-loss leg")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
@@ -473,6 +474,31 @@ def main():
                            "the PQC, autograd input derivatives, all loss terms, backward, Adam) on NVIDIA L40S or "
                            "A100, precision not stated; context only"}
         log(f"bench: paper context {line['paper_context']['ours_evals_per_s']}")
+
+    if w is not None and not args.no_total:
+        # The paper's total loss (residuals + 10 IC + 10 symmetry + 10 energy) on the same points and a
+        # 4096-point initial-condition plane: forward over [X; mirror images; IC plane], seeds, adjoint.
+        xy = W.ic_plane_points(np.random.default_rng(77), 4096)
+        tdesc = W.TotalLossDesc(phys=w.loss)
+        c.total_loss(prm, pts, xy, tdesc)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r_tot = c.total_loss(prm, pts, xy, tdesc)
+        torch.cuda.synchronize()
+        t_tot = (time.perf_counter() - t0) / reps
+        terms = r_tot["terms"].cpu().numpy()
+        n_sets = 3 if w.loss.kind == W.LOSS_VACUUM else 2
+        line["total_loss"] = {
+            "what": "L_phys + 10 L_IC + 10 L_sym + 10 L_energy: fused forward with tangents over the collocation "
+                    f"points, their {n_sets - 1} mirror image set(s) and a 4096-point IC plane, seeds, fused adjoint",
+            "points": P_total, "ic_points": 4096, "ms_per_step": round(t_tot * 1e3, 3),
+            "collocation_evals_per_s": round(P_total / t_tot, 1),
+            "relative_to_residual_only_step": round(t_tot / (ms_per_step / 1e3), 3),
+            "terms": {"total": float(terms[0]), "phys": float(terms[1]), "ic": float(terms[2]),
+                      "sym": float(terms[3]), "energy": float(terms[4])}}
+        log(f"bench: total loss {line['total_loss']}")
 
     if k == 4 and not args.no_c1:
         line["c1_plain_fp64"] = c1_plain_fp64(ctx, dev)

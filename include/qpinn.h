@@ -194,6 +194,35 @@ qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params
                            double* loss, float* d_params, float* d_angles, float* d_jac, void* ws,
                            size_t ws_bytes, uint32_t flags);
 
+/* ---- the paper's total loss -------------------------------------------------------------
+ * L_tot = L_phys + w_ic L_IC + w_sym L_sym + w_energy L_energy (eq. 2D_lossTot; the paper's
+ * weights are 10, 10, 10) with
+ *   L_phys   the residual loss of the collocation points X (as qp_maxwell_fused, means),
+ *   L_IC     mean over the initial-condition plane X_0 = {(0, x, y)} of (E_z - E_0)^2 + H_x^2 +
+ *            H_y^2, E_0 = exp(-ic_a (x^2 + y^2)) (eqs. pulse_IC_Ez, pulse_IC_Hx, pulse_IC_Hy,
+ *            IC_loss; ic_a = 25),
+ *   L_sym    mean over X of the parity defects of eq. 2D_symLoss, evaluated at the mirror images
+ *            (t, -x, y) and (t, x, -y); the x-mirror terms are left out for the dielectric losses,
+ *   L_energy mean over X of the squared local Poynting residual
+ *            eps E dE/dt + Hx dHx/dt + Hy dHy/dt - (dE/dx Hy + E dHy/dx) + (dE/dy Hx + E dHx/dy)
+ *            (eqs. Poynting_thm, Poynting_value_u, Poynting_value_S, energy_loss).
+ * The mirror images couple points, so the call runs three stream-ordered phases over the set
+ * [X; X_my; X_mx (vacuum); X_0]: forward with tangents, per-point loss terms and seeds, adjoint
+ * VJP.  points [P][3] (t, x, y) and ic_xy [P0][2] (x, y) are device buffers; out [P][m] and tan
+ * [P][m][3] (of X, may be NULL); loss_terms: device double [5] = total, phys, IC, sym, energy;
+ * d_params [K].  Point encodings only (cycled or random Fourier features): QP_EINVAL for the
+ * angle-given encoding.  Flags: only QP_FLAG_GATES_FP32 (others: QP_EUNSUPPORTED).          */
+typedef struct qp_total_loss_desc {
+  qp_maxwell_desc phys;
+  float w_ic, w_sym, w_energy;    /* weights of eq. 2D_lossTot (10, 10, 10)                 */
+  float ic_a;                     /* initial pulse exp(-ic_a (x^2 + y^2)) (25)              */
+} qp_total_loss_desc;
+size_t qp_total_workspace_bytes(const qp_circuit* c, int64_t P, int64_t P0, int32_t phys_kind);
+qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                        int64_t P, const float* ic_xy, int64_t P0, const qp_total_loss_desc* desc,
+                        float* out, float* tan, double* loss_terms, float* d_params, void* ws,
+                        size_t ws_bytes, uint32_t flags);
+
 /* ---- fused Maxwell evaluation without allocation ---------------------------------------
  * For callers that cannot allocate device memory or pass a workspace: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, checks and

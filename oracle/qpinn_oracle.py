@@ -396,7 +396,7 @@ def total_loss(f, g, f_mx, f_my, f_ic, points, ic_xy, desc):
     mean over X of the squared Poynting residual (the paper prints the residual; it is squared and
     averaged here like every other residual)."""
     P = f.shape[0]
-    phys = maxwell_loss(g, points, desc.phys)
+    phys = maxwell_loss(g, points, desc.phys) if P else 0.0
     E0 = ic_target(ic_xy, desc.ic_a)
     ic = float(np.mean((f_ic[:, 0] - E0) ** 2 + f_ic[:, 1] ** 2 + f_ic[:, 2] ** 2)) if len(E0) else 0.0
     sym = float(np.mean(_sym_terms(f, f_mx, f_my, desc))) if P else 0.0
@@ -411,7 +411,7 @@ def total_loss_seeds(f, g, f_mx, f_my, f_ic, points, ic_xy, desc):
     outputs (E_z, H_x, H_y) carry seeds."""
     P, m = f.shape
     Vf = np.zeros((P, m))
-    Wg = maxwell_seeds(g, points, desc.phys)
+    Wg = maxwell_seeds(g, points, desc.phys) if P else np.zeros((0, m, 3))
     V_mx = np.zeros((P, m))
     V_my = np.zeros((P, m))
     # energy: w_energy * mean(e^2)

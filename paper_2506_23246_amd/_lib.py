@@ -38,6 +38,11 @@ class qp_maxwell_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("eps_r", C.c_float), ("x_interface", C.c_float)]
 
 
+class qp_total_loss_desc(C.Structure):
+    _fields_ = [("phys", qp_maxwell_desc), ("w_ic", C.c_float), ("w_sym", C.c_float), ("w_energy", C.c_float),
+                ("ic_a", C.c_float)]
+
+
 class qp_batch_io(C.Structure):
     _fields_ = [("params", C.c_void_p), ("points", C.c_void_p), ("out", C.c_void_p), ("tan", C.c_void_p),
                 ("loss", C.c_void_p), ("d_params", C.c_void_p)]
@@ -64,6 +69,9 @@ _SIGS = {
     "qp_vjp": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, _P, _P, _P, C.c_size_t, C.c_uint32]),
     "qp_maxwell_fused": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(qp_maxwell_desc), _P, _P, _P,
                                    _P, _P, _P, _P, C.c_size_t, C.c_uint32]),
+    "qp_total_workspace_bytes": (C.c_size_t, [_P, C.c_int64, C.c_int64, C.c_int32]),
+    "qp_total_loss": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(qp_total_loss_desc), _P, _P,
+                                _P, _P, _P, C.c_size_t, C.c_uint32]),
     "qp_noalloc_scratch_bytes": (C.c_size_t, []),
     "qp_maxwell_fused_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(qp_maxwell_desc), _P, _P,
                                            _P, _P, _P, _P, C.c_uint32]),

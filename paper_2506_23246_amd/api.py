@@ -214,6 +214,30 @@ class Circuit:
                                            _ptr(bufs["grad"]), None, None, flags), self.ctx.h)
         return bufs
 
+    def total_loss(self, params, points, ic_xy, desc, outputs=False, flags=0):
+        """The paper's total loss (qp_total_loss): returns dict(terms (float64 [5]: total, phys, ic,
+        sym, energy), grad (float32 [K]), and out/tan of the collocation points if outputs)."""
+        dev = self.ctx.dev
+        prm, pts = _f32(params, dev), _f32(points, dev)
+        xy = _f32(ic_xy, dev)
+        P, P0 = int(pts.shape[0]), int(xy.shape[0])
+        r = {"terms": torch.empty(5, dtype=torch.float64, device=dev),
+             "grad": torch.empty(self.K, dtype=torch.float32, device=dev),
+             "out": torch.empty((P, self.m), dtype=torch.float32, device=dev) if outputs else None,
+             "tan": torch.empty((P, self.m, 3), dtype=torch.float32, device=dev) if outputs else None}
+        phys = desc.phys
+        d = L.qp_total_loss_desc(maxwell_desc(phys), float(desc.w_ic), float(desc.w_sym), float(desc.w_energy),
+                                 float(desc.ic_a))
+        nb = int(L.qp_total_workspace_bytes(self.h, P, P0, int(phys.kind)))
+        key = ("total", nb)
+        if key not in self._ws:
+            self._ws[key] = _aligned_bytes(nb, dev)
+        _, wp, _ = self._ws[key]
+        L.check(L.qp_total_loss(self.ctx.h, self.h, _ptr(prm), _ptr(pts), P, _ptr(xy), P0, C.byref(d),
+                                _ptr(r["out"]), _ptr(r["tan"]), _ptr(r["terms"]), _ptr(r["grad"]), wp, nb, flags),
+                self.ctx.h)
+        return r
+
     # ---- plain baseline -------------------------------------------------------------------
     def plain_workspace(self, P, precision):
         nb = int(L.qp_plain_workspace_bytes(self.h, int(P), int(precision)))

@@ -16,6 +16,7 @@
 #include "fused.hpp"
 #include "plain.hpp"
 #include "plan.hpp"
+#include "total.hpp"
 #include "tune.hpp"
 
 using namespace qp;
@@ -477,6 +478,94 @@ extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const fl
                                       float* d_jac, void* ws, size_t ws_bytes, uint32_t flags) {
   return maxwell_entry(ctx, c, params, points, angles, jac, P, ld, out, tan, loss, d_params, d_angles, d_jac, ws,
                        ws_bytes, flags, "qp_maxwell_fused");
+}
+
+// ---------------------------------------------------------------- total loss ----------------
+namespace {
+struct TotalLayout { size_t ext, out, tan, dout, dtan, part, counts, fused, total; int64_t P_ext, ic_base; int with_mx; };
+
+TotalLayout total_layout(const qp_circuit* c, int64_t P, int64_t P0, int phys_kind) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  TotalLayout L{};
+  L.with_mx = phys_kind == QP_LOSS_VACUUM ? 1 : 0;
+  L.ic_base = P * (L.with_mx ? 3 : 2);
+  L.P_ext = L.ic_base + P0;
+  const size_t m = (size_t)c->hp.m, Pe = (size_t)L.P_ext;
+  size_t off = 0;
+  L.ext = off; off = al(off + sizeof(float) * 3 * Pe);
+  L.out = off; off = al(off + sizeof(float) * m * Pe);
+  L.tan = off; off = al(off + sizeof(float) * 3 * m * Pe);
+  L.dout = off; off = al(off + sizeof(float) * m * Pe);
+  L.dtan = off; off = al(off + sizeof(float) * 3 * m * Pe);
+  L.part = off; off = al(off + sizeof(float) * 4 * (size_t)std::max(1, total_seed_blocks(P, P0)));
+  L.counts = off; off = al(off + 2 * sizeof(int));
+  L.fused = off; off = al(off + fused_layout(c, L.P_ext, c->ctx->cu_count * 4).total);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t qp_total_workspace_bytes(const qp_circuit* c, int64_t P, int64_t P0, int32_t phys_kind) {
+  if (!c || P < 0 || P0 < 0) return 0;
+  return total_layout(c, P, P0, phys_kind).total;
+}
+
+extern "C" qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
+                                   int64_t P, const float* ic_xy, int64_t P0, const qp_total_loss_desc* d,
+                                   float* out, float* tan, double* loss_terms, float* d_params, void* ws,
+                                   size_t ws_bytes, uint32_t flags) {
+  const char* who = "qp_total_loss";
+  if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
+  if (!d) return fail(ctx, QP_EINVAL, "%s: loss descriptor is null", who);
+  const int kind = d->phys.kind;
+  if (kind < QP_LOSS_VACUUM || kind > QP_LOSS_DIEL_INTUITIVE) return fail(ctx, QP_EINVAL, "%s: unknown loss kind", who);
+  if (P < 0 || P0 < 0) return fail(ctx, QP_EINVAL, "%s: P < 0 or P0 < 0", who);
+  if (c->hp.enc_kind == QP_ENC_ANGLES)
+    return fail(ctx, QP_EINVAL, "%s: the mirrored and initial-condition points need a point encoding", who);
+  if (!c->hp.fused_ok) return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
+  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "%s: the loss needs 3 outputs (E_z, H_x, H_y)", who);
+  if (flags & (QP_FLAG_DENSE_MFMA | QP_FLAG_LOSS_SUM | QP_FLAG_TUNE))
+    return fail(ctx, QP_EUNSUPPORTED, "%s: flags other than QP_FLAG_GATES_FP32 are not supported", who);
+  const TotalLayout L = total_layout(c, P, P0, kind);
+  if (L.P_ext > (int64_t)INT32_MAX) return fail(ctx, QP_EUNSUPPORTED, "%s: too many points for one call", who);
+  if ((c->hp.K > 0 && (!params || !d_params)) || (P > 0 && !points) || (P0 > 0 && !ic_xy) || !loss_terms)
+    return fail(ctx, QP_EINVAL, "%s: null pointer argument", who);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or misaligned", who);
+  if (ws_bytes < L.total) return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, L.total);
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  char* w = static_cast<char*>(ws);
+  float* ext = reinterpret_cast<float*>(w + L.ext);
+  float* fo = reinterpret_cast<float*>(w + L.out);
+  float* fg = reinterpret_cast<float*>(w + L.tan);
+  float* dout = reinterpret_cast<float*>(w + L.dout);
+  float* dtan = reinterpret_cast<float*>(w + L.dtan);
+  int* counts = reinterpret_cast<int*>(w + L.counts);
+  void* fws = w + L.fused;
+  const uint32_t gflags = flags & QP_FLAG_GATES_FP32;
+  hipError_t e = launch_total_points(points, P, ic_xy, P0, L.with_mx, ext, st);
+  if (e != hipSuccess) return hipcheck(ctx, e, "total-loss points");
+  if (kind == QP_LOSS_DIEL_SPLIT && (e = launch_count(points, P, d->phys.x_interface, counts, st)) != hipSuccess)
+    return hipcheck(ctx, e, "count");
+  qp_status s = run_fused(ctx, c, kModeFwd, params, ext, nullptr, nullptr, L.P_ext, nullptr, fo, fg, nullptr, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, fws, gflags, 0, 0);
+  if (s != QP_OK) return s;
+  TotalSeedArgs a{};
+  a.out = fo; a.tan = fg; a.points = points; a.ic_xy = ic_xy;
+  a.P = P; a.P0 = P0; a.ic_base = L.ic_base; a.m = c->hp.m; a.with_mx = L.with_mx;
+  a.phys_kind = kind; a.eps_r = d->phys.eps_r; a.x_if = d->phys.x_interface; a.counts = counts;
+  a.w_ic = d->w_ic; a.w_sym = d->w_sym; a.w_energy = d->w_energy; a.ic_a = d->ic_a;
+  a.d_out = dout; a.d_tan = dtan;
+  a.part = reinterpret_cast<float*>(w + L.part);
+  a.terms = loss_terms;
+  if ((e = launch_total_seeds(a, st)) != hipSuccess) return hipcheck(ctx, e, "total-loss seeds");
+  if (out && P > 0 && (e = hipMemcpyAsync(out, fo, sizeof(float) * c->hp.m * P, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hipcheck(ctx, e, "copy outputs");
+  if (tan && P > 0 && (e = hipMemcpyAsync(tan, fg, sizeof(float) * 3 * c->hp.m * P, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hipcheck(ctx, e, "copy tangents");
+  if (c->hp.K == 0) return QP_OK;
+  return run_fused(ctx, c, kModeVjp, params, ext, nullptr, nullptr, L.P_ext, nullptr, nullptr, nullptr, dout, dtan,
+                   nullptr, d_params, nullptr, nullptr, fws, gflags, 0, 0);
 }
 
 // ---------------------------------------------------------------- plain ---------------------
