@@ -465,10 +465,30 @@ def main():
             torch.cuda.synchronize()
             ours[f"{side}^3"] = round(Pc / ((time.perf_counter() - t0) / 5), 1)
             del ang, jac
+        # the paper's other ansatz families at the 40^3 grid (angle gradients included, as the hybrid model needs)
+        per_ansatz = {}
+        Pc = 40 ** 3
+        ang = torch.tensor(rng.uniform(0.0, math.pi, (Pc, 7)).astype(np.float32), device=dev)
+        jac = torch.tensor(rng.standard_normal((Pc, 7, 3)).astype(np.float32), device=dev)
+        for name in ("basic", "strong", "noent", "cross_mesh", "cross_mesh_2rot", "cross_mesh_cnot"):
+            pa = W.paper_context_circuit(name)
+            ca = Circuit(ctx, pa)
+            pr = torch.tensor(rng.uniform(0, 2 * math.pi, pa.n_params).astype(np.float32), device=dev)
+            ca.maxwell(pr, None, W.MaxwellDesc(), angles=ang, jac=jac, input_grads=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ca.maxwell(pr, None, W.MaxwellDesc(), angles=ang, jac=jac, input_grads=True)
+            torch.cuda.synchronize()
+            per_ansatz[name] = {"quantum_params": pa.n_params,
+                                "evals_per_s": round(Pc / ((time.perf_counter() - t0) / 5), 1)}
+            ca.close()
+        del ang, jac
         line["paper_context"] = {
             "what": "the paper's circuit shape: 7 qubits x 4 layers, Rot + CNOT ring, RX(acos) embedding of given "
                     "angles, fused forward + 3 input tangents + Maxwell loss + adjoint gradient",
             "ours_evals_per_s": ours,
+            "ansatz_families_40cubed_with_angle_gradients": per_ansatz,
             "paper_torq_points_per_s": {"40^3": 4.41e5, "87^3": 7.75e5},
             "paper_scope": "grid^3 / seconds per training epoch of the whole hybrid model (66848-parameter MLP, "
                            "the PQC, autograd input derivatives, all loss terms, backward, Adam) on NVIDIA L40S or "

@@ -67,7 +67,7 @@ template <int N>
 __device__ __forceinline__ void batch_tiles(const BatchCirc& C, const BatchItem& it, float2* buf, float* slots,
                                             float* red, float& lacc) {
   for (int t = it.tile0; t < it.tile0 + it.ntile; ++t)
-    fused_tile<N, kBT, kBEXS, kModeMaxwell>(C.a, t, buf, slots, red, lacc);
+    fused_tile<N, kBT, kBEXS, kModeMaxwell>(C.a, t, buf, slots, nullptr, red, lacc);
 }
 
 __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ circs, const BatchItem* __restrict__ items,

@@ -34,6 +34,7 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
     if (c->hp.n > 11) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: batch supports n <= 11", i));
     if (c->hp.m < 3) return cleanup(fail(ctx, QP_ESHAPE, "qp_batch_compile: circuit %d needs 3 outputs", i));
     if (c->hp.enc_kind == QP_ENC_RFF) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: RFF encoding not batched", i));
+    if (!c->hp.phases.empty()) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: CRZ stages not batched", i));
     b->P.push_back(P[i]);
     b->max_fused = std::max(b->max_fused, (int)c->hp.fused.size());
   }
@@ -210,6 +211,9 @@ static qp_status batch_bind(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io, con
     a.counts = reinterpret_cast<int*>(w + L.counts_c[i]);
     a.mpart = nullptr;
     a.lpart = nullptr;
+    a.d_angles = nullptr;
+    a.d_jac = nullptr;
+    a.n_mom = 0;   // no phase stages in a batch
     C.params = o.params;
     C.loss = o.loss;
     C.d_params = o.d_params;

@@ -144,7 +144,9 @@ extern "C" qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_plane
   if (exchange_planes != 2 && exchange_planes != 4)
     return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: exchange_planes must be 2 or 4");
   const int max_wg = fused_max_wg_per_cu(c->hp.n);
-  const size_t lds = fused_lds_bytes(c->hp.n, exchange_planes, (int)c->hp.fused.size());
+  if (exchange_planes == 4 && !c->hp.phases.empty())
+    return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: circuits with CRZ phase stages run with 2 exchange planes");
+  const size_t lds = fused_lds_bytes(c->hp.n, exchange_planes, (int)c->hp.fused.size(), n_moments(c));
   if (wg_per_cu < 1 || wg_per_cu > max_wg || lds * (size_t)wg_per_cu > 160 * 1024)
     return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: %d workgroups of %zu LDS bytes do not fit a CU", wg_per_cu, lds);
   c->exs = exchange_planes;
@@ -205,17 +207,20 @@ void qp::choose_launch(qp_ctx* ctx, qp_circuit* c) {
   const size_t lds_cap = 160 * 1024;
   const int T = fused_threads(n);
   const int max_wg_vgpr = (T == 512) ? 1 : 2;   // ~256 VGPRs per lane: 2 waves per SIMD
+  const int NM = n_moments(c);
   c->exs = 4;
-  size_t lds = fused_lds_bytes(n, 4, F);
-  if (lds * max_wg_vgpr > lds_cap) {
+  size_t lds = fused_lds_bytes(n, 4, F, NM);
+  if (lds * max_wg_vgpr > lds_cap || NM > 0) {   // phase stages are applied by the unpipelined kernel
     c->exs = 2;
-    lds = fused_lds_bytes(n, 2, F);
+    lds = fused_lds_bytes(n, 2, F, NM);
   }
   int wg = (int)std::min<size_t>(max_wg_vgpr, lds_cap / std::max<size_t>(lds, 1));
   c->wg_per_cu = std::max(wg, 1);
   const TuneEntry* te = tune_lookup(ctx, c);
-  if (te) { c->exs = te->exs; c->wg_per_cu = te->wg_per_cu; }
+  if (te && !(NM > 0 && te->exs == 4)) { c->exs = te->exs; c->wg_per_cu = te->wg_per_cu; }
 }
+
+int qp::n_moments(const qp_circuit* c) { return (int)c->hp.phases.size() * phase_terms(c->hp.n); }
 
 int qp::fused_grid(const qp_ctx* ctx, const qp_circuit* c, int64_t P) {
   const int ppw = fused_points_per_tile(c->hp.n);
@@ -228,16 +233,17 @@ WsLayout qp::fused_layout(const qp_circuit* c, int64_t P, int grid_cap) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   WsLayout L{};
   const int F = (int)c->hp.fused.size();
+  const int NM = n_moments(c);
   size_t off = 0;
-  L.gtab = off; off = al(off + sizeof(float) * kGT * (F + 1));   // + identity entry
+  L.gtab = off; off = al(off + sizeof(float) * kGT * (F + 1) + sizeof(uint32_t) * NM);   // + identity, phases
   L.counts = off; off = al(off + 2 * sizeof(int));
   if (c->hp.enc_kind == QP_ENC_RFF) {
     L.angles = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n);
     L.jac = off; off = al(off + sizeof(float) * (size_t)P * c->hp.n * 3);
   }
-  L.mpart = off; off = al(off + sizeof(float) * (size_t)grid_cap * F * kGS);
+  L.mpart = off; off = al(off + sizeof(float) * (size_t)grid_cap * (F * kGS + NM));
   L.lpart = off; off = al(off + sizeof(float) * (size_t)std::max(grid_cap, 1));
-  L.m64 = off; off = al(off + sizeof(double) * (size_t)std::max(F, 1) * kGS);
+  L.m64 = off; off = al(off + sizeof(double) * ((size_t)std::max(F, 1) * kGS + NM));
   L.total = off;
   return L;
 }
@@ -355,7 +361,8 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   char* w = static_cast<char*>(ws);
   float* gtab = reinterpret_cast<float*>(w + L.gtab);
   int* counts = reinterpret_cast<int*>(w + L.counts);
-  hipError_t e = launch_gate_table(c->dplan, F, params, gtab, (flags & QP_FLAG_GATES_FP32) ? 1 : 0, st);
+  const int NM = n_moments(c);
+  hipError_t e = launch_gate_table(c->dplan, F, NM, params, gtab, (flags & QP_FLAG_GATES_FP32) ? 1 : 0, st);
   if (e != hipSuccess) return hipcheck(ctx, e, "gate table");
   const float* ang = angles;
   const float* jc = jac;
@@ -371,8 +378,8 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   int grid = fused_grid(ctx, c, P);
   if (grid_override > 0) grid = (int)std::min<int64_t>(grid_override, (P + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
   grid = std::min(grid, cap);
-  const int exs = exs_override > 0 ? exs_override : c->exs;
-  const size_t lds = fused_lds_bytes(n, exs, F);
+  const int exs = NM > 0 ? 2 : (exs_override > 0 ? exs_override : c->exs);   // phases: unpipelined kernel
+  const size_t lds = fused_lds_bytes(n, exs, F, NM);
   FusedArgs a{};
   a.plan = c->dplan;
   a.gtab = gtab;
@@ -393,6 +400,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.counts = counts;
   a.mpart = reinterpret_cast<float*>(w + L.mpart);
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
+  a.n_mom = NM;
   a.d_angles = mode == kModeFwd ? nullptr : d_angles;
   a.d_jac = mode == kModeFwd ? nullptr : d_jac;
   if (grid > 0) {
@@ -402,7 +410,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   }
   if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
   double* m64 = reinterpret_cast<double*>(w + L.m64);
-  if ((e = launch_reduce(a.mpart, grid, F * kGS, mode == kModeMaxwell ? a.lpart : nullptr, m64,
+  if ((e = launch_reduce(a.mpart, grid, F * kGS + NM, mode == kModeMaxwell ? a.lpart : nullptr, m64,
                          mode == kModeMaxwell ? loss : nullptr, st)) != hipSuccess)
     return hipcheck(ctx, e, "reduce");
   if (d_params && (e = launch_param_grads(c->dplan, c->hp.K, params, m64, d_params, st)) != hipSuccess)

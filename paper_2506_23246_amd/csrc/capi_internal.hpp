@@ -41,6 +41,7 @@ qp_status hipcheck(qp_ctx* c, hipError_t e, const char* what);
 void choose_launch(qp_ctx* ctx, qp_circuit* c);
 int fused_grid(const qp_ctx* ctx, const qp_circuit* c, int64_t P);
 WsLayout fused_layout(const qp_circuit* c, int64_t P, int grid_cap);
+int n_moments(const qp_circuit* c);   // phase-stage moments of the fused adjoint (0 without CRZ)
 qp_status run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                     const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                     float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,

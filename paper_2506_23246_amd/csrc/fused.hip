@@ -93,6 +93,39 @@ __global__ void k_gate_table(const QPlanDev* __restrict__ plan, const float* __r
   store_gate_entry(gtab + f * kGT, u);
 }
 
+// Phase-stage coefficients in 32-bit fractions of a turn (one thread per coefficient):
+// alpha_q = -(1/2) sum_t theta_qt, beta_qq' = theta_qq' + theta_q'q (see QPhaseStage).  Like the
+// gate table this is O(K) work per call and runs in FP64; the result is reduced modulo one turn.
+__global__ void k_phase_table(const QPlanDev* __restrict__ plan, const float* __restrict__ params,
+                              uint32_t* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = plan->n, nt = phase_terms(n);
+  if (i >= plan->n_phase * nt) return;
+  const char* pb = reinterpret_cast<const char*>(plan);
+  const QPhaseStage& st = reinterpret_cast<const QPhaseStage*>(pb + plan->off_phase)[i / nt];
+  const QPhaseGate* gates = reinterpret_cast<const QPhaseGate*>(pb + plan->off_phase_gates) + st.gate0;
+  const int e = i % nt;
+  int qa = e, qb = -1;   // alpha_qa, or beta of the pair (qa, qb)
+  if (e >= n) {
+    int r = e - n;
+    qa = 0;
+    while (r >= n - 1 - qa) { r -= n - 1 - qa; ++qa; }
+    qb = qa + 1 + r;
+  }
+  double turns = 0.0;
+  const double inv2pi = 0.15915494309189533577;
+  for (int g = 0; g < st.ngates; ++g) {
+    const double th = (double)params[gates[g].param];
+    if (qb < 0) {
+      if (gates[g].c == qa) turns -= 0.5 * th * inv2pi;
+    } else if ((gates[g].c == qa && gates[g].t == qb) || (gates[g].c == qb && gates[g].t == qa)) {
+      turns += th * inv2pi;
+    }
+  }
+  const double frac = turns - floor(turns);                 // [0, 1)
+  coef[st.coef_off + e] = (uint32_t)(unsigned long long)(frac * 4294967296.0);
+}
+
 // Random-Fourier-feature angles: phi = [cos(Bp); sin(Bp)], theta = W phi, J = W dphi/dp.
 __global__ void k_rff_angles(const QPlanDev* __restrict__ plan, const float* __restrict__ points,
                              long long P, float* __restrict__ angles, float* __restrict__ jac) {
@@ -172,9 +205,9 @@ __global__ void k_param_grads(const QPlanDev* __restrict__ plan, const float* __
 int fused_threads(int n) { return fused_wg_threads(n); }
 int fused_max_wg_per_cu(int n) { return fused_threads(n) == 512 ? 1 : 4; }
 int fused_points_per_tile(int n) { return fused_threads(n) / (1 << (n - 3)); }
-size_t fused_lds_bytes(int n, int exs, int n_fused) {
+size_t fused_lds_bytes(int n, int exs, int n_fused, int n_mom) {
   const int T = fused_threads(n);
-  return (size_t)exs * T * 8 * sizeof(float2) + (size_t)(T / 64) * n_fused * kGS * sizeof(float) +
+  return (size_t)exs * T * 8 * sizeof(float2) + (size_t)(T / 64) * (n_fused * kGS + n_mom) * sizeof(float) +
          (size_t)(T / 64) * 40 * sizeof(float);
 }
 
@@ -194,10 +227,14 @@ hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, 
   }
 }
 
-hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, int fp32, hipStream_t st) {
+hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, int n_phase_coef, const float* params, float* gtab,
+                             int fp32, hipStream_t st) {
   const int entries = n_fused + 1;   // + identity
   if (fp32) hipLaunchKernelGGL(k_gate_table, dim3((entries + 127) / 128), dim3(128), 0, st, plan, params, gtab);
   else hipLaunchKernelGGL(k_gate_table64, dim3((entries + 127) / 128), dim3(128), 0, st, plan, params, gtab);
+  if (n_phase_coef > 0)
+    hipLaunchKernelGGL(k_phase_table, dim3((n_phase_coef + 127) / 128), dim3(128), 0, st, plan, params,
+                       reinterpret_cast<uint32_t*>(gtab + (size_t)entries * kGT));
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct FusedArgs {
   float* lpart;           // [grid]
   float* d_angles;        // [P][n] dL/d angles (angle-given encoding) or null
   float* d_jac;           // [P][n][3] dL/d Jacobian or null
+  int n_mom;              // phase-stage moments per workgroup partial (after the F * kGS statistics)
 };
 
 int fused_threads(int n);
@@ -39,9 +40,11 @@ int fused_threads(int n);
 // SIMD resident, so a grid above two 256-thread workgroups per CU runs in generations.
 int fused_max_wg_per_cu(int n);
 int fused_points_per_tile(int n);
-size_t fused_lds_bytes(int n, int exs, int n_fused);
+size_t fused_lds_bytes(int n, int exs, int n_fused, int n_mom);
 hipError_t launch_fused(int n, int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st);
-hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, const float* params, float* gtab, int fp32, hipStream_t st);
+// Gate table [F + 1][kGT] and, after it, the phase-stage coefficients (n_phase_coef words).
+hipError_t launch_gate_table(const QPlanDev* plan, int n_fused, int n_phase_coef, const float* params, float* gtab,
+                             int fp32, hipStream_t st);
 hipError_t launch_rff(const QPlanDev* plan, const float* points, long long P, float* angles, float* jac, hipStream_t st);
 hipError_t launch_count(const float* points, long long P, float x_if, int* counts, hipStream_t st);
 hipError_t launch_reduce(const float* mpart, int nblk, int ncol, const float* lpart, double* m64, double* loss, hipStream_t st);

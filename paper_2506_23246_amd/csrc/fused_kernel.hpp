@@ -445,6 +445,116 @@ __device__ __forceinline__ void round_adj_all(float (&sr)[8][8], float (&si)[8][
   adj_gate_all<0, PULL>(sr, si, rk->gate[0], gtab, F, slots, wave, lane);
 }
 
+// ---- phase stages (CRZ runs) ------------------------------------------------------------------
+// In a round's input mapping, slot k (register bit k < 3, thread bit k - 3 otherwise) holds the
+// index bit of qubit N - 1 - tpos[k].  phi(j) = sum_q alpha_q b_q + sum_(q<q') beta_qq' b_q b_q' is
+// split into the thread's part and per-register terms; all sums are unsigned 32-bit fractions of a
+// turn, so they are exact modulo 2 pi, and only the final angle of each amplitude is rounded.
+template <int N>
+__device__ __forceinline__ uint32_t phase_beta(CP<uint32_t> coef, int a, int b) {
+  return a < b ? coef[N + phase_pair_index(N, a, b)] : coef[N + phase_pair_index(N, b, a)];
+}
+
+template <int N>
+__device__ __forceinline__ void phase_factors(CP<QRound> rk, CP<uint32_t> coef, uint32_t u, float (&pc)[8],
+                                              float (&ps)[8]) {
+  int qk[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) qk[k] = N - 1 - rk->tpos[k];
+  uint32_t th = 0, g0 = coef[qk[0]], g1 = coef[qk[1]], g2 = coef[qk[2]];
+#pragma unroll
+  for (int k = 3; k < N; ++k) {
+    const uint32_t bk = (u >> (k - 3)) & 1u;
+    uint32_t t = coef[qk[k]];
+#pragma unroll
+    for (int k2 = k + 1; k2 < N; ++k2) t += ((u >> (k2 - 3)) & 1u) * phase_beta<N>(coef, qk[k], qk[k2]);
+    th += bk * t;
+    g0 += bk * phase_beta<N>(coef, qk[0], qk[k]);
+    g1 += bk * phase_beta<N>(coef, qk[1], qk[k]);
+    g2 += bk * phase_beta<N>(coef, qk[2], qk[k]);
+  }
+  const uint32_t d01 = phase_beta<N>(coef, qk[0], qk[1]);
+  const uint32_t d02 = phase_beta<N>(coef, qk[0], qk[2]);
+  const uint32_t d12 = phase_beta<N>(coef, qk[1], qk[2]);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    uint32_t ph = th;
+    if (r & 1) ph += g0;
+    if (r & 2) ph += g1;
+    if (r & 4) ph += g2;
+    if ((r & 3) == 3) ph += d01;
+    if ((r & 5) == 5) ph += d02;
+    if ((r & 6) == 6) ph += d12;
+    // angle = 2 pi ph / 2^32 = pi x with x = (signed) ph / 2^31 in [-1, 1)
+    sincospif((float)(int32_t)ph * 4.656612873077392578125e-10f, &ps[r], &pc[r]);
+  }
+}
+
+// Multiply statevectors [S0, S0 + NS) by e^{+i phi} (CONJ: e^{-i phi}).
+template <int S0, int NS, bool CONJ>
+__device__ __forceinline__ void apply_phase(float (&sr)[8][8], float (&si)[8][8], const float (&pc)[8],
+                                            const float (&ps)[8]) {
+#pragma unroll
+  for (int s = S0; s < S0 + NS; ++s)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float c = pc[r], sn = CONJ ? -ps[r] : ps[r];
+      const float a = sr[s][r], b = si[s][r];
+      sr[s][r] = a * c - b * sn;
+      si[s][r] = a * sn + b * c;
+    }
+}
+
+// Phase-stage moments of w_j = Im(conj(lambda_j) psi_j) + sum_c Im(conj(mu_c,j) dpsi_c,j): M_q and
+// M_qq' (q < q') summed over the wave, added to the wave's slots mslots[mom_off ...].
+template <int N>
+__device__ __forceinline__ void phase_moments(const float (&sr)[8][8], const float (&si)[8][8], CP<QRound> rk, uint32_t u,
+                                              float* __restrict__ mslots, int lane) {
+  float w[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    float v = 0.f;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) v += sr[4 + p][r] * si[p][r] - si[4 + p][r] * sr[p][r];
+    w[r] = v;
+  }
+  float Wi[3] = {0.f, 0.f, 0.f}, Wii[3] = {0.f, 0.f, 0.f}, Wt = 0.f;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    Wt += w[r];
+    if (r & 1) Wi[0] += w[r];
+    if (r & 2) Wi[1] += w[r];
+    if (r & 4) Wi[2] += w[r];
+    if ((r & 3) == 3) Wii[0] += w[r];
+    if ((r & 5) == 5) Wii[1] += w[r];
+    if ((r & 6) == 6) Wii[2] += w[r];
+  }
+  int qk[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) qk[k] = N - 1 - rk->tpos[k];
+  auto flush = [&](float v, int idx) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) slot_add(mslots + idx, v);
+  };
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const float v = k < 3 ? Wi[k] : (((u >> (k - 3)) & 1u) ? Wt : 0.f);
+    flush(v, qk[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int k2 = k + 1; k2 < N; ++k2) {
+      float v;
+      if (k2 < 3) v = Wii[k + k2 - 1];                                  // (0,1) (0,2) (1,2)
+      else if (k < 3) v = ((u >> (k2 - 3)) & 1u) ? Wi[k] : 0.f;
+      else v = (((u >> (k - 3)) & (u >> (k2 - 3))) & 1u) ? Wt : 0.f;
+      const int a = qk[k] < qk[k2] ? qk[k] : qk[k2], b = qk[k] < qk[k2] ? qk[k2] : qk[k];
+      flush(v, N + phase_pair_index(N, a, b));
+    }
+}
+
 // ---- angle encoding of one qubit ------------------------------------------------------------
 // Embedded single-qubit state e(b) (b = 0, 1) and its angle derivative d(b) for qubit q, with the
 // Jacobian d theta_q / d(t, x, y).  RY: e = (cos, sin), RX: e = (cos, -i sin), of theta/2.  When the
@@ -679,7 +789,8 @@ __device__ __forceinline__ void encoding_grads(const float (&sr)[8][8], const fl
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
 template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
-                                           float* __restrict__ slots, float* __restrict__ red, float& lacc) {
+                                           float* __restrict__ slots, float* __restrict__ mslots,
+                                           float* __restrict__ red, float& lacc) {
   constexpr int TP = 1 << (N - 3);         // threads per point
   constexpr int PPW = T / TP;              // points per workgroup tile
   constexpr int DIM = 1 << N;
@@ -690,6 +801,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
   CP<QXchg> xf = reinterpret_cast<CP<QXchg>>(pb + plan->off_xf);
   CP<QXchg> xb = reinterpret_cast<CP<QXchg>>(pb + plan->off_xb);
   CP<float> gtab = to_const(a.gtab);
+  // phase stages: descriptors in the plan, coefficients after the gate table
+  const QPhaseStage* pstages = reinterpret_cast<const QPhaseStage*>(reinterpret_cast<const char*>(a.plan) + plan->off_phase);
+  CP<uint32_t> pcoef = reinterpret_cast<CP<uint32_t>>(gtab + (a.n_fused + 1) * kGT);
   const int R = plan->n_rounds;
   const int m = plan->n_out;
   const int F = a.n_fused;
@@ -839,6 +953,11 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
         if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, xf + k, lane_words(lanes, 0, R, k, TP, u, pb8));
+        if (rk->phase >= 0) {   // CRZ phase stage after the exchange (unpipelined kernel only)
+          float pc[8], ps[8];
+          phase_factors<N>(rk, pcoef + to_const(pstages)[rk->phase].coef_off, u, pc, ps);
+          apply_phase<0, 4, false>(sr, si, pc, ps);
+        }
         const RoundCoef Rk = load_round<false, NS>(rk, gtab, F);
         round_fwd<0, NS>(sr, si, Rk);
         round_fwd<2, NS>(sr, si, Rk);
@@ -1062,6 +1181,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = R - 1; k >= H; --k) {
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, true>(sr, si, rk, gtab, F, slots, wave, lane);
+        if (rk->phase >= 0) {   // CRZ phase stage: moments at its output, then uncompute and pull back
+          CP<QPhaseStage> pst = to_const(pstages) + rk->phase;
+          phase_moments<N>(sr, si, rk, u, mslots + wave * a.n_mom + pst->mom_off, lane);
+          float pc[8], ps[8];
+          phase_factors<N>(rk, pcoef + pst->coef_off, u, pc, ps);
+          apply_phase<0, 8, true>(sr, si, pc, ps);
+        }
         if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
       for (int k = H - 1; k >= 0; --k) {   // the leading stage: statistics only
@@ -1085,13 +1211,14 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   extern __shared__ float4 smem4[];
   float2* buf = reinterpret_cast<float2*>(planes);
   float* slots = reinterpret_cast<float*>(smem4);                   // [WAVES][F][kGS]
-  float* red = slots + WAVES * a.n_fused * kGS;                      // [WAVES][40]
+  float* mslots = slots + WAVES * a.n_fused * kGS;                   // [WAVES][n_mom] phase moments
+  float* red = mslots + WAVES * a.n_mom;                             // [WAVES][40]
   const int F = a.n_fused;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   if (MODE != kModeFwd) {
-    for (int i = tid; i < WAVES * F * kGS; i += T) slots[i] = 0.f;
+    for (int i = tid; i < WAVES * (F * kGS + a.n_mom); i += T) slots[i] = 0.f;
   }
   __syncthreads();
   float lacc = 0.f;
@@ -1107,14 +1234,20 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
     t_step = gridDim.x / kXcd;
   }
   for (int tile = t_begin; tile < t_end; tile += t_step)
-    fused_tile<N, T, EXS, MODE, SG, EG>(a, tile, buf, slots, red, lacc);
+    fused_tile<N, T, EXS, MODE, SG, EG>(a, tile, buf, slots, mslots, red, lacc);
   if (MODE == kModeFwd) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
+  const int ncol = F * kGS + a.n_mom;
   for (int i = tid; i < F * kGS; i += T) {
     float s = 0.f;
     for (int w = 0; w < WAVES; ++w) s += slots[w * F * kGS + i];
-    a.mpart[(long long)blockIdx.x * F * kGS + i] = s;
+    a.mpart[(long long)blockIdx.x * ncol + i] = s;
+  }
+  for (int i = tid; i < a.n_mom; i += T) {
+    float s = 0.f;
+    for (int w = 0; w < WAVES; ++w) s += mslots[w * a.n_mom + i];
+    a.mpart[(long long)blockIdx.x * ncol + F * kGS + i] = s;
   }
   if (MODE == kModeMaxwell) {
 #pragma unroll

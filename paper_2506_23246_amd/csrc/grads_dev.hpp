@@ -76,6 +76,24 @@ __device__ inline double param_grad_one(const QPlanDev* __restrict__ plan, const
     const double* S = s64 + fi * kGS;
     gsum += nv[0] * S[0] + nv[1] * S[1] + nv[2] * S[2];
   }
+  // CRZ(c, t) occurrences: dL/dtheta = M_c - 2 M_ct from the phase-stage moments, which follow the
+  // fused-gate statistics (see QPhaseStage)
+  if (plan->n_phase > 0) {
+    const int* pptr = reinterpret_cast<const int*>(pb + plan->off_pcsr_ptr);
+    const int* pidx = reinterpret_cast<const int*>(pb + plan->off_pcsr_idx);
+    const QPhaseStage* stages = reinterpret_cast<const QPhaseStage*>(pb + plan->off_phase);
+    const QPhaseGate* pg = reinterpret_cast<const QPhaseGate*>(pb + plan->off_phase_gates);
+    const int n = plan->n;
+    for (int e = pptr[k]; e < pptr[k + 1]; ++e) {
+      const int gi = pidx[e];
+      int s = 0;
+      while (s + 1 < plan->n_phase && stages[s + 1].gate0 <= gi) ++s;
+      const double* M = s64 + plan->n_fused * kGS + stages[s].mom_off;
+      const int c = pg[gi].c, t = pg[gi].t;
+      const int a = c < t ? c : t, b = c < t ? t : c;
+      gsum += M[c] - 2.0 * M[n + phase_pair_index(n, a, b)];
+    }
+  }
   return gsum;
 }
 

@@ -1,13 +1,15 @@
 // Circuit planner for the fused register/LDS kernels.
 //
-// A circuit is a time-ordered list of rotations (RX/RY/RZ) and entanglers (CNOT/CZ).  The
+// A circuit is a time-ordered list of rotations (RX/RY/RZ) and entanglers (CNOT/CZ/CRZ).  The
 // planner
 //   1. fuses consecutive rotations on one qubit into one 2x2 gate (up to three components,
 //      e.g. RZ(omega) RY(theta) RZ(phi) of the Rot gate, eq. rot_gate);
 //   2. turns every maximal run of CNOT/CZ gates into one affine stage
 //         psi_out(j') = (-1)^Q(j') psi_in(A j'),
 //      with A an invertible GF(2) matrix on index bits and Q a quadratic form (a CNOT ring is a
-//      pure index permutation, a CZ ring a pure sign function);
+//      pure index permutation, a CZ ring a pure sign function); the CRZ gates of a run (after its
+//      CNOTs; all diagonal, so they commute) become one phase stage e^{i phi(j)}, phi quadratic in
+//      the index bits with parameter-linear coefficients (the Cross-Mesh layers, eq. crz_cross_mesh);
 //   3. groups the fused gates of every rotation stage into rounds of three qubits (the three
 //      register bits of a thread) and attaches each entangler stage to the register exchange
 //      that precedes the next round; a trailing stage is folded into the readout masks.
@@ -413,14 +415,13 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   // ---------------- fused plan ----------------
   hp->fused_ok = true;
   if (n < 3 || n > kMaxQubits) { hp->fused_ok = false; hp->fused_reason = "fused kernels support 3..12 qubits"; }
-  for (const auto& g : hp->gates)
-    if (g.kind == QP_CRZ) { hp->fused_ok = false; hp->fused_reason = "CRZ is supported by the plain path only"; }
 
   struct Stage {
     bool rot;
     std::map<int, int> fused_of_qubit;   // qubit -> index into hp->fused
     std::vector<int> order;              // fused ids in creation order
     Affine aff;
+    std::vector<QPhaseGate> phase;       // CRZ gates of an entangler stage (after its CNOT map)
   };
   std::vector<Stage> stages;
   hp->fused.clear();
@@ -450,16 +451,25 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
       f.kind[f.ncomp] = g.kind;
       f.param[f.ncomp] = g.param;
       f.ncomp++;
-    } else if (g.kind == QP_CNOT || g.kind == QP_CZ) {
+    } else if (g.kind == QP_CNOT || g.kind == QP_CZ || g.kind == QP_CRZ) {
       if (stages.empty() || stages.back().rot) {
         stages.push_back(Stage{});
         stages.back().rot = false;
         stages.back().aff.init(n);
       }
-      Affine& a = stages.back().aff;
+      Stage& st = stages.back();
+      Affine& a = st.aff;
       const int b0 = n - 1 - g.q0, b1 = n - 1 - g.q1;
-      if (g.kind == QP_CNOT) a.cnot(b0, b1);
-      else a.cz(b0, b1);
+      if (g.kind == QP_CRZ) {
+        st.phase.push_back(QPhaseGate{g.q0, g.q1, g.param, 0});
+      } else if (g.kind == QP_CNOT) {
+        // the stage applies its index map, then its diagonal (CZ signs and CRZ phases commute
+        // with each other); a CNOT after a CRZ would need the phase moved through the map
+        if (!st.phase.empty()) { hp->fused_ok = false; hp->fused_reason = "a CNOT after a CRZ in one entangler stage"; }
+        a.cnot(b0, b1);
+      } else {
+        a.cz(b0, b1);
+      }
       if ((int)a.terms.size() > kMaxTerms) { hp->fused_ok = false; hp->fused_reason = "too many CZ terms in one entangler stage"; }
     }
   }
@@ -488,9 +498,11 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   hp->rounds.clear();
   std::vector<Affine> round_ent;    // entangler applied in the exchange before round k
   std::vector<bool> round_has_ent;
+  std::vector<std::vector<QPhaseGate>> round_phase;   // CRZ phase applied after that exchange
   Affine pending;
   pending.init(n);
   bool have_pending = false;
+  std::vector<QPhaseGate> pending_phase;
   const int nsw = swap_slots(n);
   auto push_round = [&](const int* gate_ids, const int* reg, const int* sgate_ids, const int* spos) {
     QRound R{};
@@ -504,11 +516,14 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     make_tpos(n, reg, fixed, R.tpos);
     for (int k = 0; k < 16; ++k) R.tpost[k] = R.tpos[k];
     for (int i = 0; i < nsw; ++i) std::swap(R.tpost[i], R.tpost[3 + 4 + i]);
+    R.phase = -1;
     hp->rounds.push_back(R);
     round_ent.push_back(pending);
     round_has_ent.push_back(have_pending);
+    round_phase.push_back(pending_phase);
     pending.init(n);
     have_pending = false;
+    pending_phase.clear();
   };
   // any nsw distinct positions other than reg[] (for rounds whose swap slots carry no gate)
   auto free_spos = [&](const int* reg, int* spos) {
@@ -522,6 +537,7 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
   for (size_t si = 0; si < stages.size(); ++si) {
     Stage& s = stages[si];
     if (!s.rot) {
+      pending_phase = s.phase;   // (two entangler stages are never adjacent: consecutive gates share one)
       // compose: pending then s.aff  ->  psi(j) = sP(j') ... apply s after pending
       if (!have_pending) { pending = s.aff; have_pending = true; continue; }
       // composition of two affine stages: first P (A1, Q1) then S (A2, Q2):
@@ -548,11 +564,14 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
       free_spos(reg, spos);
       Affine keep = pending;
       bool hk = have_pending;
+      std::vector<QPhaseGate> kp = pending_phase;
       pending.init(n);
       have_pending = false;
+      pending_phase.clear();
       push_round(none, reg, snone, spos);
       pending = keep;
       have_pending = hk;
+      pending_phase = kp;
     }
     // fused gates of the stage sorted by qubit, in chunks of 3 + nsw: three on the register bits,
     // the rest on the swap slots
@@ -595,11 +614,39 @@ std::string build_plan(const qp_circuit_desc* d, HostPlan* hp, int* status) {
     free_spos(reg, spos);
     Affine keep = pending;
     bool hk = have_pending;
+    std::vector<QPhaseGate> kp = pending_phase;
     pending.init(n);
     have_pending = false;
+    pending_phase.clear();
     push_round(none, reg, snone, spos);
     pending = keep;
     have_pending = hk;
+    pending_phase = kp;
+  }
+  // A trailing phase stage (pending_phase here) is diagonal right before the Z readout: it changes
+  // neither the readouts nor their tangents (a common phase per amplitude), and its parameters get
+  // an exactly zero gradient, so it is dropped.
+  // Phase stages before rounds 1..R-1, their coefficient and moment slots, parameter map.
+  hp->phases.clear();
+  hp->phase_gates.clear();
+  for (size_t k = 1; k < hp->rounds.size(); ++k) {
+    if (round_phase[k].empty()) continue;
+    QPhaseStage ps{};
+    ps.gate0 = (int)hp->phase_gates.size();
+    ps.ngates = (int)round_phase[k].size();
+    ps.coef_off = (int)hp->phases.size() * phase_terms(n);
+    ps.mom_off = ps.coef_off;
+    hp->rounds[k].phase = (int)hp->phases.size();
+    hp->phases.push_back(ps);
+    for (const auto& pg : round_phase[k]) hp->phase_gates.push_back(pg);
+  }
+  hp->pcsr_ptr.assign(hp->K + 1, 0);
+  for (const auto& pg : hp->phase_gates) hp->pcsr_ptr[pg.param + 1]++;
+  for (int k = 0; k < hp->K; ++k) hp->pcsr_ptr[k + 1] += hp->pcsr_ptr[k];
+  hp->pcsr_idx.assign(hp->pcsr_ptr[hp->K], 0);
+  {
+    std::vector<int> fill(hp->pcsr_ptr.begin(), hp->pcsr_ptr.end() - 1);
+    for (size_t gi = 0; gi < hp->phase_gates.size(); ++gi) hp->pcsr_idx[fill[hp->phase_gates[gi].param]++] = (int)gi;
   }
   // An opening rotation stage acts on the product state: one fused gate per qubit, all commuting.
   // Its rounds are folded into the encoding and their gates take their statistics at the stage
@@ -698,6 +745,13 @@ image:
   h.off_dcsr_ptr = (int)off; off = align16(off + sizeof(int32_t) * hp->dcsr_ptr.size());
   h.off_dcsr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->dcsr_idx.size()));
   h.off_lanes = (int)off; off = align16(off + sizeof(QLane) * hp->lanes.size());
+  h.n_phase = hp->fused_ok ? (int)hp->phases.size() : 0;
+  h.n_phase_coef = h.n_phase * phase_terms(n);
+  h.n_moments = h.n_phase_coef;
+  h.off_phase = (int)off; off = align16(off + sizeof(QPhaseStage) * hp->phases.size());
+  h.off_phase_gates = (int)off; off = align16(off + sizeof(QPhaseGate) * hp->phase_gates.size());
+  h.off_pcsr_ptr = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->pcsr_ptr.size()));
+  h.off_pcsr_idx = (int)off; off = align16(off + sizeof(int32_t) * std::max<size_t>(1, hp->pcsr_idx.size()));
   h.bytes = (int)off;
   hp->blob.assign(off, 0);
   std::memcpy(hp->blob.data(), &h, sizeof(h));
@@ -717,6 +771,11 @@ image:
   std::memcpy(hp->blob.data() + h.off_dcsr_ptr, hp->dcsr_ptr.data(), sizeof(int32_t) * hp->dcsr_ptr.size());
   if (!hp->dcsr_idx.empty()) std::memcpy(hp->blob.data() + h.off_dcsr_idx, hp->dcsr_idx.data(), sizeof(int32_t) * hp->dcsr_idx.size());
   if (!hp->lanes.empty()) std::memcpy(hp->blob.data() + h.off_lanes, hp->lanes.data(), sizeof(QLane) * hp->lanes.size());
+  if (!hp->phases.empty()) std::memcpy(hp->blob.data() + h.off_phase, hp->phases.data(), sizeof(QPhaseStage) * hp->phases.size());
+  if (!hp->phase_gates.empty())
+    std::memcpy(hp->blob.data() + h.off_phase_gates, hp->phase_gates.data(), sizeof(QPhaseGate) * hp->phase_gates.size());
+  if (!hp->pcsr_ptr.empty()) std::memcpy(hp->blob.data() + h.off_pcsr_ptr, hp->pcsr_ptr.data(), sizeof(int32_t) * hp->pcsr_ptr.size());
+  if (!hp->pcsr_idx.empty()) std::memcpy(hp->blob.data() + h.off_pcsr_idx, hp->pcsr_idx.data(), sizeof(int32_t) * hp->pcsr_idx.size());
   return "";
 }
 

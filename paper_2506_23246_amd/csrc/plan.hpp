@@ -29,6 +29,9 @@ struct HostPlan {
   std::vector<int32_t> csr_ptr, csr_idx;
   int n_exchanges = 0;                 // exchanges that move data
   bool has_signs = false;              // some exchange carries CZ signs
+  std::vector<QPhaseStage> phases;     // CRZ phase stages, by exchange
+  std::vector<QPhaseGate> phase_gates;
+  std::vector<int32_t> pcsr_ptr, pcsr_idx;
   int n_head = 0;                      // leading rounds folded into the encoding
   int32_t head_gate[16];               // per qubit: its leading-stage fused gate, or -1
   // dense-block plan (MFMA path)

@@ -51,7 +51,7 @@ QP_HD inline constexpr int fused_wg_threads(int n) { return n == 12 ? 512 : 256;
 
 struct alignas(16) QRound {
   int32_t gate[3];    // fused-gate id applied on register bit b in the round's input mapping (-1: none)
-  int32_t pad0;
+  int32_t phase;      // phase stage applied after the exchange into this round (-1: none)
   int32_t sgate[2];   // fused-gate id applied on register bit i after swap slot i (-1: none)
   int32_t pad1[2];
   int32_t tpos[16];   // input mapping: logical index-bit position of physical bit k
@@ -104,6 +104,30 @@ struct alignas(16) QFused {
 };
 static_assert(sizeof(QFused) == 48, "QFused layout");
 
+// Phase stage: a run of CRZ gates (with any CZ of the same stage), all diagonal, applied as one
+// phase e^{i phi(j)} per basis index after the exchange that precedes a round.  With
+// CRZ(c, t)(theta) = |0><0|_c (x) I + |1><1|_c (x) RZ_t(theta),
+//   phi(j) = sum_(c,t) theta_ct (-1/2) b_c(j) (1 - 2 b_t(j)) = sum_q alpha_q b_q + sum_(q<q') beta_qq' b_q b_q',
+//   alpha_q = -(1/2) sum_t theta_qt,  beta_qq' = theta_qq' + theta_q'q.
+// The coefficients are kept as unsigned 32-bit fractions of a turn (2 pi = 2^32), so phases add
+// exactly modulo 2 pi.  Per stage: n alpha's then the n(n-1)/2 beta's (pairs q < q' in row order),
+// at coef_off (in 32-bit words) of the phase table that follows the gate table.  The adjoint
+// accumulates the moments M_q = sum_j w_j b_q and M_qq' = sum_j w_j b_q b_q' of
+// w_j = Im(conj(lambda_j) psi_j) + sum_c Im(conj(mu_c,j) dpsi_c,j) at the stage output (same
+// order, at mom_off among the phase moments), and dL/dtheta_ct = M_c - 2 M_ct.
+struct alignas(16) QPhaseStage {
+  int32_t gate0, ngates;  // range in the QPhaseGate array
+  int32_t coef_off;       // first coefficient (32-bit words) in the phase table
+  int32_t mom_off;        // first moment among the phase moments
+};
+struct alignas(16) QPhaseGate {
+  int32_t c, t, param, pad;   // control and target qubits, parameter index
+};
+QP_HD inline constexpr int phase_pair_index(int n, int a, int b) {   // a < b
+  return a * n - a * (a + 1) / 2 + (b - a - 1);
+}
+QP_HD inline constexpr int phase_terms(int n) { return n + n * (n - 1) / 2; }
+
 enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2 };
 
 // Dense 2^5 blocks (MFMA path): a contiguous run of gates acting on at most five qubits.
@@ -143,6 +167,14 @@ struct alignas(16) QPlanDev {
   int32_t n_head;                   // leading rounds folded into the encoding (rounds 0 .. n_head-1; < n_rounds)
   int32_t head_gate[16];            // per qubit: fused gate of the leading stage, -1 if none
   int32_t off_lanes;                // QLane[2][n_rounds][2^(n-3)]: forward (0) and reverse (1) exchanges
+  int32_t n_phase;                  // phase stages (CRZ runs)
+  int32_t off_phase;                // QPhaseStage[n_phase]
+  int32_t off_phase_gates;          // QPhaseGate[...]
+  int32_t n_phase_coef;             // 32-bit words of the phase table (n_phase * phase_terms(n))
+  int32_t n_moments;                // phase moments accumulated by the adjoint (same count)
+  int32_t off_pcsr_ptr;             // int32[n_params+1]: parameter -> CRZ occurrences
+  int32_t off_pcsr_idx;             // int32[...]: phase-gate index
+  int32_t pad_end;
 };
 
 }  // namespace qp

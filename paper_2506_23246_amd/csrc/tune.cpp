@@ -96,8 +96,10 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
   hipEventCreate(&e1);
   TuneEntry best{c->exs, c->wg_per_cu, 1e30};
   const int max_wg = fused_max_wg_per_cu(n);
+  const int NM = n_moments(c);
   for (int exs : {2, 4}) {
-    const size_t lds = fused_lds_bytes(n, exs, F);
+    if (exs == 4 && NM > 0) continue;   // phase stages run on the unpipelined kernel
+    const size_t lds = fused_lds_bytes(n, exs, F, NM);
     if (lds > cap) continue;
     for (int wg = 1; wg <= max_wg; ++wg) {
       if (lds * wg > cap) break;

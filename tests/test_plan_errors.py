@@ -3,6 +3,7 @@
 import ctypes as C
 import os
 
+import numpy as np
 import pytest
 
 import workloads as W
@@ -56,10 +57,40 @@ def test_malformed_descriptors_are_status_codes(case):
 
 
 def test_plain_only_circuits_have_no_fused_plan():
-    """13 qubits and CRZ gates are evaluated by the plain path only: the fused planner reports
-    QP_EUNSUPPORTED instead of building register rounds."""
+    """13 qubits, and a CNOT after a CRZ within one entangler stage (the phase would have to move
+    through the index map), are evaluated by the plain path only: the fused planner reports
+    QP_EUNSUPPORTED instead of building register rounds.  A CRZ run alone plans."""
     from paper_2506_23246_amd import _lib as L
     st, _ = _status(W.layered(13, 1, "xyz", lambda l: W.ring(13, W.CNOT, 1)))
     assert st == L.QP_EUNSUPPORTED
-    st, _ = _status(_circ(4, [(W.RX, 0, -1, 0), (W.CRZ, 0, 1, 1)], 2))
+    st, _ = _status(_circ(4, [(W.RX, 0, -1, 0), (W.CRZ, 0, 1, 1), (W.CNOT, 1, 2, -1), (W.RY, 2, -1, 2)], 3))
     assert st == L.QP_EUNSUPPORTED
+    st, _ = _status(_circ(4, [(W.RX, 0, -1, 0), (W.CNOT, 1, 2, -1), (W.CRZ, 0, 1, 1), (W.RY, 2, -1, 2)], 3))
+    assert st == L.QP_OK
+
+
+def test_cross_mesh_phase_stages_in_the_plan_image():
+    """The 7-qubit, 4-layer Cross-Mesh plan: one phase stage per layer but the last (a diagonal
+    right before the Z readout changes no output and has zero gradient), n + n(n-1)/2 = 28
+    coefficients and moments per stage, each CRZ parameter of the first three layers mapped to
+    exactly one phase gate, the last layer's to none."""
+    import ctypes as C
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import make_desc
+    from tests.plan_emulator import HDR
+    circ = W.paper_context_circuit("cross_mesh")
+    d, keep = make_desc(circ)
+    nb = C.c_size_t(0)
+    L.qp_plan_image(C.byref(d), None, 0, C.byref(nb))
+    buf = (C.c_ubyte * nb.value)()
+    assert L.qp_plan_image(C.byref(d), buf, nb.value, C.byref(nb)) == L.QP_OK
+    raw = bytes(buf)
+    base = HDR.itemsize
+    n_phase, off_phase, off_gates, n_coef, n_mom, off_ptr, off_idx = np.frombuffer(raw, "<i4", 7, base)
+    assert n_phase == 3 and n_coef == n_mom == 3 * 28
+    stages = np.frombuffer(raw, "<i4", 4 * 3, off_phase).reshape(3, 4)
+    assert list(stages[:, 1]) == [42, 42, 42] and list(stages[:, 2]) == [0, 28, 56]
+    ptr = np.frombuffer(raw, "<i4", circ.n_params + 1, off_ptr)
+    crz = [p for (k, q0, q1, p) in circ.gates if k == W.CRZ]
+    counts = np.diff(ptr)
+    assert all(counts[p] == 1 for p in crz[:126]) and all(counts[p] == 0 for p in crz[126:])
