@@ -182,6 +182,7 @@ def main():
                     help="points of the CPU oracle sample (default: two chunks per core at 12 qubits)")
     ap.add_argument("--no-c1", action="store_true", help="skip the plain FP64 4-qubit wall-time leg")
     ap.add_argument("--no-total", action="store_true", help="skip the paper's total-loss leg")
+    ap.add_argument("--no-training", action="store_true", help="skip the training-epoch leg")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-block MFMA comparison leg")
@@ -519,6 +520,35 @@ def main():
             "terms": {"total": float(terms[0]), "phys": float(terms[1]), "ic": float(terms[2]),
                       "sym": float(terms[3]), "energy": float(terms[4])}}
         log(f"bench: total loss {line['total_loss']}")
+
+    if k == 4 and not args.no_training:
+        # Training epochs of the paper's hybrid model (classical network, 7-qubit 4-layer Basic
+        # Entangling Layers, linear head) with the total loss and Adam, full batch, at the grid sizes of
+        # the paper's runtime table; the same epoch for the circuit alone (qp_total_loss) at 40^3.
+        from paper_2506_23246_amd.hybrid import HybridQPINN
+        from paper_2506_23246_amd.train import grid_points, ic_plane, train_circuit, train_hybrid
+        tr = {}
+        for side in (40, 87):
+            model = HybridQPINN(W.paper_context_circuit("basic"), ctx=ctx, seed=0).cuda()
+            lg = train_hybrid(model, grid_points(side, device=dev), ic_plane(side, device=dev), W.TotalLossDesc(),
+                              epochs=4)
+            tr[f"{side}^3"] = {"s_per_epoch": round(lg.s_per_epoch(), 4), "loss_first_last": [lg.loss[0], lg.loss[-1]]}
+            del model
+        pc = W.paper_context_circuit("basic")
+        pc.enc = W.Encoding()          # the circuit alone: cycled RY(pi c) encoding of the points
+        cc = Circuit(ctx, pc)
+        rng_t = np.random.default_rng(5)
+        lg = train_circuit(cc, rng_t.uniform(0, 2 * math.pi, pc.n_params), grid_points(40, device=dev),
+                           ic_plane(40, device=dev), W.TotalLossDesc(), epochs=4)
+        line["training_epoch"] = {
+            "what": "Adam epochs, full batch, total loss (residuals + 10 IC + 10 symmetry + 10 energy), paper's 7-qubit "
+                    "4-layer circuit: hybrid = RFF + 256/128 tanh network + circuit (autograd Jacobian of the angles, "
+                    "engine tangents and adjoint) + Linear(7, 3); circuit_alone = qp_total_loss on the circuit",
+            "hybrid": tr, "circuit_alone_40^3_s_per_epoch": round(lg.s_per_epoch(), 4),
+            "paper_torq_s_per_epoch": {"40^3": 0.145136, "87^3": 0.849967},
+            "paper_scope": "TorQ, NVIDIA L40S or A100, precision not stated; the paper's model also has the periodic "
+                           "input map; context only"}
+        log(f"bench: training {line['training_epoch']}")
 
     if k == 4 and not args.no_c1:
         line["c1_plain_fp64"] = c1_plain_fp64(ctx, dev)

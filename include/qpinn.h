@@ -223,6 +223,30 @@ qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float* params, c
                         float* out, float* tan, double* loss_terms, float* d_params, void* ws,
                         size_t ws_bytes, uint32_t flags);
 
+/* ---- diagnostics of the "black hole" study --------------------------------------------
+ * (section "'Black hole' loss landscape")
+ * qp_bloch: for every point, the Bloch vector r_k = (<X_k>, <Y_k>, <Z_k>) of every qubit of the
+ * circuit's output state, bloch [P][n][3], and the global Meyer-Wallach entanglement
+ *   Q = 2 (1 - (1/n) sum_k Tr rho_k^2) = 1 - (1/n) sum_k |r_k|^2   (rho_k = (I + r_k . sigma) / 2),
+ * mw [P] (or NULL): 0 for product states, 1 for GHZ states.  Evaluated on the plain path (the
+ * state held in the workspace, any circuit the plain path runs): precision 32 or 64 selects the
+ * real type of params, points/angles and the outputs; points [P][3] for point encodings, angles
+ * [P][n] for the angle-given encoding; workspace qp_plain_workspace_bytes(c, P, precision).
+ * qp_energy_profile: the total field energy U(t_i) = sum over the grid xg x yg of
+ *   (eps E_z^2 + H_x^2 + H_y^2) / 2 at every time t_i (device double [Nt]), eps = eps_r where
+ *   x >= x_interface for the dielectric losses, else 1, from the fused forward on the Nt Nx Ny grid
+ *   points (t-major); the collapse indicator I_BH = 1 - min_{t >= delta} U(t) / U(0) follows on the
+ *   host.  Point encodings only; device inputs t [Nt], xg [Nx], yg [Ny]; workspace
+ *   qp_energy_workspace_bytes.                                                                */
+qp_status qp_bloch(qp_ctx* ctx, const qp_circuit* c, int32_t precision, const void* params,
+                   const void* points, const void* angles, int64_t P, void* bloch, void* mw, void* ws,
+                   size_t ws_bytes);
+size_t qp_energy_workspace_bytes(const qp_circuit* c, int64_t Nt, int64_t Nx, int64_t Ny);
+qp_status qp_energy_profile(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* t,
+                            int64_t Nt, const float* xg, int64_t Nx, const float* yg, int64_t Ny,
+                            const qp_maxwell_desc* desc, double* U, void* ws, size_t ws_bytes,
+                            uint32_t flags);
+
 /* ---- fused Maxwell evaluation without allocation ---------------------------------------
  * For callers that cannot allocate device memory or pass a workspace: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, checks and

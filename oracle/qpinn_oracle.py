@@ -473,6 +473,79 @@ def total_eval(circ, params, points, ic_xy, desc):
     return terms, grad
 
 
+# ---------------------------------------------------------------- diagnostics ------------------
+# Section "'Black hole' loss landscape": the global Meyer-Wallach entanglement of the circuit's
+# output state and the total field energy over time with its collapse indicator.
+
+def reduced_density_matrices(psi, n):
+    """rho_k [n, 2, 2] of one pure state psi [2^n] by explicit partial traces (qubit 0 = leftmost
+    tensor factor): reshape to (2^k, 2, 2^(n-k-1)) and contract the other factors."""
+    out = np.zeros((n, 2, 2), np.complex128)
+    for k in range(n):
+        t = psi.reshape(2 ** k, 2, 2 ** (n - k - 1))
+        out[k] = np.einsum("aib,ajb->ij", t, np.conj(t))
+    return out
+
+
+def bloch_vectors(circ, params, points=None, angles=None, jac=None):
+    """(<X_k>, <Y_k>, <Z_k>) [P, n, 3] of every qubit of every point's output state, from the reduced
+    density matrices: rho = (I + r . sigma) / 2, so r = (2 Re rho_01, -2 Im rho_01, rho_00 - rho_11)."""
+    psi, _ = final_states(circ, params, points, angles, jac)
+    n, P = circ.n, psi.shape[1]
+    r = np.zeros((P, n, 3))
+    for p in range(P):
+        rho = reduced_density_matrices(psi[:, p], n)
+        r[p, :, 0] = 2 * rho[:, 0, 1].real
+        r[p, :, 1] = -2 * rho[:, 0, 1].imag
+        r[p, :, 2] = (rho[:, 0, 0] - rho[:, 1, 1]).real
+    return r
+
+
+def meyer_wallach(circ, params, points=None, angles=None, jac=None):
+    """Global entanglement Q = 2 (1 - (1/n) sum_k Tr rho_k^2) of every point's output state
+    (Meyer and Wallach's measure in Brennen's form): 0 for product states, 1 for GHZ states."""
+    psi, _ = final_states(circ, params, points, angles, jac)
+    n, P = circ.n, psi.shape[1]
+    q = np.zeros(P)
+    for p in range(P):
+        rho = reduced_density_matrices(psi[:, p], n)
+        purity = np.einsum("kij,kji->k", rho, rho).real
+        q[p] = 2.0 * (1.0 - purity.mean())
+    return q
+
+
+def energy_grid(t_values, xg, yg):
+    """Points (t, x, y) of the time slices t over the spatial grid xg x yg, t-major."""
+    T, X, Y = np.meshgrid(np.asarray(t_values, np.float64), np.asarray(xg, np.float64),
+                          np.asarray(yg, np.float64), indexing="ij")
+    return np.stack([T.ravel(), X.ravel(), Y.ravel()], 1)
+
+
+def energy_from_fields(f, points, n_t, desc):
+    """U(t) = sum over the spatial grid of (eps E^2 + Hx^2 + Hy^2) / 2 for every time slice (f and
+    points t-major, n_t slices)."""
+    eps = _eps(points, desc)
+    u = 0.5 * (eps * f[:, 0] ** 2 + f[:, 1] ** 2 + f[:, 2] ** 2)
+    return u.reshape(n_t, -1).sum(axis=1)
+
+
+def energy_profile(circ, params, t_values, xg, yg, desc):
+    pts = energy_grid(t_values, xg, yg)
+    f, _ = simulate(circ, params, pts)
+    return energy_from_fields(f, pts, len(t_values), desc)
+
+
+def black_hole_indicator(U, t_values, delta):
+    """I_BH = 1 - min_{t in [delta, T]} U(t) / U(0) (U(0) the slice at t = 0)."""
+    t = np.asarray(t_values, np.float64)
+    U = np.asarray(U, np.float64)
+    i0 = int(np.argmin(np.abs(t)))
+    if t[i0] != 0.0:
+        raise ValueError("the time slices must include t = 0")
+    sel = t >= delta
+    return float(1.0 - np.min(U[sel] / U[i0]))
+
+
 # --------------------------------------------------------------- gradients --------------------
 
 def grad_reverse(circ, params, points, seeds_f, seeds_g, angles=None, jac=None, chunk=None,

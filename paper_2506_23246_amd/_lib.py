@@ -72,6 +72,10 @@ _SIGS = {
     "qp_total_workspace_bytes": (C.c_size_t, [_P, C.c_int64, C.c_int64, C.c_int32]),
     "qp_total_loss": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(qp_total_loss_desc), _P, _P,
                                 _P, _P, _P, C.c_size_t, C.c_uint32]),
+    "qp_bloch": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_size_t]),
+    "qp_energy_workspace_bytes": (C.c_size_t, [_P, C.c_int64, C.c_int64, C.c_int64]),
+    "qp_energy_profile": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int64,
+                                    C.POINTER(qp_maxwell_desc), _P, _P, C.c_size_t, C.c_uint32]),
     "qp_noalloc_scratch_bytes": (C.c_size_t, []),
     "qp_maxwell_fused_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(qp_maxwell_desc), _P, _P,
                                            _P, _P, _P, _P, C.c_uint32]),

@@ -238,6 +238,37 @@ class Circuit:
                 self.ctx.h)
         return r
 
+    def bloch(self, params, points=None, angles=None, precision=32):
+        """Per-qubit Bloch vectors [P, n, 3] and Meyer-Wallach entanglement [P] of the output states."""
+        dt = torch.float64 if precision == 64 else torch.float32
+        dev = self.ctx.dev
+        prm = torch.as_tensor(params).to(dev, dt).contiguous()
+        pts = None if points is None else torch.as_tensor(points).to(dev, dt).contiguous()
+        ang = None if angles is None else torch.as_tensor(angles).to(dev, dt).contiguous()
+        P = int((pts if pts is not None else ang).shape[0])
+        r = torch.empty((P, self.n, 3), dtype=dt, device=dev)
+        mw = torch.empty(P, dtype=dt, device=dev)
+        _, wp, nb = self.plain_workspace(P, precision)
+        L.check(L.qp_bloch(self.ctx.h, self.h, precision, _ptr(prm), _ptr(pts), _ptr(ang), P, _ptr(r), _ptr(mw), wp,
+                           nb), self.ctx.h)
+        return r, mw
+
+    def energy_profile(self, params, t, xg, yg, loss=None, flags=0):
+        """U(t_i) = sum over the grid xg x yg of (eps E^2 + Hx^2 + Hy^2) / 2, float64 [Nt]."""
+        dev = self.ctx.dev
+        prm, tt, xx, yy = _f32(params, dev), _f32(t, dev), _f32(xg, dev), _f32(yg, dev)
+        Nt, Nx, Ny = int(tt.shape[0]), int(xx.shape[0]), int(yy.shape[0])
+        U = torch.empty(Nt, dtype=torch.float64, device=dev)
+        nb = int(L.qp_energy_workspace_bytes(self.h, Nt, Nx, Ny))
+        key = ("energy", nb)
+        if key not in self._ws:
+            self._ws[key] = _aligned_bytes(nb, dev)
+        _, wp, _ = self._ws[key]
+        md = maxwell_desc(loss) if loss is not None else None
+        L.check(L.qp_energy_profile(self.ctx.h, self.h, _ptr(prm), _ptr(tt), Nt, _ptr(xx), Nx, _ptr(yy), Ny,
+                                    C.byref(md) if md is not None else None, _ptr(U), wp, nb, flags), self.ctx.h)
+        return U
+
     # ---- plain baseline -------------------------------------------------------------------
     def plain_workspace(self, P, precision):
         nb = int(L.qp_plain_workspace_bytes(self.h, int(P), int(precision)))

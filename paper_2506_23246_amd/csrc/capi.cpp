@@ -12,6 +12,7 @@
 #include "../../include/qpinn.h"
 #include "batch.hpp"
 #include "dense.hpp"
+#include "diag.hpp"
 #include "capi_internal.hpp"
 #include "fused.hpp"
 #include "plain.hpp"
@@ -486,6 +487,80 @@ extern "C" qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const fl
                                       float* d_jac, void* ws, size_t ws_bytes, uint32_t flags) {
   return maxwell_entry(ctx, c, params, points, angles, jac, P, ld, out, tan, loss, d_params, d_angles, d_jac, ws,
                        ws_bytes, flags, "qp_maxwell_fused");
+}
+
+// ---------------------------------------------------------------- diagnostics ---------------
+static PlainProblem plain_problem(const qp_circuit* c, int64_t P);
+
+extern "C" qp_status qp_bloch(qp_ctx* ctx, const qp_circuit* c, int32_t precision, const void* params,
+                              const void* points, const void* angles, int64_t P, void* bloch, void* mw, void* ws,
+                              size_t ws_bytes) {
+  const char* who = "qp_bloch";
+  if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
+  if (precision != 32 && precision != 64) return fail(ctx, QP_EINVAL, "%s: precision must be 32 or 64", who);
+  if (P < 0) return fail(ctx, QP_EINVAL, "%s: P < 0", who);
+  const bool given = c->hp.enc_kind == QP_ENC_ANGLES;
+  if ((c->hp.K > 0 && !params) || (P > 0 && (given ? !angles : !points)) || (P > 0 && !bloch))
+    return fail(ctx, QP_EINVAL, "%s: null params, %s or bloch", who, given ? "angles" : "points");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or misaligned", who);
+  if (ws_bytes < qp_plain_workspace_bytes(c, P, precision)) return fail(ctx, QP_EWORKSPACE, "%s: workspace too small", who);
+  hipSetDevice(ctx->device);
+  return hipcheck(ctx, plain_bloch(plain_problem(c, P), precision, params, given ? nullptr : points,
+                                   given ? angles : nullptr, bloch, mw, ws, ctx->stream),
+                  "bloch");
+}
+
+namespace {
+struct EnergyLayout { size_t pts, out, fused, total; int64_t P; };
+EnergyLayout energy_layout(const qp_circuit* c, int64_t Nt, int64_t Nx, int64_t Ny) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  EnergyLayout L{};
+  L.P = Nt * Nx * Ny;
+  size_t off = 0;
+  L.pts = off; off = al(off + sizeof(float) * 3 * (size_t)L.P);
+  L.out = off; off = al(off + sizeof(float) * c->hp.m * (size_t)L.P);
+  L.fused = off; off = al(off + fused_layout(c, L.P, c->ctx->cu_count * 4).total);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t qp_energy_workspace_bytes(const qp_circuit* c, int64_t Nt, int64_t Nx, int64_t Ny) {
+  if (!c || Nt < 0 || Nx < 0 || Ny < 0) return 0;
+  return energy_layout(c, Nt, Nx, Ny).total;
+}
+
+extern "C" qp_status qp_energy_profile(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* t,
+                                       int64_t Nt, const float* xg, int64_t Nx, const float* yg, int64_t Ny,
+                                       const qp_maxwell_desc* desc, double* U, void* ws, size_t ws_bytes,
+                                       uint32_t flags) {
+  const char* who = "qp_energy_profile";
+  if (!ctx || !c) return fail(ctx, QP_EINVAL, "%s: null context or circuit", who);
+  if (Nt < 0 || Nx < 0 || Ny < 0) return fail(ctx, QP_EINVAL, "%s: negative grid size", who);
+  if (c->hp.enc_kind == QP_ENC_ANGLES) return fail(ctx, QP_EINVAL, "%s: the grid needs a point encoding", who);
+  if (!c->hp.fused_ok) return fail(ctx, QP_EUNSUPPORTED, "%s: %s", who, c->hp.fused_reason.c_str());
+  if (c->hp.m < 3) return fail(ctx, QP_ESHAPE, "%s: the energy needs 3 outputs (E_z, H_x, H_y)", who);
+  if (flags & ~QP_FLAG_GATES_FP32) return fail(ctx, QP_EUNSUPPORTED, "%s: only QP_FLAG_GATES_FP32 is supported", who);
+  const EnergyLayout L = energy_layout(c, Nt, Nx, Ny);
+  if (L.P > (int64_t)INT32_MAX) return fail(ctx, QP_EUNSUPPORTED, "%s: grid too large for one call", who);
+  if ((c->hp.K > 0 && !params) || (Nt > 0 && (!t || !U)) || (L.P > 0 && (!xg || !yg)))
+    return fail(ctx, QP_EINVAL, "%s: null pointer argument", who);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or misaligned", who);
+  if (ws_bytes < L.total) return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, L.total);
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  char* w = static_cast<char*>(ws);
+  float* pts = reinterpret_cast<float*>(w + L.pts);
+  float* f = reinterpret_cast<float*>(w + L.out);
+  hipError_t e = launch_energy_grid(t, Nt, xg, Nx, yg, Ny, pts, st);
+  if (e != hipSuccess) return hipcheck(ctx, e, "energy grid");
+  qp_status s = run_fused(ctx, c, kModeFwd, params, pts, nullptr, nullptr, L.P, nullptr, f, nullptr, nullptr, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, w + L.fused, flags, 0, 0);
+  if (s != QP_OK) return s;
+  const int diel = desc && desc->kind != QP_LOSS_VACUUM;
+  e = launch_energy_reduce(f, c->hp.m, pts, Nt, Nx * Ny, diel, desc ? desc->eps_r : 1.f, desc ? desc->x_interface : 0.f,
+                           U, st);
+  return hipcheck(ctx, e, "energy reduce");
 }
 
 // ---------------------------------------------------------------- total loss ----------------

@@ -216,9 +216,46 @@ __global__ void k_plain_fd_param(const double* __restrict__ lp, const double* __
 // ---------------------------------------------------------------------------------------------
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Bloch vectors r_k = (<X_k>, <Y_k>, <Z_k>) of every qubit of every point's state, and the global
+// Meyer-Wallach entanglement Q = 2 (1 - (1/n) sum_k Tr rho_k^2) = 1 - (1/n) sum_k |r_k|^2 (a qubit's
+// reduced state is rho_k = (I + r_k . sigma) / 2); one wave per point.
+template <typename TR>
+__global__ void k_plain_bloch(int n, long long P, const C2<TR>* __restrict__ st, TR* __restrict__ bloch,
+                              TR* __restrict__ mw) {
+  const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= P) return;
+  const C2<TR>* s = st + (p << n);
+  TR q = 0;
+  for (int k = 0; k < n; ++k) {
+    const uint32_t mk = 1u << (n - 1 - k);
+    TR x = 0, y = 0, z = 0;
+    for (uint32_t i = lane; i < (1u << (n - 1)); i += 64) {
+      const uint32_t lo = i & (mk - 1);
+      const uint32_t j0 = ((i ^ lo) << 1) | lo, j1 = j0 | mk;
+      const C2<TR> a = s[j0], b = s[j1];
+      x += 2 * (a.r * b.r + a.i * b.i);      // 2 Re(conj(a) b)
+      y += 2 * (a.r * b.i - a.i * b.r);      // 2 Im(conj(a) b)
+      z += (a.r * a.r + a.i * a.i) - (b.r * b.r + b.i * b.i);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      x += __shfl_xor(x, off);
+      y += __shfl_xor(y, off);
+      z += __shfl_xor(z, off);
+    }
+    if (lane == 0) {
+      bloch[(p * n + k) * 3 + 0] = x;
+      bloch[(p * n + k) * 3 + 1] = y;
+      bloch[(p * n + k) * 3 + 2] = z;
+    }
+    q += x * x + y * y + z * z;
+  }
+  if (lane == 0 && mw) mw[p] = 1 - q / (TR)n;
+}
+
 template <typename TR>
 hipError_t plain_forward_t(const PlainProblem& pr, const TR* params, const TR* points, int coord, double delta,
-                           TR* f, void* ws, hipStream_t st) {
+                           TR* f, void* ws, hipStream_t st, const TR* angles = nullptr) {
   const PlainLayout L = plain_layout(pr, sizeof(TR));
   char* w = static_cast<char*>(ws);
   TR* tab = reinterpret_cast<TR*>(w + L.off_tab);
@@ -229,7 +266,8 @@ hipError_t plain_forward_t(const PlainProblem& pr, const TR* params, const TR* p
   const int n = pr.enc.n;
   if (P == 0) return hipSuccess;
   if (ng > 0) hipLaunchKernelGGL(k_plain_gates<TR>, dim3(nblk(ng, 128)), dim3(128), 0, st, pr.gates_dev, ng, params, tab);
-  hipLaunchKernelGGL(k_plain_angles<TR>, dim3(nblk(P, 128)), dim3(128), 0, st, pr.enc, points, P, coord, (TR)delta, theta);
+  if (angles) theta = const_cast<TR*>(angles);   // angle-given encoding: the angles are the input
+  else hipLaunchKernelGGL(k_plain_angles<TR>, dim3(nblk(P, 128)), dim3(128), 0, st, pr.enc, points, P, coord, (TR)delta, theta);
   hipLaunchKernelGGL(k_plain_init<TR>, dim3(nblk(P << n, 256)), dim3(256), 0, st, n, pr.enc.gate, theta, P, s);
   for (int g = 0; g < ng; ++g) {
     const PlainGate G = pr.gates_host[g];
@@ -238,7 +276,18 @@ hipError_t plain_forward_t(const PlainProblem& pr, const TR* params, const TR* p
     else
       hipLaunchKernelGGL(k_plain_two<TR>, dim3(nblk(P << n, 256)), dim3(256), 0, st, n, G.kind, G.q0, G.q1, tab + g * 8, P, s);
   }
-  hipLaunchKernelGGL(k_plain_readout<TR>, dim3(nblk(P, 4)), dim3(256), 0, st, n, pr.m, pr.oq, P, s, f);
+  if (f) hipLaunchKernelGGL(k_plain_readout<TR>, dim3(nblk(P, 4)), dim3(256), 0, st, n, pr.m, pr.oq, P, s, f);
+  return hipGetLastError();
+}
+
+template <typename TR>
+hipError_t plain_bloch_t(const PlainProblem& pr, const TR* params, const TR* points, const TR* angles, TR* bloch, TR* mw,
+                         void* ws, hipStream_t st) {
+  hipError_t e = plain_forward_t<TR>(pr, params, points, -1, 0.0, nullptr, ws, st, angles);
+  if (e != hipSuccess || pr.P == 0) return e;
+  const PlainLayout L = plain_layout(pr, sizeof(TR));
+  const C2<TR>* s = reinterpret_cast<const C2<TR>*>(static_cast<char*>(ws) + L.off_state);
+  hipLaunchKernelGGL(k_plain_bloch<TR>, dim3(nblk(pr.P, 4)), dim3(256), 0, st, pr.enc.n, pr.P, s, bloch, mw);
   return hipGetLastError();
 }
 
@@ -309,6 +358,15 @@ hipError_t plain_eval(const PlainProblem& pr, int prec, const void* params, cons
   if (prec == 64)
     return plain_eval_t<double>(pr, (const double*)params, (const double*)points, h, (double*)out, (double*)tan, ws, st);
   return plain_eval_t<float>(pr, (const float*)params, (const float*)points, h, (float*)out, (float*)tan, ws, st);
+}
+
+hipError_t plain_bloch(const PlainProblem& pr, int prec, const void* params, const void* points, const void* angles,
+                       void* bloch, void* mw, void* ws, hipStream_t st) {
+  if (prec == 64)
+    return plain_bloch_t<double>(pr, (const double*)params, (const double*)points, (const double*)angles, (double*)bloch,
+                                 (double*)mw, ws, st);
+  return plain_bloch_t<float>(pr, (const float*)params, (const float*)points, (const float*)angles, (float*)bloch,
+                              (float*)mw, ws, st);
 }
 
 hipError_t plain_maxwell(const PlainProblem& pr, int prec, const void* params, const void* points, const qp_maxwell_desc& ld,

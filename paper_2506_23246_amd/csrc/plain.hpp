@@ -36,6 +36,10 @@ struct PlainLayout {
 PlainLayout plain_layout(const PlainProblem& pr, size_t real_bytes);
 hipError_t plain_eval(const PlainProblem& pr, int prec, const void* params, const void* points, double h,
                       void* out, void* tan, void* ws, hipStream_t st);
+// Per-qubit Bloch vectors [P][n][3] and Meyer-Wallach entanglement [P] (mw may be null) of the
+// output states; angles [P][n] replaces the point encoding when given.
+hipError_t plain_bloch(const PlainProblem& pr, int prec, const void* params, const void* points, const void* angles,
+                       void* bloch, void* mw, void* ws, hipStream_t st);
 hipError_t plain_maxwell(const PlainProblem& pr, int prec, const void* params, const void* points,
                          const qp_maxwell_desc& ld, int loss_sum, double h, double hp, int k0, int k1,
                          double* loss, void* dparams, void* ws, hipStream_t st);

@@ -116,6 +116,13 @@ class HybridQPINN(nn.Module):
         dfields = torch.einsum("fi,pic->pfc", self.head.weight, tan)
         return fields, dfields
 
+    def fields(self, points):
+        """Fields [P,3] alone (no input derivatives: the circuit gets a zero Jacobian)."""
+        theta = self.angles(points)
+        jac = torch.zeros(theta.shape + (3,), dtype=theta.dtype, device=theta.device)
+        out, _ = self.quantum(theta, jac)
+        return self.head(out.to(self.head.weight.dtype))
+
     def classical_parameter_count(self) -> int:
         return sum(p.numel() for n, p in self.named_parameters() if not n.startswith("quantum."))
 

@@ -4,6 +4,7 @@ Table of parameter counts up to the learned time period of its periodic input ma
 import math
 
 import numpy as np
+import pytest
 import torch
 
 import workloads as W
@@ -47,3 +48,26 @@ def test_hybrid_reference_forward_backward_runs():
     for name, p in model.named_parameters():
         if name != "head.bias":
             assert p.grad is not None and torch.isfinite(p.grad).all() and p.grad.abs().max() > 0, name
+
+
+def test_hybrid_total_loss_terms_are_the_oracle_formulas():
+    """The torch total loss of the hybrid model equals the oracle's total-loss function applied to
+    the same model's fields and derivatives at the four point sets (float64, CPU)."""
+    from oracle import qpinn_oracle as O
+    from paper_2506_23246_amd.hybrid import HybridQPINN
+    from paper_2506_23246_amd.train import hybrid_total_loss
+    circ = W.paper_context_circuit("basic")
+    model = HybridQPINN(circ, circuit_fn=oracle_circuit_fn(circ), dtype=torch.float64, seed=3)
+    rng = np.random.default_rng(5)
+    pts = torch.tensor(rng.uniform(-1, 1, (4, 3)))
+    xy = torch.tensor(rng.uniform(-1, 1, (3, 2)))
+    for kind in (W.LOSS_VACUUM, W.LOSS_DIEL_SPLIT):
+        desc = W.TotalLossDesc(phys=W.MaxwellDesc(kind, 4.0, 0.0))
+        t = hybrid_total_loss(model, pts, xy, desc)
+        f, g = (a.detach().numpy() for a in model(pts))
+        f_mx = model.fields(torch.tensor(O.mirror_points(pts.numpy(), 1))).detach().numpy()
+        f_my = model.fields(torch.tensor(O.mirror_points(pts.numpy(), 2))).detach().numpy()
+        f_ic = model.fields(torch.tensor(O.ic_points(xy.numpy()))).detach().numpy()
+        ref = O.total_loss(f, g, f_mx, f_my, f_ic, pts.numpy(), xy.numpy(), desc)
+        for k in ("total", "phys", "ic", "sym", "energy"):
+            assert float(t[k]) == pytest.approx(ref[k], rel=1e-10, abs=1e-14), (kind, k)

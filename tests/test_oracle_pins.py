@@ -763,3 +763,47 @@ def test_total_loss_gradient_matches_fd():
             pp[k] += h
             pm[k] -= h
             assert (L(pp) - L(pm)) / (2 * h) == pytest.approx(grad[k], rel=1e-8, abs=1e-8), (kind, k)
+
+
+# ------------------------------------------------------------------------- diagnostics --------
+
+def test_bloch_vectors_and_meyer_wallach_closed_forms():
+    """Product state after RY(theta_q) embeddings and RX(a_q): r_q = (sin th cos.., ...) by the Bloch
+    rotation; Meyer-Wallach 0 for every product state; GHZ (RY(pi/2) + CNOT chain) gives r = 0 on
+    every qubit and Q = 1; a Bell pair plus an untouched qubit gives Q = 2/3."""
+    n = 4
+    rng = np.random.default_rng(21)
+    th = rng.uniform(0, math.pi, (3, n))
+    a = rng.uniform(0, 2 * math.pi, n)
+    enc = W.Encoding(kind=W.ENC_ANGLES, gate=W.ENC_RY)
+    circ = _circ(n, [(W.RX, q, -1, q) for q in range(n)], n, enc=enc, out=list(range(n)))
+    r = O.bloch_vectors(circ, a, None, th, np.zeros((3, n, 3)))
+    # RY(th)|0> has r = (sin th, 0, cos th); RX(a) rotates about x: (x, y cos a - z sin a, y sin a + z cos a)
+    exp = np.stack([np.sin(th), -np.cos(th) * np.sin(a), np.cos(th) * np.cos(a)], -1)
+    np.testing.assert_allclose(r, exp, atol=1e-12)
+    np.testing.assert_allclose(O.meyer_wallach(circ, a, None, th, np.zeros((3, n, 3))), 0.0, atol=1e-12)
+    ghz = _circ(n, [(W.RY, 0, -1, 0)] + [(W.CNOT, q, q + 1, -1) for q in range(n - 1)], 1, enc=enc,
+                out=list(range(n)))
+    z = np.zeros((1, n))
+    np.testing.assert_allclose(O.bloch_vectors(ghz, [math.pi / 2], None, z, np.zeros((1, n, 3))), 0.0, atol=1e-12)
+    assert O.meyer_wallach(ghz, [math.pi / 2], None, z, np.zeros((1, n, 3)))[0] == pytest.approx(1.0, abs=1e-12)
+    bell = _circ(3, [(W.RY, 0, -1, 0), (W.CNOT, 0, 1, -1)], 1, enc=enc, out=[0, 1, 2])
+    z3 = np.zeros((1, 3))
+    assert O.meyer_wallach(bell, [math.pi / 2], None, z3, np.zeros((1, 3, 3)))[0] == pytest.approx(2 / 3, abs=1e-12)
+
+
+def test_energy_profile_and_black_hole_indicator():
+    """U(t) sums (eps E^2 + Hx^2 + Hy^2)/2 over the spatial grid per time slice: constant fields
+    (1, 2, 3) on a 4 x 5 grid give 4 * 5 * (1 + 4 + 9) / 2 = 140 per slice (eps = 1); with eps = 4 on
+    the points with x >= 0 those points count (4 + 4 + 9) / 2 each; I_BH of U = (2, 1.5, 0.2, 1) at
+    t = (0, 0.05, 0.5, 1) with delta = 0.1 is 1 - 0.2 / 2 = 0.9."""
+    t = np.array([0.0, 0.5, 1.0])
+    xg, yg = np.linspace(-1, 1, 4), np.linspace(-1, 1, 5)
+    pts = O.energy_grid(t, xg, yg)
+    assert pts.shape == (60, 3) and np.all(pts[:20, 0] == 0.0) and np.all(pts[40:, 0] == 1.0)
+    f = np.tile([1.0, 2.0, 3.0], (60, 1))
+    np.testing.assert_allclose(O.energy_from_fields(f, pts, 3, W.MaxwellDesc()), 140.0)
+    d = W.MaxwellDesc(W.LOSS_DIEL_SPLIT, 4.0, 0.0)
+    n_diel = int(np.sum(xg >= 0)) * 5
+    np.testing.assert_allclose(O.energy_from_fields(f, pts, 3, d), 0.5 * (n_diel * (4 + 13) + (20 - n_diel) * 14))
+    assert O.black_hole_indicator([2.0, 1.5, 0.2, 1.0], [0.0, 0.05, 0.5, 1.0], 0.1) == pytest.approx(0.9)
