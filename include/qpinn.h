@@ -151,6 +151,12 @@ int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
  * applies a choice cached by an earlier tuned run (QP_TUNE_CACHE) for the same circuit shape. */
 qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_planes, int32_t wg_per_cu);
 
+/* Points per chunk of the dense-block MFMA path (QP_FLAG_DENSE_MFMA), which streams the
+ * statevectors of one chunk of points through HBM at a time: 0 (default) sizes a chunk to about
+ * 2 GiB of statevectors; a smaller positive multiple of 64 caps it (more chunks, less workspace).
+ * Results do not depend on it beyond rounding order.  QP_EINVAL for other values.            */
+qp_status qp_circuit_set_dense_chunk(qp_circuit* c, int32_t points);
+
 /* Host-only introspection: builds the execution plan of `desc` without a device and copies its
  * device image (header, rounds, exchange descriptors, fused gates, gradient map) into host_buf
  * (capacity cap bytes); *bytes receives the image size.  QP_EWORKSPACE if cap is too small.  */

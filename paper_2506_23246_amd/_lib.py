@@ -63,6 +63,7 @@ _SIGS = {
     "qp_circuit_destroy": (None, [_P]),
     "qp_circuit_info": (C.c_int64, [_P, C.c_int32]),
     "qp_circuit_set_launch": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "qp_circuit_set_dense_chunk": (C.c_int, [_P, C.c_int32]),
     "qp_plan_image": (C.c_int, [C.POINTER(qp_circuit_desc), _P, C.c_size_t, C.POINTER(C.c_size_t)]),
     "qp_workspace_bytes": (C.c_size_t, [_P, C.c_int64, C.c_uint32]),
     "qp_simulate": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_size_t, C.c_uint32]),

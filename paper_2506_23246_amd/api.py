@@ -131,6 +131,9 @@ class Circuit:
     def set_launch(self, exchange_planes: int, wg_per_cu: int) -> None:
         L.check(L.qp_circuit_set_launch(self.h, int(exchange_planes), int(wg_per_cu)), self.ctx.h)
 
+    def set_dense_chunk(self, points: int) -> None:
+        L.check(L.qp_circuit_set_dense_chunk(self.h, int(points)), self.ctx.h)
+
     def workspace(self, P: int, flags: int = 0):
         nb = int(L.qp_workspace_bytes(self.h, int(P), int(flags) & L.QP_FLAG_DENSE_MFMA))
         key = ("ws", nb)

@@ -155,6 +155,14 @@ extern "C" qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_plane
   return QP_OK;
 }
 
+extern "C" qp_status qp_circuit_set_dense_chunk(qp_circuit* c, int32_t points) {
+  if (!c) return QP_EINVAL;
+  if (points < 0 || points % 64 != 0)
+    return fail(c->ctx, QP_EINVAL, "qp_circuit_set_dense_chunk: points must be 0 or a positive multiple of 64");
+  c->dense_chunk = points;
+  return QP_OK;
+}
+
 extern "C" qp_status qp_plan_image(const qp_circuit_desc* d, void* host_buf, size_t cap, size_t* bytes) {
   if (!d || !bytes) return QP_EINVAL;
   HostPlan hp;
@@ -255,7 +263,8 @@ static int dense_nwg(const qp_ctx* ctx, const qp_circuit* c, int Pc) {
 }
 
 static DenseLayout dense_ws(const qp_circuit* c, int64_t P, bool grad, int* Pc_out, int* nwg_out) {
-  const int Pc = dense_chunk(c->hp.n, P, grad);
+  int Pc = dense_chunk(c->hp.n, P, grad);
+  if (c->dense_chunk > 0 && c->dense_chunk < Pc) Pc = c->dense_chunk;
   const int nwg = dense_nwg(c->ctx, c, Pc);
   if (Pc_out) *Pc_out = Pc;
   if (nwg_out) *nwg_out = nwg;

@@ -30,6 +30,7 @@ struct qp_circuit {
   qp::PlainGate* dpgates = nullptr;
   int exs = 4;         // exchange planes per LDS phase
   int wg_per_cu = 1;   // persistent workgroups per CU
+  int dense_chunk = 0; // points per chunk of the dense-block path (0: about 2 GiB of statevectors)
 };
 
 namespace qp {

@@ -415,6 +415,131 @@ __global__ __launch_bounds__(256) void k_dense_mgemm(const QPlanDev* __restrict_
   }
 }
 
+// Adjoint of block g in one pass over the eight statevectors of the chunk (replaces an
+// uncompute pass over psi, the product pass and a pull-back pass over lambda: 16 statevector
+// transfers per block instead of 24).  Per (other-index, 64-point) tile and pair s = 0..3 the
+// tiles of psi_s and lambda_s, both at the block output, are staged in LDS; waves 0 and 1
+// uncompute psi_s <- B^H psi_s for 32 points each, writing the result to HBM and over the psi
+// tile; waves 2 and 3 pull lambda_s <- B^H lambda_s back from the staged tile and write it to HBM;
+// then every wave adds conj(lambda_out) psi_in^T over 16 of the tile's columns to its M
+// accumulators (M taken with psi at the block input and lambda at its output).  At the end the
+// four waves are combined in a fixed order into the workgroup's slot of mpart.
+__global__ __launch_bounds__(256) void k_dense_adj(const QPlanDev* __restrict__ plan, const float* __restrict__ tab,
+                                                   int g, float2* __restrict__ X, int Pc, float* __restrict__ mpart,
+                                                   int nwg) {
+  constexpr int LD = 65;   // padded row stride (float2)
+  __shared__ float2 sm[2 * 32 * LD];   // lambda tile, psi tile; reused for the wave combine
+  __shared__ float sa[2 * 32 * 64];    // the block's A-operands (read per k-step: frees 64 VGPRs a lane)
+  float2* tl = sm;
+  float2* tp = sm + 32 * LD;
+  float* red = reinterpret_cast<float*>(sm);
+  const int n = plan->n;
+  const QDenseGroup* G = dgroup(plan, g);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, c = lane & 31;
+  const int JO = 1 << (n - 5);
+  const int PT = (Pc + 63) / 64;
+  const long long DIM = 1ll << n;
+  int pos[5];
+  uint32_t free_mask = (1u << n) - 1;
+  for (int b = 0; b < 5; ++b) { pos[b] = G->pos[b]; free_mask &= ~(1u << pos[b]); }
+  const float* tg = tab + (size_t)g * 4096;
+  for (int e = tid; e < 4096; e += 256) sa[e] = tg[e];
+  f32x16 mr, mi;
+  for (int v = 0; v < 16; ++v) { mr[v] = 0.f; mi[v] = 0.f; }
+  const int lrow = tid >> 3, lcol = (tid & 7) * 8;   // tile loader: row = amplitude, 8 points each
+  uint32_t lboff = 0;
+  for (int b = 0; b < 5; ++b) lboff |= ((uint32_t)(lrow >> b) & 1u) << pos[b];
+  const bool is_psi = wave < 2;
+  const int c0 = (wave & 1) * 32;     // the 32 tile columns this wave applies the block to
+  float2* T = is_psi ? tp : tl;
+  for (long long t = blockIdx.x; t < (long long)JO * PT; t += gridDim.x) {
+    const int pt = (int)(t % PT), jo = (int)(t / PT);
+    uint32_t jb = 0;
+    {
+      uint32_t m = free_mask, x = (uint32_t)jo;
+      for (int k = 0; k < n; ++k)
+        if ((m >> k) & 1u) { jb |= (x & 1u) << k; x >>= 1; }
+    }
+    const int p = pt * 64 + c0 + c;
+    const bool ok = p < Pc;
+    for (int s = 0; s < 4; ++s) {
+      const float2* Ls = X + ((size_t)(4 + s) * DIM + (jb | lboff)) * Pc;
+      const float2* Ps = X + ((size_t)s * DIM + (jb | lboff)) * Pc;
+      __syncthreads();
+      for (int e = 0; e < 8; ++e) {
+        const int q = pt * 64 + lcol + e;
+        tl[lrow * LD + lcol + e] = q < Pc ? Ls[q] : make_float2(0.f, 0.f);
+        tp[lrow * LD + lcol + e] = q < Pc ? Ps[q] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      {   // B^H on 32 columns of the psi tile (waves 0, 1) or of the lambda tile (waves 2, 3)
+        float bv[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+          const float2 v = T[i * LD + c0 + c];
+          bv[i] = h ? v.y : v.x;
+        }
+        f32x16 acc0, acc1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; }
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv[i], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i) * 64 + lane], bv[i], acc1, 0, 0, 0);
+        }
+        float2* dst = X + (size_t)(is_psi ? s : 4 + s) * DIM * Pc;
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int m = 8 * (v >> 2) + 4 * h + (v & 3);   // even real row = 2 * amplitude
+          const int a0 = m >> 1, a1 = 16 + (m >> 1);
+          uint32_t o0 = 0, o1 = 0;
+          for (int b = 0; b < 5; ++b) {
+            o0 |= ((uint32_t)(a0 >> b) & 1u) << pos[b];
+            o1 |= ((uint32_t)(a1 >> b) & 1u) << pos[b];
+          }
+          const float2 r0 = make_float2(acc0[v], acc0[v + 1]), r1 = make_float2(acc1[v], acc1[v + 1]);
+          if (ok) {
+            dst[(size_t)(jb | o0) * Pc + p] = r0;
+            dst[(size_t)(jb | o1) * Pc + p] = r1;
+          }
+          if (is_psi) {   // psi_in replaces psi_out in the tile for the product below
+            tp[a0 * LD + c0 + c] = r0;
+            tp[a1 * LD + c0 + c] = r1;
+          }
+        }
+      }
+      __syncthreads();
+      const int a = lane & 31;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int col = wave * 16 + 2 * kk + h;
+        const float2 lv = tl[a * LD + col], pv = tp[a * LD + col];
+        // Mr += Lr Pr + Li Pi ; Mi += Lr Pi - Li Pr   (A[m=a][k=col], B[k=col][n=b])
+        mr = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.x, pv.x, mr, 0, 0, 0);
+        mr = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.y, pv.y, mr, 0, 0, 0);
+        mi = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.x, pv.y, mi, 0, 0, 0);
+        mi = __builtin_amdgcn_mfma_f32_32x32x2f32(-lv.y, pv.x, mi, 0, 0, 0);
+      }
+    }
+  }
+  // combine the four waves (fixed order) and add to this workgroup's slot
+  __syncthreads();
+  for (int v = 0; v < 16; ++v) {
+    red[((wave * 2 + 0) * 16 + v) * 64 + lane] = mr[v];
+    red[((wave * 2 + 1) * 16 + v) * 64 + lane] = mi[v];
+  }
+  __syncthreads();
+  float* slot = mpart + ((size_t)g * nwg + blockIdx.x) * 2048;
+  for (int e = tid; e < 2 * 16 * 64; e += 256) {
+    const int part = e / 1024, v = (e / 64) % 16, l = e % 64;
+    float sum = 0.f;
+    for (int wv = 0; wv < 4; ++wv) sum += red[((wv * 2 + part) * 16 + v) * 64 + l];
+    const int row = 8 * (v >> 2) + 4 * (l >> 5) + (v & 3), col = l & 31;   // M[a = row][b = col]
+    slot[part * 1024 + row * 32 + col] += sum;
+  }
+}
+
 __global__ void k_dense_zero(float* __restrict__ p, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -546,11 +671,8 @@ hipError_t dense_run(const DenseCall& c, hipStream_t st) {
                        c.grad ? seeds : nullptr, c.grad ? lterm : nullptr);
     if (!c.grad) continue;
     hipLaunchKernelGGL(k_dense_lambda, dim3(nb(DIM * Pc, 256)), dim3(256), 0, st, plan, seeds, Pc, X);
-    for (int g = G - 1; g >= 0; --g) {
-      hipLaunchKernelGGL(k_dense_apply, dim3(apply_grid), dim3(256), 0, st, plan, tabA, g, X, 0, 4, Pc);
-      hipLaunchKernelGGL(k_dense_mgemm, dim3(c.nwg), dim3(256), 0, st, plan, g, X, Pc, mpart, c.nwg);
-      hipLaunchKernelGGL(k_dense_apply, dim3(apply_grid), dim3(256), 0, st, plan, tabA, g, X, 4, 4, Pc);
-    }
+    for (int g = G - 1; g >= 0; --g)
+      hipLaunchKernelGGL(k_dense_adj, dim3(c.nwg), dim3(256), 0, st, plan, tabA, g, X, Pc, mpart, c.nwg);
   }
   if (!c.grad) return hipGetLastError();
   const long long cols = (long long)G * 2048 + 1;

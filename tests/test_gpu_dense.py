@@ -100,3 +100,21 @@ def test_dense_matches_fused_on_c5_chunked(ctx):
     report("dense vs fused c5 P=20000", **e)
     for key, v in e.items():
         assert v < 2 * TOL, (key, v)
+
+
+@pytest.mark.parametrize("name,chunk", [("c5_first4096", 1024), ("c5_first4096", 0), ("c3_first16384", 4096)])
+def test_dense_multi_chunk_against_stored_oracle(ctx, name, chunk):
+    """Several point chunks through HBM (chunk 1024 or 4096: four chunks) and the default chunk:
+    outputs, tangents, loss and gradient against the stored oracle results of the whole set."""
+    from tests.golden.make_oracle_fixtures import SETS, load
+    w = SETS[name]()
+    ref = load(name)
+    c = _circ(ctx, w.circuit)
+    c.set_dense_chunk(chunk)
+    r = c.maxwell(w.params, w.points, w.loss, flags=_flags())
+    idx = ref["idx"]
+    e = dict(f=rel(t2n(r["out"])[idx], ref["f"]), g=rel(t2n(r["tan"])[idx], ref["g"]),
+             loss=rel(t2n(r["loss"]), [float(ref["loss"])]), grad=rel(t2n(r["grad"]), ref["grad"]))
+    report(f"dense stored oracle {name} chunk {chunk}", **e)
+    for key, v in e.items():
+        assert v < TOL, (key, v)
