@@ -52,19 +52,29 @@ def executed_flops_per_point(n_fused: int, n: int, n_folded: int = 0) -> float:
     return (2 ** n) * (float(n_fused) * 216 - float(n_folded) * 168)
 
 
-def sources_digest() -> str:
-    """SHA-256 of the library sources (kernels, planner, C ABI); hardware counters recorded for one
-    digest do not describe a library built from other sources."""
+# Sources that determine each kernel's code and memory accesses (device code and the planner
+# that writes its plan image).  A counter record taken for one digest does not describe a kernel
+# built from other sources.
+KERNEL_SOURCES = {
+    "k_fused": ["fused_kernel.hpp", "fused.hip", "fused.hpp", "fused_n*.hip", "qp_internal.hpp", "grads_dev.hpp",
+                "rot_dev.hpp", "plan.cpp", "plan.hpp"],
+    "k_batch": ["batch.hip", "batch.hpp", "batch_api.cpp", "fused_kernel.hpp", "fused.hpp", "qp_internal.hpp",
+                "grads_dev.hpp", "rot_dev.hpp", "plan.cpp", "plan.hpp"],
+}
+
+
+def sources_digest(kernel: str = "k_fused") -> str:
+    """SHA-256 of the sources behind `kernel` (KERNEL_SOURCES)."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2506_23246_amd", "csrc", "*")))
-    files.append(os.path.join(ROOT, "include", "qpinn.h"))
-    for f in files:
-        if os.path.isfile(f):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    files = []
+    for pat in KERNEL_SOURCES[kernel]:
+        files += glob.glob(os.path.join(ROOT, "paper_2506_23246_amd", "csrc", pat))
+    for f in sorted(set(files)):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -73,7 +83,7 @@ def recorded_traffic(kernel: str, workload: str):
     profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's readings), or None when there
     is no record for the current sources."""
     import glob
-    digest = sources_digest()
+    digest = sources_digest(kernel)
     for path in sorted(glob.glob(os.path.join(PROFILES, "*hbm_counters*.md"))):
         with open(path) as fh:
             for ln in fh:

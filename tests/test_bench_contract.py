@@ -47,16 +47,21 @@ def test_recorded_traffic_needs_kernel_workload_and_sources_to_match(tmp_path, m
     (tmp_path / "k_fused_w12_hbm_counters.md").write_text(
         "# counters\n| a | b |\n" + json.dumps(rec) + "\n" + "{not json\n")
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
-    monkeypatch.setattr(bench, "sources_digest", lambda: "digest-a")
+    monkeypatch.setattr(bench, "sources_digest", lambda kernel="k_fused": "digest-a")
     value, src = bench.recorded_traffic("k_fused", "w12")
     assert value == 1234 and src.endswith("k_fused_w12_hbm_counters.md")
     assert bench.recorded_traffic("k_batch", "w12") == (None, None)
     assert bench.recorded_traffic("k_fused", "w6") == (None, None)
-    monkeypatch.setattr(bench, "sources_digest", lambda: "digest-b")
+    monkeypatch.setattr(bench, "sources_digest", lambda kernel="k_fused": "digest-b")
     assert bench.recorded_traffic("k_fused", "w12") == (None, None)
 
 
 def test_sources_digest_covers_the_library_sources():
     d = bench.sources_digest()
     assert len(d) == 64 and int(d, 16) >= 0
-    assert d == bench.sources_digest()
+    assert d == bench.sources_digest("k_fused")
+    assert bench.sources_digest("k_batch") != d
+    for kernel, pats in bench.KERNEL_SOURCES.items():
+        import glob
+        for pat in pats:
+            assert glob.glob(os.path.join(ROOT, "paper_2506_23246_amd", "csrc", pat)), (kernel, pat)
