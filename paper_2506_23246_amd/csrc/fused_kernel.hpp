@@ -650,12 +650,19 @@ __device__ __forceinline__ float enc_pair(float nx, float ny, float nz, float sb
   return nx * im_p + sb * (ny * re_p - nz * im_o);
 }
 
+// One of two passes (PASS 0: partners of psi and dpsi_t; PASS 1: of dpsi_x and dpsi_y).  The
+// qubits are taken one at a time (a loop, so no per-qubit register arrays), each qubit's sums are
+// reduced over the point's threads at once, and the point's first thread writes them (PASS 0) or
+// adds its share (PASS 1).
 template <int N, int T, int PASS>
 __device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const float (&si)[8][8],
-                                              float2* __restrict__ buf, CP<QPlanDev> plan, CP<QRound> r0,
-                                              CP<float> gtab, uint32_t jl, float (&at)[N], float (&aj)[N][3]) {
+                                              float2* __restrict__ buf, float* __restrict__ red, CP<QPlanDev> plan,
+                                              CP<QRound> r0, CP<float> gtab, uint32_t jl, const FusedArgs& a,
+                                              long long pt, bool valid, uint32_t u) {
   constexpr int PLANE = T * 8;
+  constexpr int TP = 1 << (N - 3);
   const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const uint32_t l0 = r0->tpos[0], l1 = r0->tpos[1], l2 = r0->tpos[2];
   __syncthreads();   // the planes are free (every wave is past its last read of the sweep)
 #pragma unroll
@@ -666,7 +673,7 @@ __device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const flo
   }
   __syncthreads();
   const bool rx = plan->enc_gate == QP_ENC_RX;
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < N; ++q) {
     const int pos = N - 1 - q;
     uint32_t rmask = 0, tmask = 0;
@@ -678,27 +685,26 @@ __device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const flo
       }
     }
     // axis of U G U^H (U: the opening-stage gate on q, identity if none; G = X or Y)
-    float u[8] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+    float u8[8] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
     const int hg = plan->head_gate[q];
     if (hg >= 0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) u[i] = gtab[hg * kGT + i];
+      for (int i = 0; i < 8; ++i) u8[i] = gtab[hg * kGT + i];
     }
     // W = U G: X swaps U's columns; Y gives [[i u01, -i u00], [i u11, -i u10]]
-    float w00r, w00i, w01r, w01i, w10r, w10i, w11r, w11i;
+    float w00r, w00i, w01r, w01i;
     if (rx) {
-      w00r = u[2]; w00i = u[3]; w01r = u[0]; w01i = u[1];
-      w10r = u[6]; w10i = u[7]; w11r = u[4]; w11i = u[5];
+      w00r = u8[2]; w00i = u8[3]; w01r = u8[0]; w01i = u8[1];
     } else {
-      w00r = -u[3]; w00i = u[2]; w01r = u[1]; w01i = -u[0];
-      w10r = -u[7]; w10i = u[6]; w11r = u[5]; w11i = -u[4];
+      w00r = -u8[3]; w00i = u8[2]; w01r = u8[1]; w01i = -u8[0];
     }
     // M = W U^H: M00 = W00 conj(u00) + W01 conj(u01), M01 = W00 conj(u10) + W01 conj(u11)
-    const float m00r = w00r * u[0] + w00i * u[1] + w01r * u[2] + w01i * u[3];
-    const float m01r = w00r * u[4] + w00i * u[5] + w01r * u[6] + w01i * u[7];
-    const float m01i = w00i * u[4] - w00r * u[5] + w01i * u[6] - w01r * u[7];
+    const float m00r = w00r * u8[0] + w00i * u8[1] + w01r * u8[2] + w01i * u8[3];
+    const float m01r = w00r * u8[4] + w00i * u8[5] + w01r * u8[6] + w01i * u8[7];
+    const float m01i = w00i * u8[4] - w00r * u8[5] + w01i * u8[6] - w01r * u8[7];
     const float nx = m01r, ny = -m01i, nz = m00r;
     const uint32_t ptid = tid ^ tmask;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const uint32_t j = jl ^ reg_off(r, l0, l1, l2);
@@ -707,14 +713,56 @@ __device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const flo
       const float2 y0 = buf[e];
       const float2 y1 = buf[PLANE + e];
       if (PASS == 0) {   // partners of psi and dpsi_t
-        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[4][r], si[4][r], sr[0][r], si[0][r], y0);
-        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[5][r], si[5][r], sr[1][r], si[1][r], y1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          aj[q][c] += enc_pair<N, T>(nx, ny, nz, sb, sr[5 + c][r], si[5 + c][r], sr[0][r], si[0][r], y0);
+        s0 += enc_pair<N, T>(nx, ny, nz, sb, sr[4][r], si[4][r], sr[0][r], si[0][r], y0);
+        s0 += enc_pair<N, T>(nx, ny, nz, sb, sr[5][r], si[5][r], sr[1][r], si[1][r], y1);
+        s1 += enc_pair<N, T>(nx, ny, nz, sb, sr[5][r], si[5][r], sr[0][r], si[0][r], y0);
+        s2 += enc_pair<N, T>(nx, ny, nz, sb, sr[6][r], si[6][r], sr[0][r], si[0][r], y0);
+        s3 += enc_pair<N, T>(nx, ny, nz, sb, sr[7][r], si[7][r], sr[0][r], si[0][r], y0);
       } else {           // partners of dpsi_x and dpsi_y
-        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[6][r], si[6][r], sr[2][r], si[2][r], y0);
-        at[q] += enc_pair<N, T>(nx, ny, nz, sb, sr[7][r], si[7][r], sr[3][r], si[3][r], y1);
+        s0 += enc_pair<N, T>(nx, ny, nz, sb, sr[6][r], si[6][r], sr[2][r], si[2][r], y0);
+        s0 += enc_pair<N, T>(nx, ny, nz, sb, sr[7][r], si[7][r], sr[3][r], si[3][r], y1);
+      }
+    }
+    // sum over the point's threads
+#pragma unroll
+    for (int off = 1; off < (TP < 64 ? TP : 64); off <<= 1) {
+      s0 += __shfl_xor(s0, off);
+      if (PASS == 0) {
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+        s3 += __shfl_xor(s3, off);
+      }
+    }
+    if (TP > 64) {   // the point spans TP / 64 waves: combine them through the scratch slots
+      constexpr int WPP = TP > 64 ? TP / 64 : 1;
+      if (lane == 0) {
+        red[wave * 40 + 0] = s0;
+        red[wave * 40 + 1] = s1;
+        red[wave * 40 + 2] = s2;
+        red[wave * 40 + 3] = s3;
+      }
+      __syncthreads();
+      const int w0 = (wave / WPP) * WPP;
+      float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+      for (int w = 0; w < WPP; ++w) {
+        t0 += red[(w0 + w) * 40 + 0];
+        t1 += red[(w0 + w) * 40 + 1];
+        t2 += red[(w0 + w) * 40 + 2];
+        t3 += red[(w0 + w) * 40 + 3];
+      }
+      s0 = t0; s1 = t1; s2 = t2; s3 = t3;
+      __syncthreads();
+    }
+    if (valid && u == 0) {
+      if (PASS == 0) {
+        if (a.d_angles) a.d_angles[pt * N + q] = s0;
+        if (a.d_jac) {
+          a.d_jac[(pt * N + q) * 3 + 0] = s1;
+          a.d_jac[(pt * N + q) * 3 + 1] = s2;
+          a.d_jac[(pt * N + q) * 3 + 2] = s3;
+        }
+      } else if (a.d_angles) {
+        a.d_angles[pt * N + q] += s0;
       }
     }
   }
@@ -722,72 +770,20 @@ __device__ __forceinline__ void enc_grad_pass(const float (&sr)[8][8], const flo
 
 template <int N, int T>
 __device__ __forceinline__ void encoding_grads(const float (&sr)[8][8], const float (&si)[8][8],
-                                               float2* __restrict__ buf, CP<QPlanDev> plan, CP<QRound> r0,
-                                               CP<float> gtab, const FusedArgs& a, long long pt, bool valid,
-                                               uint32_t u) {
-  constexpr int TP = 1 << (N - 3);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
+                                               float2* __restrict__ buf, float* __restrict__ red, CP<QPlanDev> plan,
+                                               CP<QRound> r0, CP<float> gtab, const FusedArgs& a, long long pt,
+                                               bool valid, uint32_t u) {
   const uint32_t jl = deposit_thread<N>(u, r0->tpos);
-  float at[N], aj[N][3];
-#pragma unroll
-  for (int q = 0; q < N; ++q) { at[q] = 0.f; aj[q][0] = aj[q][1] = aj[q][2] = 0.f; }
-  enc_grad_pass<N, T, 0>(sr, si, buf, plan, r0, gtab, jl, at, aj);
-  enc_grad_pass<N, T, 1>(sr, si, buf, plan, r0, gtab, jl, at, aj);
-  // sum over the point's threads
-#pragma unroll
-  for (int off = 1; off < (TP < 64 ? TP : 64); off <<= 1) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      at[q] += __shfl_xor(at[q], off);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) aj[q][c] += __shfl_xor(aj[q][c], off);
-    }
-  }
-  if (TP > 64) {     // the point spans TP / 64 waves: combine them through LDS
-    float* fb = reinterpret_cast<float*>(buf);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        fb[wave * 4 * N + 4 * q] = at[q];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fb[wave * 4 * N + 4 * q + 1 + c] = aj[q][c];
-      }
-    }
-    __syncthreads();
-    constexpr int WPP = TP / 64;
-    const int w0 = (wave / WPP) * WPP;
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-      for (int w = 0; w < WPP; ++w) {
-        s0 += fb[(w0 + w) * 4 * N + 4 * q];
-        s1 += fb[(w0 + w) * 4 * N + 4 * q + 1];
-        s2 += fb[(w0 + w) * 4 * N + 4 * q + 2];
-        s3 += fb[(w0 + w) * 4 * N + 4 * q + 3];
-      }
-      at[q] = s0; aj[q][0] = s1; aj[q][1] = s2; aj[q][2] = s3;
-    }
-  }
-  if (valid && u == 0) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      if (a.d_angles) a.d_angles[pt * N + q] = at[q];
-      if (a.d_jac) {
-        a.d_jac[(pt * N + q) * 3 + 0] = aj[q][0];
-        a.d_jac[(pt * N + q) * 3 + 1] = aj[q][1];
-        a.d_jac[(pt * N + q) * 3 + 2] = aj[q][2];
-      }
-    }
-  }
+  enc_grad_pass<N, T, 0>(sr, si, buf, red, plan, r0, gtab, jl, a, pt, valid, u);
+  enc_grad_pass<N, T, 1>(sr, si, buf, red, plan, r0, gtab, jl, a, pt, valid, u);
   __syncthreads();   // the next tile's first exchange writes the planes
 }
 
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
-template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false>
+// PH: the plan may carry CRZ phase stages (false for the uneven-batch kernel, whose circuits have
+// none: the phase code is then compiled out).
+template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false, bool PH = true>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ mslots,
                                            float* __restrict__ red, float& lacc) {
@@ -953,7 +949,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = H; k < R; ++k) {
         CP<QRound> rk = rounds + k;
         if (k > 0) exchange<N, T, 4, 2>(sr, si, buf, xf + k, lane_words(lanes, 0, R, k, TP, u, pb8));
-        if (rk->phase >= 0) {   // CRZ phase stage after the exchange (unpipelined kernel only)
+        if (PH && rk->phase >= 0) {   // CRZ phase stage after the exchange (unpipelined kernel only)
           float pc[8], ps[8];
           phase_factors<N>(rk, pcoef + to_const(pstages)[rk->phase].coef_off, u, pc, ps);
           apply_phase<0, 4, false>(sr, si, pc, ps);
@@ -1181,7 +1177,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       for (int k = R - 1; k >= H; --k) {
         CP<QRound> rk = rounds + k;
         round_adj_all<NS, true>(sr, si, rk, gtab, F, slots, wave, lane);
-        if (rk->phase >= 0) {   // CRZ phase stage: moments at its output, then uncompute and pull back
+        if (PH && rk->phase >= 0) {   // CRZ phase stage: moments at its output, then uncompute and pull back
           CP<QPhaseStage> pst = to_const(pstages) + rk->phase;
           phase_moments<N>(sr, si, rk, u, mslots + wave * a.n_mom + pst->mom_off, lane);
           float pc[8], ps[8];
@@ -1196,7 +1192,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
     }
-    if constexpr (EG) encoding_grads<N, T>(sr, si, buf, plan, rounds, gtab, a, pt, valid, u);
+    if constexpr (EG) encoding_grads<N, T>(sr, si, buf, red, plan, rounds, gtab, a, pt, valid, u);
   }
 }
 
