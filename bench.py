@@ -255,7 +255,8 @@ def main():
         if args.tune:
             batch.run(arr, W.MaxwellDesc(W.LOSS_VACUUM), flags=L.QP_FLAG_TUNE)
         cfg = {"workload": W.CONFIG_NAMES[3], "circuits": len(ws_list), "points_total": P_total,
-               "grid": batch.info(2), "work_items": batch.info(1)}
+               "work_items": batch.info(1), "work_items_3_to_8_qubits": batch.info(4),
+               "grids_3_to_8_and_9_to_11_qubits": [batch.info(5), batch.info(6)]}
         w = None
     else:
         w = W.config(k)

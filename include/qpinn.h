@@ -301,7 +301,12 @@ qp_status qp_batch_run(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
 qp_status qp_batch_graph_launch(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
                                 const qp_maxwell_desc* loss_desc, void* ws, size_t ws_bytes,
                                 uint32_t flags);
-/* what: 0 circuits, 1 work items, 2 grid size in use, 3 graph captured (0/1) */
+/* what: 0 circuits, 1 work items, 2 persistent grid when one qubit-count class has work, 3 graph
+ * captured (0/1), 4 work items of the low class (3..8 qubits), 5 and 6 the grids of the low and
+ * high class (9..11 qubits) when both have work: the classes then run as two kernels at once on
+ * two streams.  By default the high class runs on 2 workgroups per CU and the low class's
+ * workgroups come on top (1.25 x its share of estimated work); QP_FLAG_TUNE also times
+ * grids of 1..3 workgroups per CU, other shares and an even split of one grid.             */
 int64_t qp_batch_info(const qp_batch* b, int32_t what);
 
 /* ---- plain baseline (the speedup denominator) -----------------------------------------

@@ -23,7 +23,7 @@ constexpr int kBEXS = 2;
 __global__ void k_batch_gates(const BatchCirc* __restrict__ circs, const BatchGate* __restrict__ gates, int ngates,
                               int* __restrict__ counter) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g == 0) *counter = 0;
+  if (g == 0) { counter[0] = 0; counter[1] = 0; }   // one work counter per qubit-count class
   if (g >= ngates) return;
   const BatchGate G = gates[g];
   const BatchCirc& C = circs[G.circ];
@@ -67,9 +67,13 @@ template <int N>
 __device__ __forceinline__ void batch_tiles(const BatchCirc& C, const BatchItem& it, float2* buf, float* slots,
                                             float* red, float& lacc) {
   for (int t = it.tile0; t < it.tile0 + it.ntile; ++t)
-    fused_tile<N, kBT, kBEXS, kModeMaxwell>(C.a, t, buf, slots, nullptr, red, lacc);
+    fused_tile<N, kBT, kBEXS, kModeMaxwell, true, false, false>(C.a, t, buf, slots, nullptr, red, lacc);
 }
 
+// One kernel per class of qubit counts [NLO, NHI]: each class's tile code gets its own register
+// allocation (all counts 3..11 in one function exceeded the 256-VGPR cap and spilled 128 bytes a
+// lane, whose scratch traffic doubled the kernel's HBM bytes; 3..8 and 9..11 each fit).
+template <int NLO, int NHI>
 __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ circs, const BatchItem* __restrict__ items,
                                                int nitems, int* __restrict__ counter, float* __restrict__ mpart,
                                                float* __restrict__ lpart) {
@@ -95,15 +99,15 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchCirc* __restrict__ 
     __syncthreads();
     float lacc = 0.f;
     switch (C.n) {
-      case 3: batch_tiles<3>(C, it, buf, slots, red, lacc); break;
-      case 4: batch_tiles<4>(C, it, buf, slots, red, lacc); break;
-      case 5: batch_tiles<5>(C, it, buf, slots, red, lacc); break;
-      case 6: batch_tiles<6>(C, it, buf, slots, red, lacc); break;
-      case 7: batch_tiles<7>(C, it, buf, slots, red, lacc); break;
-      case 8: batch_tiles<8>(C, it, buf, slots, red, lacc); break;
-      case 9: batch_tiles<9>(C, it, buf, slots, red, lacc); break;
-      case 10: batch_tiles<10>(C, it, buf, slots, red, lacc); break;
-      case 11: batch_tiles<11>(C, it, buf, slots, red, lacc); break;
+      case 3: if (NLO <= 3 && 3 <= NHI) batch_tiles<3>(C, it, buf, slots, red, lacc); break;
+      case 4: if (NLO <= 4 && 4 <= NHI) batch_tiles<4>(C, it, buf, slots, red, lacc); break;
+      case 5: if (NLO <= 5 && 5 <= NHI) batch_tiles<5>(C, it, buf, slots, red, lacc); break;
+      case 6: if (NLO <= 6 && 6 <= NHI) batch_tiles<6>(C, it, buf, slots, red, lacc); break;
+      case 7: if (NLO <= 7 && 7 <= NHI) batch_tiles<7>(C, it, buf, slots, red, lacc); break;
+      case 8: if (NLO <= 8 && 8 <= NHI) batch_tiles<8>(C, it, buf, slots, red, lacc); break;
+      case 9: if (NLO <= 9 && 9 <= NHI) batch_tiles<9>(C, it, buf, slots, red, lacc); break;
+      case 10: if (NLO <= 10 && 10 <= NHI) batch_tiles<10>(C, it, buf, slots, red, lacc); break;
+      case 11: if (NLO <= 11 && 11 <= NHI) batch_tiles<11>(C, it, buf, slots, red, lacc); break;
       default: break;
     }
     __syncthreads();
@@ -167,21 +171,42 @@ size_t batch_lds_bytes(int max_fused) {   // static exchange planes + dynamic pa
 hipError_t batch_prepare(int max_fused) {
   const size_t lds = batch_dyn_lds_bytes(max_fused);
   if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_batch<3, kBatchSplit>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_batch<kBatchSplit + 1, 11>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* items, int nitems,
-                        const BatchGate* gates, int ngates, const BatchCol* cols, int ncols,
-                        const BatchGate* pars, int npars, int* counter, float* mpart, float* lpart,
-                        int grid, int max_fused, int count_needed, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1) {
+hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* items, int nitems, int nitems_lo,
+                        const BatchGate* gates, int ngates, const BatchCol* cols, int ncols, const BatchGate* pars,
+                        int npars, int* counter, float* mpart, float* lpart, int grid, int grid_lo, int grid_hi,
+                        int max_fused, int count_needed, hipStream_t st, hipStream_t aux, hipEvent_t ev_fork,
+                        hipEvent_t ev_join, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(k_batch_gates, dim3(ngates > 0 ? (ngates + 127) / 128 : 1), dim3(128), 0, st,
                      circs, gates, ngates, counter);
   if (count_needed) hipLaunchKernelGGL(k_batch_counts, dim3(ncirc), dim3(256), 0, st, circs);
   if (ev0) hipEventRecord(ev0, st);
-  if (grid > 0 && nitems > 0)
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBT), batch_dyn_lds_bytes(max_fused), st, circs, items, nitems,
-                       counter, mpart, lpart);
+  // The items of each class are contiguous (the low class first), each in longest-first order.
+  // When both classes have work the two kernels run at once on two streams with their own
+  // persistent grids (grid_lo, grid_hi); otherwise the one class runs on `grid`.
+  const int nitems_hi = nitems - nitems_lo;
+  const size_t dyn = batch_dyn_lds_bytes(max_fused);
+  if (grid_lo > 0 && grid_hi > 0 && nitems_lo > 0 && nitems_hi > 0 && aux) {
+    hipEventRecord(ev_fork, st);
+    hipStreamWaitEvent(aux, ev_fork, 0);
+    hipLaunchKernelGGL((k_batch<3, kBatchSplit>), dim3(grid_lo), dim3(kBT), dyn, st, circs, items, nitems_lo, counter,
+                       mpart, lpart);
+    hipLaunchKernelGGL((k_batch<kBatchSplit + 1, 11>), dim3(grid_hi), dim3(kBT), dyn, aux, circs, items + nitems_lo,
+                       nitems_hi, counter + 1, mpart, lpart);
+    hipEventRecord(ev_join, aux);
+    hipStreamWaitEvent(st, ev_join, 0);
+  } else {
+    if (grid > 0 && nitems_lo > 0)
+      hipLaunchKernelGGL((k_batch<3, kBatchSplit>), dim3(grid), dim3(kBT), dyn, st, circs, items, nitems_lo, counter,
+                         mpart, lpart);
+    if (grid > 0 && nitems_hi > 0)
+      hipLaunchKernelGGL((k_batch<kBatchSplit + 1, 11>), dim3(grid), dim3(kBT), dyn, st, circs, items + nitems_lo,
+                         nitems_hi, counter + 1, mpart, lpart);
+  }
   if (ev1) hipEventRecord(ev1, st);
   hipLaunchKernelGGL(k_batch_reduce, dim3((ncols + 3) / 4), dim3(256), 0, st, circs, cols, ncols, mpart, lpart);
   if (npars > 0) hipLaunchKernelGGL(k_batch_grads, dim3((npars + 127) / 128), dim3(128), 0, st, circs, pars, npars);

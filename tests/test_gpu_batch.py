@@ -87,8 +87,8 @@ def test_batch_matches_single_circuit_path(env):
 
 
 def test_batch_autotuned_grid_matches_oracle(env):
-    """QP_FLAG_TUNE times a few persistent grid sizes once; the tuned batch still matches the
-    oracle per circuit."""
+    """QP_FLAG_TUNE times persistent grid sizes and class grids (split or stacked) once; the tuned
+    batch still matches the oracle per circuit."""
     import torch
     from paper_2506_23246_amd import _lib as L
     ctx, s = env
@@ -104,7 +104,7 @@ def test_batch_autotuned_grid_matches_oracle(env):
         f, g, Lo, grad = O.maxwell_eval(w.circuit, w.params, w.points, w.loss)
         e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
                  loss=rel(t2n(bufs[i]["loss"]), [Lo]), grad=rel(t2n(bufs[i]["grad"]), grad))
-        report(f"tuned batch {w.name} grid={b.info(2)}", **e)
+        report(f"tuned batch {w.name} grids={b.info(5)},{b.info(6)}", **e)
         for k, v in e.items():
             assert v < TOL, (w.name, k, v)
 
@@ -175,3 +175,29 @@ def test_full_size_batch_sampled_outputs(env):
             e = rel(t2n(bufs[i]["out"])[idx], f), rel(t2n(bufs[i]["tan"])[idx], g)
             report(f"full batch {w.name} P={len(w.points)}", f=e[0], g=e[1])
             assert e[0] < TOL and e[1] < TOL
+
+
+@pytest.mark.parametrize("cls", ["low", "high"])
+def test_batch_with_one_class_only(env, cls):
+    """Every member in one qubit-count class (3..8 or 9..11): one kernel on the whole grid, before
+    and after tuning, equal to the single-circuit path."""
+    import torch
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import Circuit
+    ctx, s = env
+    ws = [w for w in W.batch_config(P_cap=200) if (w.circuit.n <= 8) == (cls == "low")][:6]
+    assert ws
+    b = _batch(ctx, ws)
+    assert b.info(4) == (b.info(1) if cls == "low" else 0)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        for flags in (0, L.QP_FLAG_TUNE):
+            b.run(arr, W.MaxwellDesc(), flags=flags)
+            singles = [Circuit(ctx, w.circuit).maxwell(w.params, w.points, w.loss) for w in ws]
+            s.synchronize()
+            for i, w in enumerate(ws):
+                for key in ("out", "tan"):
+                    assert np.array_equal(t2n(bufs[i][key]), t2n(singles[i][key])), (w.name, key)
+                assert rel(t2n(bufs[i]["grad"]), t2n(singles[i]["grad"])) < 1e-6
+                assert rel(t2n(bufs[i]["loss"]), t2n(singles[i]["loss"])) < 1e-6
+    assert b.info(2) % ctx.cu_count == 0
