@@ -204,7 +204,7 @@ def test_hybrid_model_end_to_end_gradients(ctx):
     rloss = maxwell_residual_loss(rdf, xr)
     rloss.backward()
     errs = {"fields": rel(t2n(fields), rf.detach().numpy()), "dfields": rel(t2n(dfields), rdf.detach().numpy()),
-            "loss": rel([float(loss)], [float(rloss)])}
+            "loss": rel([float(loss.detach())], [float(rloss.detach())])}
     for (name, p1), (_, p2) in zip(gpu.named_parameters(), ref.named_parameters()):
         if p2.grad is not None:
             errs["grad " + name] = rel(t2n(p1.grad), p2.grad.numpy())

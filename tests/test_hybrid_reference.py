@@ -70,4 +70,4 @@ def test_hybrid_total_loss_terms_are_the_oracle_formulas():
         f_ic = model.fields(torch.tensor(O.ic_points(xy.numpy()))).detach().numpy()
         ref = O.total_loss(f, g, f_mx, f_my, f_ic, pts.numpy(), xy.numpy(), desc)
         for k in ("total", "phys", "ic", "sym", "energy"):
-            assert float(t[k]) == pytest.approx(ref[k], rel=1e-10, abs=1e-14), (kind, k)
+            assert float(t[k].detach()) == pytest.approx(ref[k], rel=1e-10, abs=1e-14), (kind, k)
