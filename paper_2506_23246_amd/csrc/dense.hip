@@ -142,32 +142,35 @@ __global__ void k_dense_encode(const QPlanDev* __restrict__ plan, const float* _
     } else {
       c = 0.f;   // padding point: zero state
     }
-    float* e = enc + ((size_t)p * n + q) * 5;
-    e[0] = c; e[1] = s; e[2] = j0; e[3] = j1; e[4] = j2;
+    float* e = enc + (size_t)q * 5 * Pc + p;   // [q][5][Pc]: consecutive points contiguous
+    e[0] = c; e[Pc] = s; e[2 * (size_t)Pc] = j0; e[3 * (size_t)Pc] = j1; e[4 * (size_t)Pc] = j2;
   }
 }
 
-// psi, dpsi_c (statevectors 0..3) of every (amplitude, point) of the chunk.
+// psi, dpsi_c (statevectors 0..3) of every (amplitude, point) of the chunk.  Grid (points / 256,
+// amplitudes / kDenseRows): each thread builds kDenseRows amplitudes of one point.
+constexpr int kDenseRows = 4;
 __global__ void k_dense_init(const QPlanDev* __restrict__ plan, const float* __restrict__ enc, int Pc,
                              float2* __restrict__ X) {
   const int n = plan->n;
   const long long DIM = 1ll << n;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= DIM * Pc) return;
-  const int p = (int)(idx % Pc);
-  const uint32_t j = (uint32_t)(idx / Pc);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Pc) return;
   const bool rx = plan->enc_gate == QP_ENC_RX;
+  for (int rr = 0; rr < kDenseRows; ++rr) {
+  const uint32_t j = blockIdx.y * kDenseRows + rr;
+  if (j >= (uint32_t)DIM) break;
   float Pr = 1.f, Pi = 0.f, Dr[3] = {0.f, 0.f, 0.f}, Di[3] = {0.f, 0.f, 0.f};
   for (int q = 0; q < n; ++q) {
-    const float* e = enc + ((size_t)p * n + q) * 5;
+    const float* e = enc + (size_t)q * 5 * Pc + p;
     const bool b = (j >> (n - 1 - q)) & 1u;
-    const float c = e[0], s = e[1];
+    const float c = e[0], s = e[Pc];
     float er, ei, dr, di;
     if (!b) { er = c; ei = 0.f; dr = -0.5f * s; di = 0.f; }
     else if (!rx) { er = s; ei = 0.f; dr = 0.5f * c; di = 0.f; }
     else { er = 0.f; ei = -s; dr = 0.f; di = -0.5f * c; }
     for (int k = 0; k < 3; ++k) {
-      const float jj = e[2 + k];
+      const float jj = e[(2 + k) * (size_t)Pc];
       const float nr = Dr[k] * er - Di[k] * ei + jj * (Pr * dr - Pi * di);
       const float ni = Dr[k] * ei + Di[k] * er + jj * (Pr * di + Pi * dr);
       Dr[k] = nr; Di[k] = ni;
@@ -177,12 +180,17 @@ __global__ void k_dense_init(const QPlanDev* __restrict__ plan, const float* __r
   }
   X[((size_t)0 * DIM + j) * Pc + p] = make_float2(Pr, Pi);
   for (int k = 0; k < 3; ++k) X[((size_t)(1 + k) * DIM + j) * Pc + p] = make_float2(Dr[k], Di[k]);
+  }
 }
 
 // Apply a block (A-operands tab) to statevectors [s0, s0+ns) of the chunk: one wave per
 // (statevector, other-index, 32 points) column group, in place.
-__global__ __launch_bounds__(256) void k_dense_apply(const QPlanDev* __restrict__ plan, const float* __restrict__ tab,
-                                                     int g, float2* __restrict__ X, int s0, int ns, int Pc) {
+// The block's A-operands sit in LDS (read per k-step), which keeps the kernel at 4 waves per SIMD
+// so that loads of some waves overlap the MFMA chains of others.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_dense_apply(const QPlanDev* __restrict__ plan, const float* __restrict__ tab, int g, float2* __restrict__ X,
+                   int s0, int ns, int Pc) {
+  __shared__ float sa[2 * 32 * 64];
   const int n = plan->n;
   const QDenseGroup* G = dgroup(plan, g);
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
@@ -193,10 +201,9 @@ __global__ __launch_bounds__(256) void k_dense_apply(const QPlanDev* __restrict_
   int pos[5];
   uint32_t free_mask = (1u << n) - 1;
   for (int b = 0; b < 5; ++b) { pos[b] = G->pos[b]; free_mask &= ~(1u << pos[b]); }
-  float A0[32], A1[32];
   const float* tg = tab + (size_t)g * 4096;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) { A0[i] = tg[(0 * 32 + i) * 64 + lane]; A1[i] = tg[(1 * 32 + i) * 64 + lane]; }
+  for (int e = threadIdx.x; e < 4096; e += blockDim.x) sa[e] = tg[e];
+  __syncthreads();
   uint32_t boff[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
@@ -207,6 +214,7 @@ __global__ __launch_bounds__(256) void k_dense_apply(const QPlanDev* __restrict_
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long t = wave; t < tiles; t += nwaves) {
+    asm volatile("" ::: "memory");   // keep the A-operand LDS reads inside the loop (not hoisted to registers)
     const int pt = (int)(t % PT);
     const long long r2 = t / PT;
     const int jo = (int)(r2 % JO);
@@ -233,10 +241,10 @@ __global__ __launch_bounds__(256) void k_dense_apply(const QPlanDev* __restrict_
     for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; acc2[v] = 0.f; acc3[v] = 0.f; }
 #pragma unroll
     for (int i = 0; i < 32; i += 2) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[i], bv[i], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[i], bv[i], acc1, 0, 0, 0);
-      acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[i + 1], bv[i + 1], acc2, 0, 0, 0);
-      acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[i + 1], bv[i + 1], acc3, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv[i], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i) * 64 + lane], bv[i], acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i + 1) * 64 + lane], bv[i + 1], acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i + 1) * 64 + lane], bv[i + 1], acc3, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) { acc0[v] += acc2[v]; acc1[v] += acc3[v]; }
@@ -251,42 +259,88 @@ __global__ __launch_bounds__(256) void k_dense_apply(const QPlanDev* __restrict_
   }
 }
 
-// Readout of the chunk (f, g) and, for gradient modes, the per-point seeds and loss term.
-__global__ void k_dense_readout(const QPlanDev* __restrict__ plan, const float2* __restrict__ X, long long P0, int Pc,
-                                int Pv, DenseLoss L, float* __restrict__ out, float* __restrict__ tan,
-                                float* __restrict__ seeds, float* __restrict__ lterm) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= Pc) return;
+// Readout, first stage: Z-weighted sums of |psi|^2 and 2 Re(conj(psi) dpsi_c) over a slice of
+// the amplitudes.  Grid (Pc / 64, ceil(nsl / 4)), 4 waves of 64 points; wave w of group y takes
+// slice 4y + w of nsl equal slices (each a multiple of 32 amplitudes, summed in blocks of 32);
+// the four waves are combined in LDS in a fixed order and group y writes
+// zpart[(y * 4m + k) * Pc + p].
+__global__ __launch_bounds__(256) void k_dense_zsum(const QPlanDev* __restrict__ plan, const float2* __restrict__ X,
+                                                    int Pc, int nsl, float* __restrict__ zpart) {
+  __shared__ float red[4][kMaxOut * 4][64];
   const int n = plan->n, m = plan->n_out;
   const long long DIM = 1ll << n;
-  // two-level sum (blocks of 32 amplitudes, then the block sums) keeps FP32 chains short
-  float acc[kMaxOut * 4], blk[kMaxOut * 4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  const int sl = blockIdx.y * 4 + w;
+  const long long len = DIM / nsl;
+  uint32_t zp[kMaxOut];
+  float acc[kMaxOut * 4];
+#pragma unroll
+  for (int i = 0; i < kMaxOut; ++i) zp[i] = i < m ? plan->zplain[i] : 0u;
+#pragma unroll
   for (int i = 0; i < kMaxOut * 4; ++i) acc[i] = 0.f;
-  for (long long j0 = 0; j0 < DIM; j0 += 32) {
-    for (int i = 0; i < kMaxOut * 4; ++i) blk[i] = 0.f;
-    for (long long j = j0; j < j0 + 32 && j < DIM; ++j) {
-      const float2 a = X[j * Pc + p];
-      const float2 t0 = X[(DIM + j) * Pc + p], t1 = X[(2 * DIM + j) * Pc + p], t2 = X[(3 * DIM + j) * Pc + p];
-      const float p2 = a.x * a.x + a.y * a.y;
-      const float g0 = 2.f * (a.x * t0.x + a.y * t0.y), g1 = 2.f * (a.x * t1.x + a.y * t1.y),
-                  g2 = 2.f * (a.x * t2.x + a.y * t2.y);
-      for (int i = 0; i < m; ++i) {
-        const float z = (__popc(plan->zplain[i] & (uint32_t)j) & 1) ? -1.f : 1.f;
-        blk[i * 4] += z * p2; blk[i * 4 + 1] += z * g0; blk[i * 4 + 2] += z * g1; blk[i * 4 + 3] += z * g2;
+  if (p < Pc && sl < nsl) {
+    for (long long j0 = sl * len; j0 < (sl + 1) * len; j0 += 32) {
+      float blk[kMaxOut * 4];
+#pragma unroll
+      for (int i = 0; i < kMaxOut * 4; ++i) blk[i] = 0.f;
+      const long long j1 = j0 + 32 < DIM ? j0 + 32 : DIM;
+      for (long long j = j0; j < j1; ++j) {
+        const float2 a = X[j * Pc + p];
+        const float2 t0 = X[(DIM + j) * Pc + p], t1 = X[(2 * DIM + j) * Pc + p], t2 = X[(3 * DIM + j) * Pc + p];
+        const float p2 = a.x * a.x + a.y * a.y;
+        const float g0 = 2.f * (a.x * t0.x + a.y * t0.y), g1 = 2.f * (a.x * t1.x + a.y * t1.y),
+                    g2 = 2.f * (a.x * t2.x + a.y * t2.y);
+#pragma unroll
+        for (int i = 0; i < kMaxOut; ++i) {
+          if (i >= m) break;
+          const float z = (__popc(zp[i] & (uint32_t)j) & 1) ? -1.f : 1.f;
+          blk[i * 4] += z * p2; blk[i * 4 + 1] += z * g0; blk[i * 4 + 2] += z * g1; blk[i * 4 + 3] += z * g2;
+        }
       }
+#pragma unroll
+      for (int i = 0; i < kMaxOut * 4; ++i) acc[i] += blk[i];
     }
-    for (int i = 0; i < kMaxOut * 4; ++i) acc[i] += blk[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxOut * 4; ++i)
+    if (i < 4 * m) red[w][i][lane] = acc[i];
+  __syncthreads();
+  for (int i = w; i < 4 * m; i += 4) {
+    const float v = ((red[0][i][lane] + red[1][i][lane]) + red[2][i][lane]) + red[3][i][lane];
+    if (p < Pc) zpart[((size_t)blockIdx.y * 4 * m + i) * Pc + p] = v;
+  }
+}
+
+// Readout, second stage, one thread per point: the slice groups' sums in order give (f, g); for
+// gradient modes also the per-point seeds and loss term.
+__global__ void k_dense_readout(const QPlanDev* __restrict__ plan, const float* __restrict__ zpart, int ngy,
+                                long long P0, int Pc, int Pv, DenseLoss L, float* __restrict__ out,
+                                float* __restrict__ tan, float* __restrict__ seeds, float* __restrict__ lterm) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Pc) return;
+  const int m = plan->n_out;
+  float acc[kMaxOut * 4];
+#pragma unroll
+  for (int i = 0; i < kMaxOut * 4; ++i) acc[i] = 0.f;
+  for (int y = 0; y < ngy; ++y) {
+#pragma unroll
+    for (int i = 0; i < kMaxOut * 4; ++i)
+      if (i < 4 * m) acc[i] += zpart[((size_t)y * 4 * m + i) * Pc + p];
   }
   const bool valid = p < Pv;
   const long long pt = P0 + p;
   if (valid) {
-    for (int i = 0; i < m; ++i) {
+#pragma unroll
+    for (int i = 0; i < kMaxOut; ++i) {
+      if (i >= m) break;
       if (out) out[pt * m + i] = acc[i * 4];
       if (tan) { tan[(pt * m + i) * 3] = acc[i * 4 + 1]; tan[(pt * m + i) * 3 + 1] = acc[i * 4 + 2]; tan[(pt * m + i) * 3 + 2] = acc[i * 4 + 3]; }
     }
   }
   if (!seeds) return;
   float V[kMaxOut], Wt[kMaxOut][3];
+#pragma unroll
   for (int i = 0; i < kMaxOut; ++i) { V[i] = 0.f; Wt[i][0] = Wt[i][1] = Wt[i][2] = 0.f; }
   float lt = 0.f;
   if (valid && L.maxwell) {
@@ -306,113 +360,42 @@ __global__ void k_dense_readout(const QPlanDev* __restrict__ plan, const float2*
     Wt[0][0] = A; Wt[2][1] = -A * ie; Wt[1][2] = A * ie;
     Wt[1][0] = Bq; Wt[0][2] += Bq; Wt[2][0] = C; Wt[0][1] += -C;
   } else if (valid) {
-    for (int i = 0; i < m; ++i) {
+#pragma unroll
+    for (int i = 0; i < kMaxOut; ++i) {
+      if (i >= m) break;
       if (L.d_out) V[i] = L.d_out[pt * m + i];
       if (L.d_tan) for (int k = 0; k < 3; ++k) Wt[i][k] = L.d_tan[(pt * m + i) * 3 + k];
     }
   }
-  for (int i = 0; i < m; ++i) {
-    float* sd = seeds + ((size_t)p * kMaxOut + i) * 4;
-    sd[0] = V[i]; sd[1] = Wt[i][0]; sd[2] = Wt[i][1]; sd[3] = Wt[i][2];
+#pragma unroll
+  for (int i = 0; i < kMaxOut; ++i) {
+    if (i >= m) break;
+    float* sd = seeds + (size_t)i * 4 * Pc + p;   // [i][4][Pc]
+    sd[0] = V[i]; sd[Pc] = Wt[i][0]; sd[2 * (size_t)Pc] = Wt[i][1]; sd[3 * (size_t)Pc] = Wt[i][2];
   }
   if (lterm && valid) lterm[pt] = lt;
 }
 
 // lambda = Df psi + sum_c D_c dpsi_c and mu_c = D_c psi (statevectors 4..7).
+// Grid (points / 256, amplitudes).
 __global__ void k_dense_lambda(const QPlanDev* __restrict__ plan, const float* __restrict__ seeds, int Pc,
                                float2* __restrict__ X) {
   const int n = plan->n, m = plan->n_out;
   const long long DIM = 1ll << n;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= DIM * Pc) return;
-  const int p = (int)(idx % Pc);
-  const uint32_t j = (uint32_t)(idx / Pc);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Pc) return;
+  const uint32_t j = blockIdx.y;
   float Df = 0.f, D[3] = {0.f, 0.f, 0.f};
   for (int i = 0; i < m; ++i) {
     const float z = (__popc(plan->zplain[i] & j) & 1) ? -1.f : 1.f;
-    const float* sd = seeds + ((size_t)p * kMaxOut + i) * 4;
-    Df += z * sd[0]; D[0] += z * sd[1]; D[1] += z * sd[2]; D[2] += z * sd[3];
+    const float* sd = seeds + (size_t)i * 4 * Pc + p;
+    Df += z * sd[0]; D[0] += z * sd[Pc]; D[1] += z * sd[2 * (size_t)Pc]; D[2] += z * sd[3 * (size_t)Pc];
   }
   const float2 a = X[(size_t)j * Pc + p];
   const float2 t0 = X[((size_t)DIM + j) * Pc + p], t1 = X[((size_t)2 * DIM + j) * Pc + p], t2 = X[((size_t)3 * DIM + j) * Pc + p];
   X[((size_t)4 * DIM + j) * Pc + p] = make_float2(Df * a.x + D[0] * t0.x + D[1] * t1.x + D[2] * t2.x,
                                                   Df * a.y + D[0] * t0.y + D[1] * t1.y + D[2] * t2.y);
   for (int k = 0; k < 3; ++k) X[((size_t)(5 + k) * DIM + j) * Pc + p] = make_float2(D[k] * a.x, D[k] * a.y);
-}
-
-// M_g += sum over columns of conj(Lambda) Psi^T for the four statevector pairs.  A workgroup
-// (4 waves) stages [32 amplitudes x 64 points] tiles of lambda_s and psi_s in LDS; each wave
-// takes 16 of the 64 columns (8 MFMA k-steps) and keeps the full 32x32 product (re, im) in
-// accumulators; at the end the waves are combined in a fixed order and added to the
-// workgroup's slot of mpart[g][wg][2][32][32].
-__global__ __launch_bounds__(256) void k_dense_mgemm(const QPlanDev* __restrict__ plan, int g,
-                                                     const float2* __restrict__ X, int Pc,
-                                                     float* __restrict__ mpart, int nwg) {
-  constexpr int LD = 65;   // padded row stride (float2)
-  __shared__ float2 sm[2 * 32 * LD];   // lambda tile, psi tile; reused for the wave combine
-  float2* tl = sm;
-  float2* tp = sm + 32 * LD;
-  float* red = reinterpret_cast<float*>(sm);   // [4][2][16][64] floats after the main loop
-  const int n = plan->n;
-  const QDenseGroup* G = dgroup(plan, g);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int JO = 1 << (n - 5);
-  const int PT = (Pc + 63) / 64;
-  const long long DIM = 1ll << n;
-  int pos[5];
-  uint32_t free_mask = (1u << n) - 1;
-  for (int b = 0; b < 5; ++b) { pos[b] = G->pos[b]; free_mask &= ~(1u << pos[b]); }
-  f32x16 mr, mi;
-  for (int v = 0; v < 16; ++v) { mr[v] = 0.f; mi[v] = 0.f; }
-  const int lrow = tid >> 3, lcol = (tid & 7) * 8;   // tile loader: row = amplitude, 8 points each
-  uint32_t lboff = 0;
-  for (int b = 0; b < 5; ++b) lboff |= ((uint32_t)(lrow >> b) & 1u) << pos[b];
-  for (long long t = blockIdx.x; t < (long long)JO * PT; t += gridDim.x) {
-    const int pt = (int)(t % PT), jo = (int)(t / PT);
-    uint32_t jb = 0;
-    {
-      uint32_t m = free_mask, x = (uint32_t)jo;
-      for (int k = 0; k < n; ++k)
-        if ((m >> k) & 1u) { jb |= (x & 1u) << k; x >>= 1; }
-    }
-    for (int s = 0; s < 4; ++s) {
-      const float2* Ls = X + ((size_t)(4 + s) * DIM + (jb | lboff)) * Pc;
-      const float2* Ps = X + ((size_t)s * DIM + (jb | lboff)) * Pc;
-      __syncthreads();
-      for (int e = 0; e < 8; ++e) {
-        const int p = pt * 64 + lcol + e;
-        tl[lrow * LD + lcol + e] = p < Pc ? Ls[p] : make_float2(0.f, 0.f);
-        tp[lrow * LD + lcol + e] = p < Pc ? Ps[p] : make_float2(0.f, 0.f);
-      }
-      __syncthreads();
-      const int a = lane & 31, h = lane >> 5;
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int col = wave * 16 + 2 * kk + h;
-        const float2 lv = tl[a * LD + col], pv = tp[a * LD + col];
-        // Mr += Lr Pr + Li Pi ; Mi += Lr Pi - Li Pr   (A[m=a][k=col], B[k=col][n=b])
-        mr = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.x, pv.x, mr, 0, 0, 0);
-        mr = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.y, pv.y, mr, 0, 0, 0);
-        mi = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.x, pv.y, mi, 0, 0, 0);
-        mi = __builtin_amdgcn_mfma_f32_32x32x2f32(-lv.y, pv.x, mi, 0, 0, 0);
-      }
-    }
-  }
-  // combine the four waves (fixed order) and add to this workgroup's slot
-  __syncthreads();
-  for (int v = 0; v < 16; ++v) {
-    red[((wave * 2 + 0) * 16 + v) * 64 + lane] = mr[v];
-    red[((wave * 2 + 1) * 16 + v) * 64 + lane] = mi[v];
-  }
-  __syncthreads();
-  float* slot = mpart + ((size_t)g * nwg + blockIdx.x) * 2048;
-  for (int e = tid; e < 2 * 16 * 64; e += 256) {
-    const int part = e / 1024, v = (e / 64) % 16, l = e % 64;
-    float sum = 0.f;
-    for (int wv = 0; wv < 4; ++wv) sum += red[((wv * 2 + part) * 16 + v) * 64 + l];
-    const int row = 8 * (v >> 2) + 4 * (l >> 5) + (v & 3), col = l & 31;   // M[a = row][b = col]
-    slot[part * 1024 + row * 32 + col] += sum;
-  }
 }
 
 // Adjoint of block g in one pass over the eight statevectors of the chunk (replaces an
@@ -447,46 +430,68 @@ __global__ __launch_bounds__(256) void k_dense_adj(const QPlanDev* __restrict__ 
   for (int e = tid; e < 4096; e += 256) sa[e] = tg[e];
   f32x16 mr, mi;
   for (int v = 0; v < 16; ++v) { mr[v] = 0.f; mi[v] = 0.f; }
-  const int lrow = tid >> 3, lcol = (tid & 7) * 8;   // tile loader: row = amplitude, 8 points each
-  uint32_t lboff = 0;
-  for (int b = 0; b < 5; ++b) lboff |= ((uint32_t)(lrow >> b) & 1u) << pos[b];
+  // Tile loader: per instruction a wave reads two whole 64-point rows as float4 (2 points a lane);
+  // thread tid loads rows 8k + tid/32 (k = 0..3), points 2 (tid % 32) and 2 (tid % 32) + 1.  The
+  // next unit's rows are loaded into registers while the current unit is computed.
+  const int lc4 = tid & 31, lr0 = tid >> 5;
+  uint32_t lboff[4];
+  for (int k = 0; k < 4; ++k) {
+    uint32_t o = 0;
+    for (int b = 0; b < 5; ++b) o |= ((uint32_t)((8 * k + lr0) >> b) & 1u) << pos[b];
+    lboff[k] = o;
+  }
   const bool is_psi = wave < 2;
   const int c0 = (wave & 1) * 32;     // the 32 tile columns this wave applies the block to
   float2* T = is_psi ? tp : tl;
-  for (long long t = blockIdx.x; t < (long long)JO * PT; t += gridDim.x) {
-    const int pt = (int)(t % PT), jo = (int)(t / PT);
-    uint32_t jb = 0;
-    {
-      uint32_t m = free_mask, x = (uint32_t)jo;
-      for (int k = 0; k < n; ++k)
-        if ((m >> k) & 1u) { jb |= (x & 1u) << k; x >>= 1; }
+  const long long ntile = (long long)JO * PT;
+  auto tile_jb = [&](long long t) {
+    const int jo = (int)(t / PT);
+    uint32_t jb = 0;   // deposit jo into the free (non-block) index bits, ascending
+    uint32_t m = free_mask, x = (uint32_t)jo;
+    for (int k = 0; k < n; ++k)
+      if ((m >> k) & 1u) { jb |= (x & 1u) << k; x >>= 1; }
+    return jb;
+  };
+  float4 rl[4], rp[4];
+  auto load_unit = [&](long long t, int s) {
+    const uint32_t jb = tile_jb(t);
+    const int q = (int)(t % PT) * 64 + 2 * lc4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const size_t rowL = ((size_t)(4 + s) * DIM + (jb | lboff[k])) * Pc, rowP = ((size_t)s * DIM + (jb | lboff[k])) * Pc;
+      rl[k] = q < Pc ? *reinterpret_cast<const float4*>(X + rowL + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+      rp[k] = q < Pc ? *reinterpret_cast<const float4*>(X + rowP + q) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+  };
+  if ((long long)blockIdx.x < ntile) load_unit(blockIdx.x, 0);
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int pt = (int)(t % PT);
+    const uint32_t jb = tile_jb(t);
     const int p = pt * 64 + c0 + c;
     const bool ok = p < Pc;
     for (int s = 0; s < 4; ++s) {
-      const float2* Ls = X + ((size_t)(4 + s) * DIM + (jb | lboff)) * Pc;
-      const float2* Ps = X + ((size_t)s * DIM + (jb | lboff)) * Pc;
       __syncthreads();
-      for (int e = 0; e < 8; ++e) {
-        const int q = pt * 64 + lcol + e;
-        tl[lrow * LD + lcol + e] = q < Pc ? Ls[q] : make_float2(0.f, 0.f);
-        tp[lrow * LD + lcol + e] = q < Pc ? Ps[q] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = 8 * k + lr0;
+        tl[r * LD + 2 * lc4] = make_float2(rl[k].x, rl[k].y);
+        tl[r * LD + 2 * lc4 + 1] = make_float2(rl[k].z, rl[k].w);
+        tp[r * LD + 2 * lc4] = make_float2(rp[k].x, rp[k].y);
+        tp[r * LD + 2 * lc4 + 1] = make_float2(rp[k].z, rp[k].w);
       }
       __syncthreads();
+      if (s < 3) load_unit(t, s + 1);
+      else if (t + gridDim.x < ntile) load_unit(t + gridDim.x, 0);
       {   // B^H on 32 columns of the psi tile (waves 0, 1) or of the lambda tile (waves 2, 3)
-        float bv[32];
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-          const float2 v = T[i * LD + c0 + c];
-          bv[i] = h ? v.y : v.x;
-        }
+        const float* Tf = reinterpret_cast<const float*>(T) + 2 * (c0 + c) + h;   // B[k][n]: re (h = 0) or im
         f32x16 acc0, acc1;
 #pragma unroll
         for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; }
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
-          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv[i], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i) * 64 + lane], bv[i], acc1, 0, 0, 0);
+          const float bv = Tf[2 * i * LD];
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i) * 64 + lane], bv, acc1, 0, 0, 0);
         }
         float2* dst = X + (size_t)(is_psi ? s : 4 + s) * DIM * Pc;
 #pragma unroll
@@ -608,6 +613,17 @@ __global__ void k_dense_params(const QPlanDev* __restrict__ plan, const double* 
 // ---------------------------------------------------------------------------------------------
 static inline unsigned nb(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Amplitude slices of the readout's first stage (a multiple of 32 amplitudes each, at most 64)
+// and the number of 4-slice groups.
+static inline int dense_readout_slices(int n) {
+  const long long dim = 1ll << n;
+  long long ns = dim / 32;
+  if (ns < 1) ns = 1;
+  if (ns > 64) ns = 64;
+  return (int)ns;
+}
+static inline int dense_readout_groups(int n) { return (dense_readout_slices(n) + 3) / 4; }
+
 DenseLayout dense_layout(int n, int m, int G, int n_docc, long long P, int Pc, int nwg, bool grad) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   DenseLayout L{};
@@ -618,6 +634,7 @@ DenseLayout dense_layout(int n, int m, int G, int n_docc, long long P, int Pc, i
   L.X = off; off = al(off + sizeof(float2) * (size_t)S * ((size_t)1 << n) * Pc);
   L.enc = off; off = al(off + sizeof(float) * 5 * (size_t)n * Pc);
   L.seeds = off; off = al(off + sizeof(float) * 4 * kMaxOut * (size_t)Pc);
+  L.zpart = off; off = al(off + sizeof(float) * 4 * kMaxOut * (size_t)dense_readout_groups(n) * Pc);
   L.lterm = off; off = al(off + sizeof(float) * (size_t)(P > 0 ? P : 1));
   L.mpart = off; off = al(off + sizeof(float) * 2048 * (size_t)(G > 0 ? G : 1) * nwg);
   L.m64 = off; off = al(off + sizeof(double) * 2048 * (size_t)(G > 0 ? G : 1));
@@ -649,6 +666,8 @@ hipError_t dense_run(const DenseCall& c, hipStream_t st) {
   float2* X = reinterpret_cast<float2*>(w + L.X);
   float* enc = reinterpret_cast<float*>(w + L.enc);
   float* seeds = reinterpret_cast<float*>(w + L.seeds);
+  float* zpart = reinterpret_cast<float*>(w + L.zpart);
+  const int nsl = dense_readout_slices(n), ngy = dense_readout_groups(n);
   float* lterm = reinterpret_cast<float*>(w + L.lterm);
   float* mpart = reinterpret_cast<float*>(w + L.mpart);
   double* m64 = reinterpret_cast<double*>(w + L.m64);
@@ -664,13 +683,14 @@ hipError_t dense_run(const DenseCall& c, hipStream_t st) {
     const int Pv = (int)((c.P - P0) < c.Pc ? (c.P - P0) : c.Pc);
     const int Pc = c.Pc;
     hipLaunchKernelGGL(k_dense_encode, dim3(nb(Pc, 128)), dim3(128), 0, st, plan, c.points, c.angles, c.jac, P0, Pc, Pv, enc);
-    hipLaunchKernelGGL(k_dense_init, dim3(nb(DIM * Pc, 256)), dim3(256), 0, st, plan, enc, Pc, X);
+    hipLaunchKernelGGL(k_dense_init, dim3(nb(Pc, 256), nb(DIM, kDenseRows)), dim3(256), 0, st, plan, enc, Pc, X);
     for (int g = 0; g < G; ++g)
       hipLaunchKernelGGL(k_dense_apply, dim3(apply_grid), dim3(256), 0, st, plan, tabF, g, X, 0, 4, Pc);
-    hipLaunchKernelGGL(k_dense_readout, dim3(nb(Pc, 64)), dim3(64), 0, st, plan, X, P0, Pc, Pv, c.loss, c.out, c.tan,
-                       c.grad ? seeds : nullptr, c.grad ? lterm : nullptr);
+    hipLaunchKernelGGL(k_dense_zsum, dim3(nb(Pc, 64), ngy), dim3(256), 0, st, plan, X, Pc, nsl, zpart);
+    hipLaunchKernelGGL(k_dense_readout, dim3(nb(Pc, 64)), dim3(64), 0, st, plan, zpart, ngy, P0, Pc, Pv, c.loss,
+                       c.out, c.tan, c.grad ? seeds : nullptr, c.grad ? lterm : nullptr);
     if (!c.grad) continue;
-    hipLaunchKernelGGL(k_dense_lambda, dim3(nb(DIM * Pc, 256)), dim3(256), 0, st, plan, seeds, Pc, X);
+    hipLaunchKernelGGL(k_dense_lambda, dim3(nb(Pc, 256), (unsigned)DIM), dim3(256), 0, st, plan, seeds, Pc, X);
     for (int g = G - 1; g >= 0; --g)
       hipLaunchKernelGGL(k_dense_adj, dim3(c.nwg), dim3(256), 0, st, plan, tabA, g, X, Pc, mpart, c.nwg);
   }

@@ -20,7 +20,7 @@ struct DenseLoss {
   const float* d_tan;
 };
 
-struct DenseLayout { size_t tabF, tabA, X, enc, seeds, lterm, mpart, m64, contrib, angles, jac, counts, total; };
+struct DenseLayout { size_t tabF, tabA, X, enc, seeds, zpart, lterm, mpart, m64, contrib, angles, jac, counts, total; };
 
 struct DenseCall {
   const QPlanDev* plan;

@@ -118,3 +118,27 @@ def test_dense_multi_chunk_against_stored_oracle(ctx, name, chunk):
     report(f"dense stored oracle {name} chunk {chunk}", **e)
     for key, v in e.items():
         assert v < TOL, (key, v)
+
+
+@pytest.mark.parametrize("n,out", [(5, [4, 0, 2, 1, 3]), (9, [8, 1, 7, 2, 6, 3, 5, 0])])
+def test_dense_readout_slices_and_output_counts(ctx, n, out):
+    """The readout's amplitude slices at their extremes: 5 qubits (one 32-amplitude slice, three
+    idle waves of the slice group) and 9 qubits (16 slices in 4 groups) with 8 read-out qubits in
+    scrambled order; forward, tangents and the VJP against the oracle."""
+    rng = np.random.default_rng(40 + n)
+    circ = W.layered(n, 2, "xyz", lambda l: W.ring(n, W.CNOT if l == 0 else W.CZ, 1), out_qubits=out)
+    params = rng.uniform(0, 2 * math.pi, circ.n_params).astype(np.float32)
+    P = 70
+    pts = rng.uniform(-1, 1, (P, 3)).astype(np.float32)
+    m = len(out)
+    d_out = rng.standard_normal((P, m)).astype(np.float32)
+    d_tan = rng.standard_normal((P, m, 3)).astype(np.float32)
+    c = _circ(ctx, circ)
+    f_got, g_got = c.simulate(params, pts, flags=_flags())
+    f, g = O.simulate(circ, params, pts)
+    got = t2n(c.vjp(params, pts, d_out, d_tan, flags=_flags()))
+    exp = O.grad_reverse(circ, params, pts, d_out, d_tan)
+    e = dict(f=rel(t2n(f_got), f), g=rel(t2n(g_got), g), grad=rel(got, exp))
+    report(f"dense readout {n}q, {m} outputs", **e)
+    for key, v in e.items():
+        assert v < TOL, (key, v)
