@@ -171,7 +171,9 @@ size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags);
  * P = 0 is valid and does nothing except zeroing reduced outputs; P above 2^31 - 1 returns
  * QP_EUNSUPPORTED (point indices are 32-bit on the device; split such a call).             */
 
-/* Forward: out [P][m]; tan [P][m][3] unless QP_FLAG_NO_TANGENTS.                           */
+/* Forward: out [P][m]; tan [P][m][3] unless QP_FLAG_NO_TANGENTS.  Without tangents the fused
+ * kernel runs packed (four points in the four statevector slots of a thread group: about a
+ * quarter of the cost per point; the outputs equal those of the tangent-carrying kernel).  */
 qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* params,
                       const float* points, const float* angles, const float* jac, int64_t P,
                       float* out, float* tan, void* ws, size_t ws_bytes, uint32_t flags);
@@ -213,8 +215,9 @@ qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params
  *            eps E dE/dt + Hx dHx/dt + Hy dHy/dt - (dE/dx Hy + E dHy/dx) + (dE/dy Hx + E dHx/dy)
  *            (eqs. Poynting_thm, Poynting_value_u, Poynting_value_S, energy_loss).
  * The mirror images couple points, so the call runs three stream-ordered phases over the set
- * [X; X_my; X_mx (vacuum); X_0]: forward with tangents, per-point loss terms and seeds, adjoint
- * VJP.  points [P][3] (t, x, y) and ic_xy [P0][2] (x, y) are device buffers; out [P][m] and tan
+ * [X; X_my; X_mx (vacuum); X_0]: forward (with tangents for X; the mirrored and initial-condition
+ * points, whose terms use the fields alone, packed four to a thread group), per-point loss terms
+ * and seeds, adjoint VJP (the same split).  points [P][3] (t, x, y) and ic_xy [P0][2] (x, y) are device buffers; out [P][m] and tan
  * [P][m][3] (of X, may be NULL); loss_terms: device double [5] = total, phys, IC, sym, energy;
  * d_params [K].  Point encodings only (cycled or random Fourier features): QP_EINVAL for the
  * angle-given encoding.  Flags: only QP_FLAG_GATES_FP32 (others: QP_EUNSUPPORTED).          */

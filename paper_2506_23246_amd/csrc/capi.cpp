@@ -385,8 +385,11 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   if (mode == kModeMaxwell && ld->kind == QP_LOSS_DIEL_SPLIT) {
     if ((e = launch_count(points, P, ld->x_interface, counts, st)) != hipSuccess) return hipcheck(ctx, e, "count");
   }
-  int grid = fused_grid(ctx, c, P);
-  if (grid_override > 0) grid = (int)std::min<int64_t>(grid_override, (P + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
+  // packed modes: four points per thread group, so a tile covers four times the points
+  const int64_t P_slots = mode_packed(mode) ? (P + 3) / 4 : P;
+  int grid = fused_grid(ctx, c, P_slots);
+  if (grid_override > 0)
+    grid = (int)std::min<int64_t>(grid_override, (P_slots + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
   grid = std::min(grid, cap);
   const int exs = NM > 0 ? 2 : (exs_override > 0 ? exs_override : c->exs);   // phases: unpipelined kernel
   const size_t lds = fused_lds_bytes(n, exs, F, NM);
@@ -397,7 +400,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.angles = ang;
   a.jac = jc;
   a.P = P;
-  a.ntiles = (int)((P + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
+  a.ntiles = (int)((P_slots + fused_points_per_tile(n) - 1) / fused_points_per_tile(n));
   a.n_fused = F;
   a.out = out;
   a.tan = tan;
@@ -411,14 +414,15 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.mpart = reinterpret_cast<float*>(w + L.mpart);
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
   a.n_mom = NM;
-  a.d_angles = mode == kModeFwd ? nullptr : d_angles;
-  a.d_jac = mode == kModeFwd ? nullptr : d_jac;
+  a.d_angles = (mode == kModeMaxwell || mode == kModeVjp) ? d_angles : nullptr;
+  a.d_jac = (mode == kModeMaxwell || mode == kModeVjp) ? d_jac : nullptr;
+  if (mode_packed(mode)) { a.tan = nullptr; a.d_tan = nullptr; }
   if (grid > 0) {
     if (ctx->timing) hipEventRecord(ctx->ev0, st);
     if ((e = launch_fused(n, mode, a, grid, exs, c->hp.has_signs, lds, st)) != hipSuccess) return hipcheck(ctx, e, "fused kernel");
     if (ctx->timing) hipEventRecord(ctx->ev1, st);
   }
-  if (mode == kModeFwd || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
+  if (mode_fwd_only(mode) || (!loss && !d_params)) return QP_OK;   // the tuner times the main kernel only
   double* m64 = reinterpret_cast<double*>(w + L.m64);
   if ((e = launch_reduce(a.mpart, grid, F * kGS + NM, mode == kModeMaxwell ? a.lpart : nullptr, m64,
                          mode == kModeMaxwell ? loss : nullptr, st)) != hipSuccess)
@@ -438,9 +442,10 @@ extern "C" qp_status qp_simulate(qp_ctx* ctx, const qp_circuit* c, const float* 
   if (flags & QP_FLAG_DENSE_MFMA)
     return run_dense(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
                      (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, ws, flags);
-  return run_fused(ctx, c, kModeFwd, params, points, angles, jac, P, nullptr, out,
-                   (flags & QP_FLAG_NO_TANGENTS) ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                   ws, flags, 0, 0);
+  // outputs alone: the packed kernel (four points per thread group, no tangent statevectors)
+  const bool no_tan = (flags & QP_FLAG_NO_TANGENTS) != 0;
+  return run_fused(ctx, c, no_tan ? kModeFwdPk : kModeFwd, params, points, angles, jac, P, nullptr, out,
+                   no_tan ? nullptr : tan, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ws, flags, 0, 0);
 }
 
 // Input gradients (dL/d angles, dL/d Jacobian) exist for the angle-given encoding on the fused path.
@@ -563,7 +568,7 @@ extern "C" qp_status qp_energy_profile(qp_ctx* ctx, const qp_circuit* c, const f
   float* f = reinterpret_cast<float*>(w + L.out);
   hipError_t e = launch_energy_grid(t, Nt, xg, Nx, yg, Ny, pts, st);
   if (e != hipSuccess) return hipcheck(ctx, e, "energy grid");
-  qp_status s = run_fused(ctx, c, kModeFwd, params, pts, nullptr, nullptr, L.P, nullptr, f, nullptr, nullptr, nullptr,
+  qp_status s = run_fused(ctx, c, kModeFwdPk, params, pts, nullptr, nullptr, L.P, nullptr, f, nullptr, nullptr, nullptr,
                           nullptr, nullptr, nullptr, nullptr, w + L.fused, flags, 0, 0);
   if (s != QP_OK) return s;
   const int diel = desc && desc->kind != QP_LOSS_VACUUM;
@@ -574,7 +579,7 @@ extern "C" qp_status qp_energy_profile(qp_ctx* ctx, const qp_circuit* c, const f
 
 // ---------------------------------------------------------------- total loss ----------------
 namespace {
-struct TotalLayout { size_t ext, out, tan, dout, dtan, part, counts, fused, total; int64_t P_ext, ic_base; int with_mx; };
+struct TotalLayout { size_t ext, out, tan, dout, dtan, dtmp, part, counts, fused, total; int64_t P_ext, ic_base; int with_mx; };
 
 TotalLayout total_layout(const qp_circuit* c, int64_t P, int64_t P0, int phys_kind) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -586,9 +591,10 @@ TotalLayout total_layout(const qp_circuit* c, int64_t P, int64_t P0, int phys_ki
   size_t off = 0;
   L.ext = off; off = al(off + sizeof(float) * 3 * Pe);
   L.out = off; off = al(off + sizeof(float) * m * Pe);
-  L.tan = off; off = al(off + sizeof(float) * 3 * m * Pe);
+  L.tan = off; off = al(off + sizeof(float) * 3 * m * (size_t)P);   // tangents of the collocation points only
   L.dout = off; off = al(off + sizeof(float) * m * Pe);
-  L.dtan = off; off = al(off + sizeof(float) * 3 * m * Pe);
+  L.dtan = off; off = al(off + sizeof(float) * 3 * m * (size_t)P);
+  L.dtmp = off; off = al(off + sizeof(float) * (size_t)std::max(1, c->hp.K));
   L.part = off; off = al(off + sizeof(float) * 4 * (size_t)std::max(1, total_seed_blocks(P, P0)));
   L.counts = off; off = al(off + 2 * sizeof(int));
   L.fused = off; off = al(off + fused_layout(c, L.P_ext, c->ctx->cu_count * 4).total);
@@ -639,9 +645,18 @@ extern "C" qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float
   if (e != hipSuccess) return hipcheck(ctx, e, "total-loss points");
   if (kind == QP_LOSS_DIEL_SPLIT && (e = launch_count(points, P, d->phys.x_interface, counts, st)) != hipSuccess)
     return hipcheck(ctx, e, "count");
-  qp_status s = run_fused(ctx, c, kModeFwd, params, ext, nullptr, nullptr, L.P_ext, nullptr, fo, fg, nullptr, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, fws, gflags, 0, 0);
-  if (s != QP_OK) return s;
+  // Forward: the collocation points with their input tangents; the mirrored and initial-condition
+  // points (whose terms use the fields alone) by the packed kernel, four points per thread group.
+  const int64_t P_rest = L.P_ext - P;
+  const int m = c->hp.m;
+  qp_status s = QP_OK;
+  if (P > 0 && (s = run_fused(ctx, c, kModeFwd, params, ext, nullptr, nullptr, P, nullptr, fo, fg, nullptr, nullptr,
+                              nullptr, nullptr, nullptr, nullptr, fws, gflags, 0, 0)) != QP_OK)
+    return s;
+  if (P_rest > 0 && (s = run_fused(ctx, c, kModeFwdPk, params, ext + 3 * P, nullptr, nullptr, P_rest, nullptr,
+                                   fo + (size_t)m * P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   fws, gflags, 0, 0)) != QP_OK)
+    return s;
   TotalSeedArgs a{};
   a.out = fo; a.tan = fg; a.points = points; a.ic_xy = ic_xy;
   a.P = P; a.P0 = P0; a.ic_base = L.ic_base; a.m = c->hp.m; a.with_mx = L.with_mx;
@@ -656,8 +671,21 @@ extern "C" qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float
   if (tan && P > 0 && (e = hipMemcpyAsync(tan, fg, sizeof(float) * 3 * c->hp.m * P, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hipcheck(ctx, e, "copy tangents");
   if (c->hp.K == 0) return QP_OK;
-  return run_fused(ctx, c, kModeVjp, params, ext, nullptr, nullptr, L.P_ext, nullptr, nullptr, nullptr, dout, dtan,
-                   nullptr, d_params, nullptr, nullptr, fws, gflags, 0, 0);
+  // Adjoint: the same split; with both parts, the packed part's gradient goes to a scratch vector
+  // and is added (each part reduced over its workgroups in FP64, rounded once, then summed).
+  const bool two = P > 0 && P_rest > 0;
+  float* dtmp = reinterpret_cast<float*>(w + L.dtmp);
+  if ((P > 0 || P_rest == 0) &&
+      (s = run_fused(ctx, c, kModeVjp, params, ext, nullptr, nullptr, P, nullptr, nullptr, nullptr, dout, dtan, nullptr,
+                     d_params, nullptr, nullptr, fws, gflags, 0, 0)) != QP_OK)
+    return s;
+  if (P_rest > 0 &&
+      (s = run_fused(ctx, c, kModeVjpPk, params, ext + 3 * P, nullptr, nullptr, P_rest, nullptr, nullptr, nullptr,
+                     dout + (size_t)m * P, nullptr, nullptr, two ? dtmp : d_params, nullptr, nullptr, fws, gflags, 0,
+                     0)) != QP_OK)
+    return s;
+  if (two && (e = launch_add(d_params, dtmp, c->hp.K, st)) != hipSuccess) return hipcheck(ctx, e, "gradient sum");
+  return QP_OK;
 }
 
 // ---------------------------------------------------------------- plain ---------------------

@@ -783,14 +783,55 @@ __device__ __forceinline__ void encoding_grads(const float (&sr)[8][8], const fl
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
 // PH: the plan may carry CRZ phase stages (false for the uneven-batch kernel, whose circuits have
 // none: the phase code is then compiled out).
+// Packed modes: the product state of point pt0 + SL in statevector slot SL, formed in the mapping
+// emap (no input tangents; an out-of-range point gives the zero state).
+template <int N, int SL>
+__device__ __forceinline__ void packed_state(float (&sr)[8][8], float (&si)[8][8], CP<QPlanDev> plan, CP<float> gtab,
+                                             const FusedArgs& a, long long pt0, uint32_t u, CP<int32_t> emap) {
+  const long long pts = pt0 + SL;
+  const bool vs = pts < a.P;
+  float q3[3] = {0.f, 0.f, 0.f};
+  if (vs && a.points && plan->enc_kind != QP_ENC_ANGLES) {
+    q3[0] = a.points[pts * 3 + 0];
+    q3[1] = a.points[pts * 3 + 1];
+    q3[2] = a.points[pts * 3 + 2];
+  }
+  float Pr = vs ? 1.f : 0.f, Pi = 0.f;
+#pragma unroll 1
+  for (int k = 3; k < N; ++k) {
+    const QEnc E = encode_qubit<N>(plan, gtab, a, pts, vs, q3, N - 1 - emap[k]);
+    const bool bit = (u >> (k - 3)) & 1u;
+    const float er = bit ? E.e1r : E.e0r, ei = bit ? E.e1i : E.e0i;
+    const float npr = Pr * er - Pi * ei, npi = Pr * ei + Pi * er;
+    Pr = npr; Pi = npi;
+  }
+  QEnc Q[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Q[i] = encode_qubit<N>(plan, gtab, a, pts, vs, q3, N - 1 - emap[i]);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    float pr = Pr, pi = Pi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const bool b = (r >> i) & 1;
+      const float er = b ? Q[i].e1r : Q[i].e0r, ei = b ? Q[i].e1i : Q[i].e0i;
+      const float npr = pr * er - pi * ei, npi = pr * ei + pi * er;
+      pr = npr; pi = npi;
+    }
+    sr[SL][r] = pr; si[SL][r] = pi;
+  }
+}
+
 template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false, bool PH = true>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ mslots,
                                            float* __restrict__ red, float& lacc) {
   constexpr int TP = 1 << (N - 3);         // threads per point
-  constexpr int PPW = T / TP;              // points per workgroup tile
+  constexpr int PPW = T / TP;              // points per workgroup tile (x4 in the packed modes)
   constexpr int DIM = 1 << N;
+  constexpr bool PK = mode_packed(MODE);
   static_assert(PPW >= 1, "tile too small");
+  static_assert(!(PK && EG), "the packed modes carry no input gradients");
   CP<QPlanDev> plan = to_const(a.plan);
   CP<char> pb = reinterpret_cast<CP<char>>(plan);
   CP<QRound> rounds = reinterpret_cast<CP<QRound>>(pb + plan->off_rounds);
@@ -821,7 +862,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
   }
   float sr[8][8], si[8][8];
   {
-    const long long pt = (long long)tile * PPW + ps;
+    // packed modes: slot s of the thread group holds point pt0 + s
+    const long long pt = PK ? ((long long)tile * PPW + ps) * 4 : (long long)tile * PPW + ps;
+    const long long pt0 = pt;
     const bool valid = pt < a.P;
 
     // ---------------- encoding and product state -------------------------------------------
@@ -836,7 +879,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       p3[1] = a.points[pt * 3 + 1];
       p3[2] = a.points[pt * 3 + 2];
     }
-    {
+    if constexpr (PK) {
+      // four product states, one per slot (no tangents); one call per slot keeps the slot index
+      // a compile-time constant (the statevector arrays stay in registers)
+      CP<int32_t> emap = H > 0 ? rounds[H - 1].tpost : rounds[0].tpos;
+      packed_state<N, 0>(sr, si, plan, gtab, a, pt0, u, emap);
+      packed_state<N, 1>(sr, si, plan, gtab, a, pt0, u, emap);
+      packed_state<N, 2>(sr, si, plan, gtab, a, pt0, u, emap);
+      packed_state<N, 3>(sr, si, plan, gtab, a, pt0, u, emap);
+    } else {
       CP<int32_t> emap = H > 0 ? rounds[H - 1].tpost : rounds[0].tpos;
       // thread part: (P, D_c) by the product rule over the thread qubits
       float Pr = valid ? 1.f : 0.f, Pi = 0.f;
@@ -969,10 +1020,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const uint32_t j = jl ^ reg_off(r, l0, l1, l2);
+      // per output: <Z> and its three input tangents, or (packed) <Z> of the four slots' points
       const float p2 = sr[0][r] * sr[0][r] + si[0][r] * si[0][r];
       float gc[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gc[c] = 2.f * (sr[0][r] * sr[1 + c][r] + si[0][r] * si[1 + c][r]);
+      for (int c = 0; c < 3; ++c)
+        gc[c] = PK ? sr[1 + c][r] * sr[1 + c][r] + si[1 + c][r] * si[1 + c][r]
+                   : 2.f * (sr[0][r] * sr[1 + c][r] + si[0][r] * si[1 + c][r]);
 #pragma unroll
       for (int i = 0; i < kMaxOut; ++i) {
         if (i < m) {
@@ -1015,7 +1069,18 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
       }
       __syncthreads();
     }
-    if (valid && u == 0) {
+    if (PK && u == 0 && a.out) {
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (pt0 + sl >= a.P) break;
+#pragma unroll
+        for (int i = 0; i < kMaxOut; ++i) {
+          if (i >= m) break;
+          a.out[(pt0 + sl) * m + i] = acc[i * 4 + sl];
+        }
+      }
+    }
+    if (!PK && valid && u == 0) {
 #pragma unroll
       for (int i = 0; i < kMaxOut; ++i) {
         if (i >= m) break;
@@ -1027,7 +1092,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         }
       }
     }
-    if (MODE == kModeFwd) return;
+    if constexpr (mode_fwd_only(MODE)) return;
 
     // ---------------- seeds -----------------------------------------------------------------
     float Wv[kMaxOut][3], Vv[kMaxOut];
@@ -1055,6 +1120,17 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         Wv[0][0] = A;  Wv[2][1] = -A * ie;  Wv[1][2] = A * ie;
         Wv[1][0] = Bq; Wv[0][2] += Bq;
         Wv[2][0] = C;  Wv[0][1] += -C;
+      }
+    } else if (PK) {   // output seeds of the four slots' points: slot 0 in Vv, slot c + 1 in Wv[.][c]
+      if (a.d_out) {
+#pragma unroll
+        for (int i = 0; i < kMaxOut; ++i) {
+          if (i >= m) break;
+          if (pt0 < a.P) Vv[i] = a.d_out[pt0 * m + i];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (pt0 + 1 + c < a.P) Wv[i][c] = a.d_out[(pt0 + 1 + c) * m + i];
+        }
       }
     } else {   // VJP seeds
       if (valid) {
@@ -1085,11 +1161,18 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
           D2 += z * Wv[i][2];
         }
       }
-      sr[4][r] = Df * sr[0][r] + D0 * sr[1][r] + D1 * sr[2][r] + D2 * sr[3][r];
-      si[4][r] = Df * si[0][r] + D0 * si[1][r] + D1 * si[2][r] + D2 * si[3][r];
-      sr[5][r] = D0 * sr[0][r]; si[5][r] = D0 * si[0][r];
-      sr[6][r] = D1 * sr[0][r]; si[6][r] = D1 * si[0][r];
-      sr[7][r] = D2 * sr[0][r]; si[7][r] = D2 * si[0][r];
+      if (PK) {   // lambda of each slot's point, paired with that slot's psi
+        sr[4][r] = Df * sr[0][r]; si[4][r] = Df * si[0][r];
+        sr[5][r] = D0 * sr[1][r]; si[5][r] = D0 * si[1][r];
+        sr[6][r] = D1 * sr[2][r]; si[6][r] = D1 * si[2][r];
+        sr[7][r] = D2 * sr[3][r]; si[7][r] = D2 * si[3][r];
+      } else {
+        sr[4][r] = Df * sr[0][r] + D0 * sr[1][r] + D1 * sr[2][r] + D2 * sr[3][r];
+        si[4][r] = Df * si[0][r] + D0 * si[1][r] + D1 * si[2][r] + D2 * si[3][r];
+        sr[5][r] = D0 * sr[0][r]; si[5][r] = D0 * si[0][r];
+        sr[6][r] = D1 * sr[0][r]; si[6][r] = D1 * si[0][r];
+        sr[7][r] = D2 * sr[0][r]; si[7][r] = D2 * si[0][r];
+      }
     }
     // ---------------- adjoint sweep with uncompute -----------------------------------------
     // Per round in reverse: psi-family <- U^H (uncompute), lambda-family <- U^H, gate statistics,
@@ -1213,7 +1296,7 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  if (MODE != kModeFwd) {
+  if (!mode_fwd_only(MODE)) {
     for (int i = tid; i < WAVES * (F * kGS + a.n_mom); i += T) slots[i] = 0.f;
   }
   __syncthreads();
@@ -1231,7 +1314,7 @@ __global__ __launch_bounds__(T, 2) void k_fused(FusedArgs a) {
   }
   for (int tile = t_begin; tile < t_end; tile += t_step)
     fused_tile<N, T, EXS, MODE, SG, EG>(a, tile, buf, slots, mslots, red, lacc);
-  if (MODE == kModeFwd) return;
+  if (mode_fwd_only(MODE)) return;
   // ---------------- per-workgroup partials (fixed order) -----------------------------------
   __syncthreads();
   const int ncol = F * kGS + a.n_mom;
@@ -1286,7 +1369,7 @@ hipError_t launch_one(const FusedArgs& a, int grid, size_t lds, hipStream_t st) 
 // pipelined kernel has a variant without the sign code for circuits that have none).
 template <int N>
 hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, bool signs, size_t lds, hipStream_t st) {
-  if (mode != kModeFwd && (a.d_angles || a.d_jac)) {   // per-point input gradients (angle-given encoding)
+  if ((mode == kModeMaxwell || mode == kModeVjp) && (a.d_angles || a.d_jac)) {   // per-point input gradients
     if (mode == kModeMaxwell)
       return exs == 2 ? launch_one<N, 2, kModeMaxwell, true, true>(a, grid, lds, st)
                       : launch_one<N, 4, kModeMaxwell, true, true>(a, grid, lds, st);
@@ -1301,6 +1384,16 @@ hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, bool 
     if (exs == 2) return launch_one<N, 2, kModeMaxwell, true>(a, grid, lds, st);
     return signs ? launch_one<N, 4, kModeMaxwell, true>(a, grid, lds, st)
                  : launch_one<N, 4, kModeMaxwell, false>(a, grid, lds, st);
+  }
+  if (mode == kModeFwdPk) {
+    if (exs == 2) return launch_one<N, 2, kModeFwdPk, true>(a, grid, lds, st);
+    return signs ? launch_one<N, 4, kModeFwdPk, true>(a, grid, lds, st)
+                 : launch_one<N, 4, kModeFwdPk, false>(a, grid, lds, st);
+  }
+  if (mode == kModeVjpPk) {
+    if (exs == 2) return launch_one<N, 2, kModeVjpPk, true>(a, grid, lds, st);
+    return signs ? launch_one<N, 4, kModeVjpPk, true>(a, grid, lds, st)
+                 : launch_one<N, 4, kModeVjpPk, false>(a, grid, lds, st);
   }
   if (exs == 2) return launch_one<N, 2, kModeVjp, true>(a, grid, lds, st);
   return signs ? launch_one<N, 4, kModeVjp, true>(a, grid, lds, st) : launch_one<N, 4, kModeVjp, false>(a, grid, lds, st);

@@ -2,11 +2,14 @@
 //
 // The symmetry term couples a collocation point with its mirror images, so the step runs in three
 // stream-ordered phases over an extended point set [X; X_my; X_mx (vacuum only); X_0]:
-//   1. the fused forward kernel (outputs and input tangents of every point),
+//   1. the fused forward kernels: outputs and input tangents of the collocation points X, outputs
+//      alone of the mirrored and initial-condition points (packed kernel, four points per group),
 //   2. k_total_seeds: per collocation point the residual, energy and symmetry terms and their
-//      seeds d L_tot / d(f, g) for the point and its two images, per initial-condition point the
-//      IC term and its seed; FP32 per-block partial sums of the four terms,
-//   3. the fused VJP kernel with those seeds (adjoint with uncompute), then the FP64 reductions.
+//      seeds d L_tot / d(f, g) for the point and d L_tot / d f for its images, per
+//      initial-condition point the IC term and its seed d L_tot / d f; FP32 per-block partial
+//      sums of the four terms,
+//   3. the fused VJP kernels with those seeds (adjoint with uncompute; the packed kernel for the
+//      points seeded through f alone), then the FP64 reductions.
 // The loss terms are summed across blocks in FP64 in a fixed order (k_total_reduce).
 #include <hip/hip_runtime.h>
 
@@ -119,8 +122,6 @@ __global__ void k_total_seeds(TotalSeedArgs a) {
         vf[c] += ks * d;
         vm[c] = -ks * s[c] * d;
       }
-      float* wm = a.d_tan + pmy * m * 3;
-      for (int j = 0; j < 3 * m; ++j) wm[j] = 0.f;
     }
     if (a.with_mx) {
       const float* fm = a.out + pmx * m;
@@ -134,17 +135,13 @@ __global__ void k_total_seeds(TotalSeedArgs a) {
         vf[c] += ks * d;
         vm[c] = -ks * s[c] * d;
       }
-      float* wm = a.d_tan + pmx * m * 3;
-      for (int j = 0; j < 3 * m; ++j) wm[j] = 0.f;
     }
   }
   if (i < a.P0) {   // initial condition (eqs. pulse_IC_Ez/Hx/Hy, IC_loss)
     const long long q = a.ic_base + i;
     const float* f = a.out + q * m;
     float* vf = a.d_out + q * m;
-    float* wg = a.d_tan + q * m * 3;
     for (int j = 0; j < m; ++j) vf[j] = 0.f;
-    for (int j = 0; j < 3 * m; ++j) wg[j] = 0.f;
     const float x = a.ic_xy[i * 2], y = a.ic_xy[i * 2 + 1];
     const float E0 = expf(-a.ic_a * (x * x + y * y));
     const float invP0 = 1.f / (float)a.P0;
@@ -186,7 +183,18 @@ __global__ void k_total_reduce(const float* __restrict__ part, int nblk, float w
   }
 }
 
+__global__ void k_add(float* __restrict__ y, const float* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
 }  // namespace
+
+hipError_t launch_add(float* y, const float* x, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add, dim3((n + 255) / 256), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
 
 int total_seed_blocks(long long P, long long P0) {
   const long long n = P > P0 ? P : P0;
