@@ -33,22 +33,39 @@ __device__ __forceinline__ uint32_t reg_off(int r, uint32_t p0, uint32_t p1, uin
 }
 
 // ---- single-qubit gate on register bit B for statevectors [S0, S0+NS) ----------------------
-// u: u00r,u00i,u01r,u01i,u10r,u10i,u11r,u11i
+// u: u00r,u00i,u01r,u01i,u10r,u10i,u11r,u11i.  Each lane applies the gate to its own amplitude
+// pairs on the matrix cores: v_mfma_f32_4x4x1f32 treats the wave as 16 blocks of 4 lanes,
+// C[m][n] += A[m] B[n] with A[m] from lane 4b + m, B[n] from lane 4b + n and C[m][n] in register m
+// of lane 4b + n.  With lane 4b + m holding row m of the gate's real 4x4 form M (acting on
+// (re x, im x, re y, im y)) as A, and every lane its own pair component k as B, four such steps
+// (k = 0..3) leave M (x, y) of each lane's pair in its four C registers.  The 2x2 products thus
+// leave the vector ALU, which keeps the gate statistics, exchanges and readout.  Called in
+// wave-uniform control flow only: a lane's result depends on the A operands of the other three
+// lanes of its block, so all 64 lanes must be active.
 template <int B, int S0, int NS>
 __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8], const float* u) {
-  const float a0r = u[0], a0i = u[1], a1r = u[2], a1i = u[3];
-  const float b0r = u[4], b0i = u[5], b1r = u[6], b1i = u[7];
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const uint32_t q = threadIdx.x & 3u;   // row m of M held by this lane
+  const bool lo = q < 2, odd = q & 1u;
+  // M rows: (u00r, -u00i, u01r, -u01i), (u00i, u00r, u01i, u01r), (u10r, -u10i, u11r, -u11i),
+  // (u10i, u10r, u11i, u11r); column k of row q:
+  const float e0 = lo ? u[0] : u[4], e1 = lo ? u[1] : u[5], e2 = lo ? u[2] : u[6], e3 = lo ? u[3] : u[7];
+  const float k0 = odd ? e1 : e0;
+  const float k1 = odd ? e0 : -e1;
+  const float k2 = odd ? e3 : e2;
+  const float k3 = odd ? e2 : -e3;
 #pragma unroll
   for (int s = S0; s < S0 + NS; ++s) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       if (r & (1 << B)) continue;
       const int r1 = r | (1 << B);
-      const float xr = sr[s][r], xi = si[s][r], yr = sr[s][r1], yi = si[s][r1];
-      sr[s][r] = a0r * xr - a0i * xi + a1r * yr - a1i * yi;
-      si[s][r] = a0r * xi + a0i * xr + a1r * yi + a1i * yr;
-      sr[s][r1] = b0r * xr - b0i * xi + b1r * yr - b1i * yi;
-      si[s][r1] = b0r * xi + b0i * xr + b1r * yi + b1i * yr;
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k0, sr[s][r], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k1, si[s][r], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k2, sr[s][r1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k3, si[s][r1], c, 0, 0, 0);
+      sr[s][r] = c[0]; si[s][r] = c[1]; sr[s][r1] = c[2]; si[s][r1] = c[3];
     }
   }
 }
