@@ -48,7 +48,8 @@ __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8],
   const uint32_t q = threadIdx.x & 3u;   // row m of M held by this lane
   const bool lo = q < 2, odd = q & 1u;
   // M rows: (u00r, -u00i, u01r, -u01i), (u00i, u00r, u01i, u01r), (u10r, -u10i, u11r, -u11i),
-  // (u10i, u10r, u11i, u11r); column k of row q:
+  // (u10i, u10r, u11i, u11r); column k of row q.  (u points at pinned coefficients: selects
+  // between the elements of a plain local array would become a per-lane indexed scratch load.)
   const float e0 = lo ? u[0] : u[4], e1 = lo ? u[1] : u[5], e2 = lo ? u[2] : u[6], e3 = lo ? u[3] : u[7];
   const float k0 = odd ? e1 : e0;
   const float k1 = odd ? e0 : -e1;
@@ -416,6 +417,18 @@ __device__ __forceinline__ void stat_accum(const float (&sr)[8][8], const float 
   accum_s1<2, C>(sr, si, q + 6);
 }
 
+// One gate's eight coefficients, loaded and pinned in SGPRs like a round's (returned by value:
+// a local array read through apply_gate's selects would be kept in scratch memory instead).
+struct GateCoef {
+  float c[8];
+};
+__device__ __forceinline__ GateCoef load_gate(CP<float> g) {
+  GateCoef G;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) { G.c[e] = g[e]; pin_sgpr(G.c[e]); }
+  return G;
+}
+
 template <int NQ>
 __device__ __forceinline__ void pin_q(float* q) {
 #pragma unroll
@@ -432,10 +445,8 @@ __device__ __forceinline__ void adj_gate_all(float (&sr)[8][8], float (&si)[8][8
   for (int e = 0; e < 6; ++e) q6[e] = 0.f;
   if (PULL) {
     const int gid = gsrc >= 0 ? gsrc : F;
-    float d[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = gtab[gid * kGT + 8 + e];   // U^H
-    apply_gate<B, 0, 8>(sr, si, d);
+    const GateCoef d = load_gate(gtab + gid * kGT + 8);   // U^H
+    apply_gate<B, 0, 8>(sr, si, d.c);
   }
   accum_s<B>(sr, si, q6);
   const float v4[4] = {q6[0] + q6[3], q6[1] + q6[4], q6[2] + q6[5], 0.f};
