@@ -807,10 +807,6 @@ __device__ __forceinline__ void encoding_grads(const float (&sr)[8][8], const fl
   __syncthreads();   // the next tile's first exchange writes the planes
 }
 
-// ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
-// buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
-// PH: the plan may carry CRZ phase stages (false for the uneven-batch kernel, whose circuits have
-// none: the phase code is then compiled out).
 // Packed modes: the product state of point pt0 + SL in statevector slot SL, formed in the mapping
 // emap (no input tangents; an out-of-range point gives the zero state).
 template <int N, int SL>
@@ -850,6 +846,10 @@ __device__ __forceinline__ void packed_state(float (&sr)[8][8], float (&si)[8][8
   }
 }
 
+// ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
+// buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
+// PH: the plan may carry CRZ phase stages (false for the uneven-batch kernel, whose circuits have
+// none: the phase code is then compiled out).
 template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false, bool PH = true>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ mslots,
@@ -1303,7 +1303,14 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         if (k > 0) exchange<N, T, 8, 2>(sr, si, buf, xb + k, lane_words(lanes, 1, R, k, TP, u, pb8));
       }
     }
-    if constexpr (EG) encoding_grads<N, T>(sr, si, buf, red, plan, rounds, gtab, a, pt, valid, u);
+    if constexpr (EG) {
+      // the point index again, from an opaque copy of the thread index: keeping pt and valid live
+      // through the adjoint sweep would cost registers there
+      uint32_t t2 = threadIdx.x;
+      asm volatile("" : "+v"(t2));
+      const long long pt2 = PK ? 0 : (long long)tile * PPW + (long long)(t2 / TP);
+      encoding_grads<N, T>(sr, si, buf, red, plan, rounds, gtab, a, pt2, pt2 < a.P, u);
+    }
   }
 }
 
