@@ -57,16 +57,26 @@ __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8],
   const float k3 = odd ? e2 : -e3;
 #pragma unroll
   for (int s = S0; s < S0 + NS; ++s) {
+    // the four pairs' chains interleaved step by step (independent MFMAs between dependent ones)
+    f32x4 c[4];
+    int rr[4], r1s[4];
+    int np = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       if (r & (1 << B)) continue;
-      const int r1 = r | (1 << B);
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k0, sr[s][r], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k1, si[s][r], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k2, sr[s][r1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_4x4x1f32(k3, si[s][r1], c, 0, 0, 0);
-      sr[s][r] = c[0]; si[s][r] = c[1]; sr[s][r1] = c[2]; si[s][r1] = c[3];
+      rr[np] = r; r1s[np] = r | (1 << B); ++np;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(k0, sr[s][rr[i]], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(k1, si[s][rr[i]], c[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(k2, sr[s][r1s[i]], c[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(k3, si[s][r1s[i]], c[i], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      sr[s][rr[i]] = c[i][0]; si[s][rr[i]] = c[i][1]; sr[s][r1s[i]] = c[i][2]; si[s][r1s[i]] = c[i][3];
     }
   }
 }
