@@ -88,19 +88,27 @@ __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8],
 //   S_z += Im(conj(x0) y0) - Im(conj(x1) y1)
 template <int B, int C>
 __device__ __forceinline__ void accum_s1(const float (&sr)[8][8], const float (&si)[8][8], float* m) {
+  // two partial sums per component (alternate register pairs): shorter dependent FMA chains
+  float a[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  int np = 0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     if (r & (1 << B)) continue;
     const int r1 = r | (1 << B);
+    float* mm = a[np & 1];
+    ++np;
     const float x0r = sr[4 + C][r], x0i = si[4 + C][r], x1r = sr[4 + C][r1], x1i = si[4 + C][r1];
     const float y0r = sr[C][r], y0i = si[C][r], y1r = sr[C][r1], y1i = si[C][r1];
-    m[0] = fmaf(x0r, y1i, m[0]); m[0] = fmaf(-x0i, y1r, m[0]);
-    m[0] = fmaf(x1r, y0i, m[0]); m[0] = fmaf(-x1i, y0r, m[0]);
-    m[1] = fmaf(x1r, y0r, m[1]); m[1] = fmaf(x1i, y0i, m[1]);
-    m[1] = fmaf(-x0r, y1r, m[1]); m[1] = fmaf(-x0i, y1i, m[1]);
-    m[2] = fmaf(x0r, y0i, m[2]); m[2] = fmaf(-x0i, y0r, m[2]);
-    m[2] = fmaf(-x1r, y1i, m[2]); m[2] = fmaf(x1i, y1r, m[2]);
+    mm[0] = fmaf(x0r, y1i, mm[0]); mm[0] = fmaf(-x0i, y1r, mm[0]);
+    mm[0] = fmaf(x1r, y0i, mm[0]); mm[0] = fmaf(-x1i, y0r, mm[0]);
+    mm[1] = fmaf(x1r, y0r, mm[1]); mm[1] = fmaf(x1i, y0i, mm[1]);
+    mm[1] = fmaf(-x0r, y1r, mm[1]); mm[1] = fmaf(-x0i, y1i, mm[1]);
+    mm[2] = fmaf(x0r, y0i, mm[2]); mm[2] = fmaf(-x0i, y0r, mm[2]);
+    mm[2] = fmaf(-x1r, y1i, mm[2]); mm[2] = fmaf(x1i, y1r, mm[2]);
   }
+  m[0] += a[0][0] + a[1][0];
+  m[1] += a[0][1] + a[1][1];
+  m[2] += a[0][2] + a[1][2];
 }
 
 template <int B>
