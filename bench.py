@@ -66,8 +66,8 @@ def matrix_core_share(n_fused: int, n_folded: int = 0) -> float:
 KERNEL_SOURCES = {
     "k_fused": ["fused_kernel.hpp", "fused.hip", "fused.hpp", "fused_n*.hip", "qp_internal.hpp", "grads_dev.hpp",
                 "rot_dev.hpp", "plan.cpp", "plan.hpp"],
-    "k_batch": ["batch.hip", "batch.hpp", "batch_api.cpp", "fused_kernel.hpp", "fused.hpp", "qp_internal.hpp",
-                "grads_dev.hpp", "rot_dev.hpp", "plan.cpp", "plan.hpp"],
+    "k_batch": ["batch.hip", "batch_ph.hip", "batch_kernel.hpp", "batch.hpp", "batch_api.cpp", "fused_kernel.hpp",
+                "fused.hpp", "qp_internal.hpp", "grads_dev.hpp", "rot_dev.hpp", "plan.cpp", "plan.hpp"],
 }
 
 

@@ -280,11 +280,15 @@ qp_status qp_maxwell_fused_noalloc(qp_ctx* ctx, const qp_circuit* c, const float
 /* ---- uneven batch: many circuits in one persistent launch ------------------------------
  * qp_batch_compile plans `count` circuits with their point counts P[count] (host), orders the
  * (circuit, point-tile) work items longest first and uploads the work list.  qp_batch_run
- * evaluates the fused Maxwell step for every circuit in one persistent kernel followed by one
- * reduction kernel; with QP_FLAG_TUNE the grid size is chosen by timing.  io is a host array
- * [count] of per-circuit device pointers.  qp_batch_graph_launch captures the whole step into
- * a hipGraph on first use (per batch, io and workspace) and replays it afterwards; parameters
- * and points may change between replays, the pointers may not.                           */
+ * evaluates the fused Maxwell step for every circuit with persistent kernels, one per qubit-count
+ * class (3..8, 9..11, 12 qubits; circuits with CRZ phase stages in their own class kernels),
+ * followed by one reduction kernel; with QP_FLAG_TUNE the grid size is chosen by timing.  Every
+ * circuit the fused path accepts may be batched, with cycled or RFF encodings, except
+ * angle-given encodings (qp_batch_io carries no per-point angles: QP_EUNSUPPORTED) and circuits
+ * with fewer than 3 outputs (QP_ESHAPE).  io is a host array [count] of per-circuit device
+ * pointers.  qp_batch_graph_launch captures the whole step into a hipGraph on first use (per
+ * batch, io and workspace) and replays it afterwards; parameters and points may change between
+ * replays, the pointers may not.                                                          */
 typedef struct qp_batch_io {
   const float* params;    /* [K_c]          */
   const float* points;    /* [P_c][3]       */
@@ -304,12 +308,14 @@ qp_status qp_batch_run(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
 qp_status qp_batch_graph_launch(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io,
                                 const qp_maxwell_desc* loss_desc, void* ws, size_t ws_bytes,
                                 uint32_t flags);
-/* what: 0 circuits, 1 work items, 2 persistent grid when one qubit-count class has work, 3 graph
+/* what: 0 circuits, 1 work items, 2 persistent grid when only one stream has work, 3 graph
  * captured (0/1), 4 work items of the low class (3..8 qubits), 5 and 6 the grids of the low and
- * high class (9..11 qubits) when both have work: the classes then run as two kernels at once on
- * two streams.  By default the high class runs on 2 workgroups per CU and the low class's
- * workgroups come on top (1.25 x its share of estimated work); QP_FLAG_TUNE also times
- * grids of 1..3 workgroups per CU, other shares and an even split of one grid.             */
+ * high class (9..11 qubits) when the low class and another have work: the low class then runs
+ * on one stream while the high and the 12-qubit classes (one 512-thread workgroup per CU) run one
+ * after the other on a second.  By default the high class runs on 2 workgroups per CU and the
+ * low class's workgroups come on top (1.25 x its share of estimated work); QP_FLAG_TUNE also
+ * times grids of 1..3 workgroups per CU, other shares and an even split of one grid.  7 work
+ * items of the 12-qubit class, 8 work items of circuits with CRZ phase stages.              */
 int64_t qp_batch_info(const qp_batch* b, int32_t what);
 
 /* ---- plain baseline (the speedup denominator) -----------------------------------------

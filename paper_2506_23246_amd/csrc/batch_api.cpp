@@ -11,16 +11,17 @@
 
 using namespace qp;
 
-// Grids of the two qubit-count classes when both have work.  The low class gets its share of
-// `grid` by estimated work, times `bias`; the high class gets the rest of `grid` (split) or all
-// of it (stacked: the low class's workgroups come on top, and the slots they leave when their
-// class is done go to the high class's waves that share the CU).
+// Grids of the low qubit-count class and of the high class when they run at once (the 12-qubit
+// class runs after the high class on one 512-thread workgroup per CU).  The low class gets its
+// share of `grid` by estimated work, times `bias`; the high class gets the rest of `grid` (split)
+// or all of it (stacked: the low class's workgroups come on top, and the slots they leave when
+// their class is done go to the high class's waves that share the CU).
 // Default: stacked, the low class's share by estimated work x 1.25 (the best of the tuner's
 // candidates on the 32-circuit, 4..10-qubit batch, 2.4 % faster than the even split).
 constexpr double kStackedBias = 1.25;
 
 static void class_grids(const qp_batch* b, int grid, double bias, bool stacked, int* g_lo, int* g_hi) {
-  const double share = b->work_lo + b->work_hi > 0.0 ? b->work_lo / (b->work_lo + b->work_hi) : 0.0;
+  const double share = b->work_lo + b->work_rest > 0.0 ? b->work_lo / (b->work_lo + b->work_rest) : 0.0;
   int lo = (int)(grid * share * bias + 0.5);
   lo = lo < 1 ? 1 : (lo > grid - 1 ? grid - 1 : lo);
   *g_lo = lo;
@@ -47,13 +48,18 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
     if (s != QP_OK) return cleanup(s);
     b->circs.push_back(c);
     if (!c->hp.fused_ok) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: %s", i, c->hp.fused_reason.c_str()));
-    if (c->hp.n > 11) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: batch supports n <= 11", i));
     if (c->hp.m < 3) return cleanup(fail(ctx, QP_ESHAPE, "qp_batch_compile: circuit %d needs 3 outputs", i));
-    if (c->hp.enc_kind == QP_ENC_RFF) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: RFF encoding not batched", i));
-    if (!c->hp.phases.empty()) return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: CRZ stages not batched", i));
+    if (c->hp.enc_kind == QP_ENC_ANGLES)   // qp_batch_io carries no per-point angles
+      return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: circuit %d: angle-given encoding not batched", i));
     b->P.push_back(P[i]);
-    b->max_fused = std::max(b->max_fused, (int)c->hp.fused.size());
+    int& mc = c->hp.n >= kBatchBig ? b->max_cols_big : b->max_cols;
+    mc = std::max(mc, (int)c->hp.fused.size() * kGS + n_moments(c));
+    if (!c->hp.phases.empty()) b->table_circs.push_back(i);
+    if (c->hp.enc_kind == QP_ENC_RFF) b->rff_circs.push_back(i);
   }
+  if ((b->max_cols > 0 && batch_lds_bytes(3, b->max_cols) > 160 * 1024) ||
+      (b->max_cols_big > 0 && batch_lds_bytes(kBatchBig, b->max_cols_big) > 160 * 1024))
+    return cleanup(fail(ctx, QP_EUNSUPPORTED, "qp_batch_compile: the gate statistics of a member exceed the LDS"));
   // work items: whole tiles, item cost ~ total / (grid * 6), longest first
   b->grid = ctx->cu_count * 2;
   std::vector<double> tile_cost(count);
@@ -61,7 +67,7 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   double total = 0.0;
   for (int i = 0; i < count; ++i) {
     const auto& hp = b->circs[i]->hp;
-    const int ppw = 256 / (1 << (hp.n - 3));
+    const int ppw = batch_points_per_tile(hp.n);
     tiles[i] = (P[i] + ppw - 1) / ppw;
     tile_cost[i] = (double)hp.fused.size() + 2.0 * (double)hp.rounds.size();
     total += tile_cost[i] * (double)tiles[i];
@@ -75,39 +81,52 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
       b->items.push_back(BatchItem{i, (int)t0, (int)std::min<int64_t>(tpi, tiles[i] - t0), slot});
     nitems[i] = slot;
   }
-  // the low qubit-count class first, each class longest first
-  auto hi = [&](const BatchItem& x) { return b->circs[x.circ]->hp.n > kBatchSplit; };
+  // the segments in order, each longest first
+  auto seg = [&](const BatchItem& x) {
+    const qp_circuit* c = b->circs[x.circ];
+    return batch_segment(c->hp.n, !c->hp.phases.empty());
+  };
   std::stable_sort(b->items.begin(), b->items.end(), [&](const BatchItem& x, const BatchItem& y) {
-    if (hi(x) != hi(y)) return !hi(x);
+    if (seg(x) != seg(y)) return seg(x) < seg(y);
     return tile_cost[x.circ] * x.ntile > tile_cost[y.circ] * y.ntile;
   });
-  b->nitems_lo = 0;
-  b->work_lo = b->work_hi = 0.0;
+  b->work_lo = b->work_rest = 0.0;
   for (const auto& it : b->items) {
-    b->nitems_lo += hi(it) ? 0 : 1;
-    (hi(it) ? b->work_hi : b->work_lo) += tile_cost[it.circ] * it.ntile;
+    const int k = seg(it);
+    b->nitems_seg[k] += 1;
+    (k == kSegLo || k == kSegLoPh ? b->work_lo : b->work_rest) += tile_cost[it.circ] * it.ntile;
   }
   class_grids(b, b->grid, kStackedBias, true, &b->grid_lo, &b->grid_hi);
+  b->grid_big = ctx->cu_count;   // one 512-thread workgroup per CU
   for (int i = 0; i < count; ++i) {
     const int F = (int)b->circs[i]->hp.fused.size();
-    for (int c = 0; c <= F * kGS; ++c) b->cols.push_back(BatchCol{i, c});
-    for (int f = 0; f <= F; ++f) b->gates.push_back(BatchGate{i, f});   // f == F: identity entry
+    const int ncol = F * kGS + n_moments(b->circs[i]);
+    for (int c = 0; c <= ncol; ++c) b->cols.push_back(BatchCol{i, c});
+    if (b->circs[i]->hp.phases.empty())   // CRZ circuits: the fused path's table kernel (run time)
+      for (int f = 0; f <= F; ++f) b->gates.push_back(BatchGate{i, f});   // f == F: identity entry
     for (int k = 0; k < b->circs[i]->hp.K; ++k) b->pars.push_back(BatchGate{i, k});
   }
   // workspace layout
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   BatchLayout& L = b->layout;
   size_t off = 0;
-  L.counter = off; off = al(off + 2 * sizeof(int));
+  L.counter = off; off = al(off + 3 * sizeof(int));
   long long mp = 0;
   L.gtab_c.resize(count); L.counts_c.resize(count); L.m64_c.resize(count); L.mpart_c.resize(count);
+  L.angles_c.assign(count, 0); L.jac_c.assign(count, 0);
   for (int i = 0; i < count; ++i) {
-    const int F = (int)b->circs[i]->hp.fused.size();
-    L.gtab_c[i] = off; off = al(off + sizeof(float) * kGT * (F + 1));
+    const qp_circuit* c = b->circs[i];
+    const int F = (int)c->hp.fused.size(), NM = n_moments(c);
+    // gate entries + identity, then the phase coefficients (as the fused path's table)
+    L.gtab_c[i] = off; off = al(off + sizeof(float) * kGT * (F + 1) + sizeof(uint32_t) * NM);
     L.counts_c[i] = off; off = al(off + 2 * sizeof(int));
-    L.m64_c[i] = off; off = al(off + sizeof(double) * kGS * std::max(F, 1));
+    L.m64_c[i] = off; off = al(off + sizeof(double) * std::max(F * kGS + NM, 1));
+    if (c->hp.enc_kind == QP_ENC_RFF) {
+      L.angles_c[i] = off; off = al(off + sizeof(float) * (size_t)P[i] * c->hp.n);
+      L.jac_c[i] = off; off = al(off + sizeof(float) * (size_t)P[i] * c->hp.n * 3);
+    }
     L.mpart_c[i] = mp;
-    mp += (long long)nitems[i] * F * kGS;
+    mp += (long long)nitems[i] * (F * kGS + NM);
   }
   L.mpart = off; off = al(off + sizeof(float) * (size_t)std::max<long long>(mp, 1));
   L.lpart = off; off = al(off + sizeof(float) * (size_t)std::max<size_t>(b->items.size(), 1));
@@ -148,7 +167,7 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   if (e == hipSuccess) e = hipMemcpy(b->dcols, b->cols.data(), sizeof(BatchCol) * b->cols.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !b->gates.empty()) e = hipMemcpy(b->dgates, b->gates.data(), sizeof(BatchGate) * b->gates.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !b->pars.empty()) e = hipMemcpy(b->dpars, b->pars.data(), sizeof(BatchGate) * b->pars.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = batch_prepare(b->max_fused);
+  if (e == hipSuccess) e = batch_prepare(b->max_cols, b->max_cols_big);
   // the second stream keeps the default priority (no other priority is used anywhere)
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
@@ -187,9 +206,11 @@ extern "C" int64_t qp_batch_info(const qp_batch* b, int32_t what) {
     case 1: return (int64_t)b->items.size();
     case 2: return b->grid;
     case 3: return b->gexec ? 1 : 0;
-    case 4: return b->nitems_lo;
+    case 4: return b->nitems_seg[kSegLo] + b->nitems_seg[kSegLoPh];
     case 5: return b->grid_lo;
     case 6: return b->grid_hi;
+    case 7: return b->nitems_seg[kSegBig] + b->nitems_seg[kSegBigPh];
+    case 8: return b->nitems_seg[kSegLoPh] + b->nitems_seg[kSegHiPh] + b->nitems_seg[kSegBigPh];
     default: return -1;
   }
 }
@@ -234,10 +255,11 @@ static qp_status batch_bind(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io, con
     a.plan = c->dplan;
     a.gtab = reinterpret_cast<float*>(w + L.gtab_c[i]);
     a.points = o.points;
-    a.angles = nullptr;
-    a.jac = nullptr;
+    const bool rff = c->hp.enc_kind == QP_ENC_RFF;
+    a.angles = rff ? reinterpret_cast<const float*>(w + L.angles_c[i]) : nullptr;
+    a.jac = rff ? reinterpret_cast<const float*>(w + L.jac_c[i]) : nullptr;
     a.P = b->P[i];
-    a.ntiles = (int)((b->P[i] + (256 >> (c->hp.n - 3)) - 1) / (256 >> (c->hp.n - 3)));
+    a.ntiles = (int)((b->P[i] + batch_points_per_tile(c->hp.n) - 1) / batch_points_per_tile(c->hp.n));
     a.n_fused = C.F;
     a.out = o.out;
     a.tan = o.tan;
@@ -252,7 +274,7 @@ static qp_status batch_bind(qp_ctx* ctx, qp_batch* b, const qp_batch_io* io, con
     a.lpart = nullptr;
     a.d_angles = nullptr;
     a.d_jac = nullptr;
-    a.n_mom = 0;   // no phase stages in a batch
+    a.n_mom = n_moments(c);
     C.params = o.params;
     C.loss = o.loss;
     C.d_params = o.d_params;
@@ -270,10 +292,24 @@ static hipError_t batch_launch(qp_ctx* ctx, qp_batch* b, const qp_maxwell_desc* 
                                int g_hi) {
   char* w = static_cast<char*>(ws);
   const BatchLayout& L = b->layout;
-  return launch_batch(b->dcirc, (int)b->circs.size(), b->ditems, (int)b->items.size(), b->nitems_lo, b->dgates,
-                      (int)b->gates.size(), b->dcols, (int)b->cols.size(), b->dpars, (int)b->pars.size(),
+  // Circuits with CRZ phase stages take the fused path's gate and phase table kernels, RFF
+  // circuits the fused path's angle kernel; both write into the batch workspace before the
+  // batch kernels read it.
+  for (int i : b->table_circs) {
+    const qp_circuit* c = b->circs[i];
+    hipError_t e = launch_gate_table(c->dplan, (int)c->hp.fused.size(), n_moments(c), b->hcirc[i].params,
+                                     reinterpret_cast<float*>(w + L.gtab_c[i]), 0, ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int i : b->rff_circs) {
+    const FusedArgs& a = b->hcirc[i].a;
+    hipError_t e = launch_rff(b->circs[i]->dplan, a.points, a.P, const_cast<float*>(a.angles),
+                              const_cast<float*>(a.jac), ctx->stream);
+    if (e != hipSuccess) return e;
+  }
+  return launch_batch(b->dcirc, (int)b->circs.size(), b->ditems, b->nitems_seg, b->dgates, (int)b->gates.size(), b->dcols, (int)b->cols.size(), b->dpars, (int)b->pars.size(),
                       reinterpret_cast<int*>(w + L.counter), reinterpret_cast<float*>(w + L.mpart),
-                      reinterpret_cast<float*>(w + L.lpart), grid, g_lo, g_hi, b->max_fused,
+                      reinterpret_cast<float*>(w + L.lpart), grid, g_lo, g_hi, b->grid_big, b->max_cols, b->max_cols_big,
                       ld->kind == QP_LOSS_DIEL_SPLIT ? 1 : 0, ctx->stream, b->aux, b->ev_fork, b->ev_join,
                       ctx->timing ? ctx->ev0 : nullptr, ctx->timing ? ctx->ev1 : nullptr);
 }
@@ -290,7 +326,8 @@ extern "C" qp_status qp_batch_run(qp_ctx* ctx, qp_batch* b, const qp_batch_io* i
     hipEventCreate(&e1);
     struct Shape { int grid, lo, hi; };
     std::vector<Shape> shapes;
-    const bool two = b->nitems_lo > 0 && b->nitems_lo < (int)b->items.size();
+    const int n_low = b->nitems_seg[kSegLo] + b->nitems_seg[kSegLoPh];
+    const bool two = n_low > 0 && n_low < (int)b->items.size();
     for (int mult : {1, 2, 3, 4}) {
       const int g = ctx->cu_count * mult;
       if (!two) { shapes.push_back({g, b->grid_lo, b->grid_hi}); continue; }

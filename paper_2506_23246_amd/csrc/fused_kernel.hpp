@@ -866,8 +866,8 @@ __device__ __forceinline__ void packed_state(float (&sr)[8][8], float (&si)[8][8
 
 // ---- one tile of PPW points: forward, readout, seeds, adjoint --------------------------------
 // buf: EXS exchange planes; slots: per-wave gate statistics [WAVES][F][kGS]; red: [WAVES][40].
-// PH: the plan may carry CRZ phase stages (false for the uneven-batch kernel, whose circuits have
-// none: the phase code is then compiled out).
+// PH: the plan may carry CRZ phase stages (false where the caller knows it has none, as the
+// uneven-batch kernels do for such circuits: the phase code is then compiled out).
 template <int N, int T, int EXS, int MODE, bool SG = true, bool EG = false, bool PH = true>
 __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2* __restrict__ buf,
                                            float* __restrict__ slots, float* __restrict__ mslots,

@@ -201,3 +201,100 @@ def test_batch_with_one_class_only(env, cls):
                 assert rel(t2n(bufs[i]["grad"]), t2n(singles[i]["grad"])) < 1e-6
                 assert rel(t2n(bufs[i]["loss"]), t2n(singles[i]["loss"])) < 1e-6
     assert b.info(2) % ctx.cu_count == 0
+
+
+def _mixed_members():
+    """Members of every work-item segment: RFF encodings, Cross-Mesh CRZ phase stages in the low,
+    high and 12-qubit classes, a 12-qubit ring circuit, and plain low and high members; point
+    counts that span several tiles with a ragged last one (one point per tile at 12 qubits)."""
+    import math
+    rng = np.random.default_rng(77)
+
+    def rff_enc(n, F=16):
+        B = rng.standard_normal((F, 3)).astype(np.float32)
+        Wm = (rng.standard_normal((n, 2 * F)) / math.sqrt(2 * F)).astype(np.float32)
+        return W.Encoding(kind=W.ENC_RFF, gate=W.ENC_RY, scale=W.SCALE_NONE, rff_B=B, rff_W=Wm)
+
+    circs = [
+        (W.layered(5, 2, "rot", lambda l: W.ring(5, W.CZ, 1 + l % 2), name="rff_5q2l", enc=rff_enc(5)), 301),
+        (W.cross_mesh(4, 2, rot="x"), 203),
+        (W.layered(6, 3, "xyz", lambda l: W.ring(6, W.CNOT, 1), name="ring_6q3l"), 190),
+        (W.cross_mesh(9, 1, rot="xz"), 11),
+        (W.layered(10, 2, "xyz", lambda l: W.ring(10, W.CZ, 1), name="ring_10q2l",
+                   enc=rff_enc(10)), 13),
+        (W.layered(12, 2, "xyz", lambda l: W.ring(12, W.CNOT, 1), name="ring_12q2l"), 5),
+        (W.cross_mesh(12, 1, rot="x"), 3),
+    ]
+    out = []
+    for c, P in circs:
+        pts = W.uniform_points(rng, P)
+        prm = W.uniform_params(rng, c.n_params)
+        out.append(W.Workload(c.name, c, prm, pts, W.MaxwellDesc(W.LOSS_DIEL_SPLIT, 4.0, 0.0)))
+    return out
+
+
+def test_batch_mixed_segments_match_oracle_and_single_path(env):
+    """RFF encodings, CRZ phase stages and 12-qubit members in one batch: every member against the
+    oracle (split dielectric loss), outputs bitwise equal to the single-circuit path."""
+    import torch
+    from paper_2506_23246_amd.api import Circuit
+    ctx, s = env
+    ws = _mixed_members()
+    b = _batch(ctx, ws)
+    assert b.info(7) > 0 and b.info(8) > 0   # 12-qubit items; items of CRZ circuits
+    loss = ws[0].loss
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, loss)
+        singles = [Circuit(ctx, w.circuit).maxwell(w.params, w.points, loss) for w in ws]
+    s.synchronize()
+    for i, w in enumerate(ws):
+        f, g, Lo, grad = O.maxwell_eval(w.circuit, w.params, w.points, loss)
+        e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
+                 loss=rel(t2n(bufs[i]["loss"]), [Lo]), grad=rel(t2n(bufs[i]["grad"]), grad))
+        report(f"mixed batch {w.name} P={len(w.points)}", **e)
+        for k, v in e.items():
+            assert v < TOL, (w.name, k, v)
+        for key in ("out", "tan"):
+            assert np.array_equal(t2n(bufs[i][key]), t2n(singles[i][key])), (w.name, key)
+        assert rel(t2n(bufs[i]["grad"]), t2n(singles[i]["grad"])) < 1e-6
+        assert rel(t2n(bufs[i]["loss"]), t2n(singles[i]["loss"])) < 1e-6
+
+
+def test_batch_mixed_segments_graph_replay(env):
+    """The table and RFF-angle kernels of CRZ and RFF members sit inside the captured graph: a
+    replay after new parameters and points are written in place equals an eager run."""
+    import torch
+    ctx, s = env
+    ws = _mixed_members()
+    b = _batch(ctx, ws)
+    loss = ws[0].loss
+    rng = np.random.default_rng(9)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, loss, graph=True)
+        for i, w in enumerate(ws):
+            bufs[i]["params"].copy_(torch.tensor(rng.uniform(0, 6.28, w.circuit.n_params), dtype=torch.float32))
+            bufs[i]["points"].copy_(torch.tensor(rng.uniform(-1, 1, (len(w.points), 3)), dtype=torch.float32))
+        b.run(arr, loss, graph=True)
+    s.synchronize()
+    got = [{k: t2n(bufs[i][k]).copy() for k in ("out", "tan", "loss", "grad")} for i in range(len(ws))]
+    with torch.cuda.stream(s):
+        b.run(arr, loss)
+    s.synchronize()
+    for i in range(len(ws)):
+        for k in got[i]:
+            assert np.array_equal(got[i][k], t2n(bufs[i][k])), (ws[i].name, k)
+    i = 1   # a CRZ member against the oracle on the new values
+    _, _, Lo, grad = O.maxwell_eval(ws[i].circuit, t2n(bufs[i]["params"]), t2n(bufs[i]["points"]), loss)
+    assert rel(got[i]["grad"], grad) < TOL and rel(got[i]["loss"], [Lo]) < TOL
+
+
+def test_batch_rejects_angle_encoding(env):
+    """qp_batch_io carries no per-point angles: an angle-given circuit is refused at compile time."""
+    from paper_2506_23246_amd import _lib as L
+    from paper_2506_23246_amd.api import Batch
+    ctx, _ = env
+    c = W.paper_context_circuit()
+    with pytest.raises(L.QPError, match="angle-given encoding not batched"):
+        Batch(ctx, [c], [16])
