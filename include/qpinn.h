@@ -71,9 +71,13 @@ enum { QP_LOSS_VACUUM = 0, QP_LOSS_DIEL_SPLIT = 1, QP_LOSS_DIEL_INTUITIVE = 2 };
 /* Flags (bitwise or). */
 #define QP_FLAG_NO_TANGENTS 0x1u  /* qp_simulate: tangents not needed (tan may be NULL)      */
 #define QP_FLAG_LOSS_SUM    0x2u  /* Maxwell: sum of squared residuals instead of MSE means  */
-#define QP_FLAG_TUNE        0x4u  /* time the candidate launch shapes on first use and cache;
-                                     the first tuned call per point-count bucket waits for the
-                                     stream (HIP events), so it must not run under graph capture */
+#define QP_FLAG_TUNE        0x4u  /* Maxwell and batch calls: time the candidate launch shapes
+                                     on first use and cache the fastest; for the fused Maxwell
+                                     call the candidates also include the dense-block path when
+                                     the circuit has one and the workspace covers it
+                                     (qp_workspace_bytes with this flag); the first tuned call
+                                     per point-count bucket waits for the stream (HIP events), so
+                                     it must not run under graph capture                        */
 #define QP_FLAG_DENSE_MFMA  0x8u  /* force the dense-block MFMA path (where the plan has one) */
 #define QP_FLAG_GATES_FP32  0x10u /* build the 2x2 gate table in FP32 instead of FP64-rounded  */
 
@@ -140,7 +144,9 @@ void qp_circuit_destroy(qp_circuit* c);
  *       6 threads per workgroup of the fused kernel, 7 points per workgroup tile,
  *       8 LDS exchange planes, 9 persistent workgroups per CU, 10 dense 2^5 blocks,
  *       11 leading rounds folded into the encoding (an opening rotation stage acts on the
- *       product state), 12 fused gates in those rounds.  -1 for an unknown code.            */
+ *       product state), 12 fused gates in those rounds, 13 fusion width chosen by the tuner
+ *       for Maxwell calls (1: dense 32x32 blocks, 0: 2x2 gates in the fused kernel).  -1 for
+ *       an unknown code.                                                                     */
 int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
 
 /* Launch shape of the fused kernel for this circuit (what the autotuner sets): exchange_planes
@@ -148,7 +154,9 @@ int64_t qp_circuit_info(const qp_circuit* c, int32_t what);
  * wg_per_cu = persistent workgroups per CU, 1 at 12 qubits, 1..4 below (above 2 the grid runs
  * in two generations).  The choice changes speed, not results beyond rounding order.
  * QP_EINVAL for other values or a shape whose LDS does not fit a CU.  Circuit compilation
- * applies a choice cached by an earlier tuned run (QP_TUNE_CACHE) for the same circuit shape. */
+ * applies a choice cached by an earlier tuned run (QP_TUNE_CACHE) for the same circuit shape,
+ * the fusion width included; setting a launch shape here puts Maxwell calls back on the fused
+ * kernel.                                                                                   */
 qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_planes, int32_t wg_per_cu);
 
 /* Points per chunk of the dense-block MFMA path (QP_FLAG_DENSE_MFMA), which streams the
@@ -162,7 +170,11 @@ qp_status qp_circuit_set_dense_chunk(qp_circuit* c, int32_t points);
  * (capacity cap bytes); *bytes receives the image size.  QP_EWORKSPACE if cap is too small.  */
 qp_status qp_plan_image(const qp_circuit_desc* desc, void* host_buf, size_t cap, size_t* bytes);
 
-/* Workspace bytes for qp_simulate / qp_vjp / qp_maxwell_fused with P points. */
+/* Workspace bytes for qp_simulate / qp_vjp / qp_maxwell_fused with P points and `flags`.  With
+ * QP_FLAG_TUNE, or once the tuner chose the dense-block path for this circuit, the size also
+ * covers that path; a call accepts any workspace that covers the path it must take (the fused
+ * kernel's, or the dense path's with QP_FLAG_DENSE_MFMA) and then keeps Maxwell calls on the
+ * fused kernel when the dense path does not fit.                                            */
 size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags);
 
 /* ---- evaluation ------------------------------------------------------------------------

@@ -135,7 +135,7 @@ class Circuit:
         L.check(L.qp_circuit_set_dense_chunk(self.h, int(points)), self.ctx.h)
 
     def workspace(self, P: int, flags: int = 0):
-        nb = int(L.qp_workspace_bytes(self.h, int(P), int(flags) & L.QP_FLAG_DENSE_MFMA))
+        nb = int(L.qp_workspace_bytes(self.h, int(P), int(flags) & (L.QP_FLAG_DENSE_MFMA | L.QP_FLAG_TUNE)))
         key = ("ws", nb)
         if key not in self._ws:
             self._ws = {key: _aligned_bytes(nb, self.ctx.dev)}

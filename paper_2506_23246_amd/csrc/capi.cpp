@@ -152,6 +152,7 @@ extern "C" qp_status qp_circuit_set_launch(qp_circuit* c, int32_t exchange_plane
     return fail(c->ctx, QP_EINVAL, "qp_circuit_set_launch: %d workgroups of %zu LDS bytes do not fit a CU", wg_per_cu, lds);
   c->exs = exchange_planes;
   c->wg_per_cu = wg_per_cu;
+  c->use_dense = false;   // an explicit launch shape of the fused kernel
   return QP_OK;
 }
 
@@ -203,6 +204,7 @@ extern "C" int64_t qp_circuit_info(const qp_circuit* c, int32_t what) {
         for (const auto& f : c->hp.fused) h += f.stat_out ? 1 : 0;
       return h;
     }
+    case 13: return c->use_dense ? 1 : 0;
     default: return -1;
   }
 }
@@ -226,7 +228,11 @@ void qp::choose_launch(qp_ctx* ctx, qp_circuit* c) {
   int wg = (int)std::min<size_t>(max_wg_vgpr, lds_cap / std::max<size_t>(lds, 1));
   c->wg_per_cu = std::max(wg, 1);
   const TuneEntry* te = tune_lookup(ctx, c);
-  if (te && !(NM > 0 && te->exs == 4)) { c->exs = te->exs; c->wg_per_cu = te->wg_per_cu; }
+  if (te && !(NM > 0 && te->exs == 4)) {
+    c->exs = te->exs;
+    c->wg_per_cu = te->wg_per_cu;
+    c->use_dense = te->dense != 0 && c->hp.dense_ok;
+  }
 }
 
 int qp::n_moments(const qp_circuit* c) { return (int)c->hp.phases.size() * phase_terms(c->hp.n); }
@@ -271,11 +277,21 @@ static DenseLayout dense_ws(const qp_circuit* c, int64_t P, bool grad, int* Pc_o
   return dense_layout(c->hp.n, c->hp.m, (int)c->hp.dgroups.size(), (int)c->hp.docc.size() / 2, P, Pc, nwg, grad);
 }
 
-extern "C" size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags) {
-  if (!c || P < 0) return 0;
+size_t qp::ws_required(const qp_circuit* c, int64_t P, uint32_t flags) {
   if (flags & QP_FLAG_DENSE_MFMA) return c->hp.dense_ok ? dense_ws(c, P, true, nullptr, nullptr).total : 0;
   const int cap = c->ctx->cu_count * 4;   // covers every launch shape the tuner may pick
   return fused_layout(c, P, cap).total;
+}
+
+// With QP_FLAG_TUNE, or once the tuner chose the dense-block path, also large enough for that
+// path, so that the tuner can time it and Maxwell calls can take it; a smaller workspace (at
+// least the fused path's) is accepted and then keeps Maxwell calls on the fused path.
+extern "C" size_t qp_workspace_bytes(const qp_circuit* c, int64_t P, uint32_t flags) {
+  if (!c || P < 0) return 0;
+  size_t need = ws_required(c, P, flags);
+  if (!(flags & QP_FLAG_DENSE_MFMA) && ((flags & QP_FLAG_TUNE) || c->use_dense) && c->hp.dense_ok)
+    need = std::max(need, ws_required(c, P, QP_FLAG_DENSE_MFMA));
+  return need;
 }
 
 static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,
@@ -297,13 +313,14 @@ static qp_status check_common(qp_ctx* ctx, const qp_circuit* c, const float* par
     }
   }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(ctx, QP_EWORKSPACE, "%s: workspace null or not 256-byte aligned", who);
-  if (ws_bytes < qp_workspace_bytes(c, P, flags))
-    return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, qp_workspace_bytes(c, P, flags));
+  if (ws_bytes < ws_required(c, P, flags))
+    return fail(ctx, QP_EWORKSPACE, "%s: workspace %zu < %zu bytes", who, ws_bytes, ws_required(c, P, flags));
   return QP_OK;
 }
 
-// Dense-block MFMA sequence (QP_FLAG_DENSE_MFMA) for the three evaluation entry points.
-static qp_status run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
+// Dense-block MFMA sequence (QP_FLAG_DENSE_MFMA, or the tuner's choice for Maxwell calls) for the
+// three evaluation entry points.
+qp_status qp::run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                            const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                            float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
                            uint32_t flags) {
@@ -490,7 +507,14 @@ qp_status qp::maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* param
   if (flags & QP_FLAG_DENSE_MFMA)
     return run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                      ws, flags);
-  if ((flags & QP_FLAG_TUNE) && P > 0) tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws);
+  // the dense-block path is open to this call: the circuit has one, the workspace covers it and
+  // no input gradient is asked for (that path does not form them)
+  const bool dense_open = c->hp.dense_ok && !d_angles && !d_jac && ws_bytes >= ws_required(c, P, QP_FLAG_DENSE_MFMA);
+  if ((flags & QP_FLAG_TUNE) && P > 0)
+    tune_circuit(ctx, const_cast<qp_circuit*>(c), params, points, angles, jac, P, ld, ws, dense_open);
+  if (c->use_dense && dense_open)
+    return run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
+                     ws, flags);
   return run_fused(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, out, tan, nullptr, nullptr, loss, d_params,
                    d_angles, d_jac, ws, flags, 0, 0);
 }

@@ -31,6 +31,7 @@ struct qp_circuit {
   int exs = 4;         // exchange planes per LDS phase
   int wg_per_cu = 1;   // persistent workgroups per CU
   int dense_chunk = 0; // points per chunk of the dense-block path (0: about 2 GiB of statevectors)
+  bool use_dense = false;   // the tuner's fusion width for Maxwell calls: dense 32x32 blocks
 };
 
 namespace qp {
@@ -47,6 +48,13 @@ qp_status run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* par
                     const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                     float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,
                     float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override);
+qp_status run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
+                    const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
+                    float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,
+                    uint32_t flags);
+// Workspace a call with `flags` cannot do without (the fused path's, or the dense path's with
+// QP_FLAG_DENSE_MFMA); qp_workspace_bytes may ask for more (see there).
+size_t ws_required(const qp_circuit* c, int64_t P, uint32_t flags);
 // Argument checks and launch sequence of the fused Maxwell evaluation (who names the entry point
 // in error messages).
 qp_status maxwell_entry(qp_ctx* ctx, const qp_circuit* c, const float* params, const float* points,

@@ -699,7 +699,8 @@ hipError_t dense_run(const DenseCall& c, hipStream_t st) {
   hipLaunchKernelGGL(k_dense_reduce, dim3(nb(cols * 64, 256)), dim3(256), 0, st, mpart, G, c.nwg, m64,
                      c.loss.maxwell ? lterm : nullptr, c.P, c.loss_out);
   if (c.n_docc > 0) hipLaunchKernelGGL(k_dense_occ, dim3(c.n_docc), dim3(64), 0, st, plan, c.params, m64, contrib);
-  if (c.K > 0) hipLaunchKernelGGL(k_dense_params, dim3(nb(c.K, 128)), dim3(128), 0, st, plan, contrib, c.d_params);
+  if (c.K > 0 && c.d_params)
+    hipLaunchKernelGGL(k_dense_params, dim3(nb(c.K, 128)), dim3(128), 0, st, plan, contrib, c.d_params);
   return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ extern "C" qp_status qp_maxwell_fused_noalloc(qp_ctx* ctx, const qp_circuit* c, 
   if (P < 0) return qp::fail(ctx, QP_EINVAL, "%s: P < 0", who);
   if (ctx->device < 0 || ctx->device >= qp::kMaxDevices)
     return qp::fail(ctx, QP_EUNSUPPORTED, "%s: device index %d out of range", who, ctx->device);
-  const size_t need = qp_workspace_bytes(c, P, 0);
+  const size_t need = qp::ws_required(c, P, 0);
   if (need > QP_NOALLOC_SCRATCH_BYTES)
     return qp::fail(ctx, QP_EWORKSPACE, "%s: this call needs %zu scratch bytes, above the fixed %zu; use qp_maxwell_fused "
                     "with a workspace or split the points", who, need, (size_t)QP_NOALLOC_SCRATCH_BYTES);

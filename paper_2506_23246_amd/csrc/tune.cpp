@@ -1,5 +1,6 @@
 // Autotuner: times every legal (exchange depth, workgroups per CU) pair of a circuit's fused
-// Maxwell step with HIP events on the context stream and keeps the fastest.  The key is
+// Maxwell step, and the dense-block path where the call may take it, with HIP events on the
+// context stream and keeps the fastest.  The key is
 // (arch, n, rounds, fused gates, entangler kinds) plus a point-count bucket; results persist as
 // JSON lines in the file named by QP_TUNE_CACHE (if set; later lines override earlier ones).
 // Each tuning also records its choice under the bucket "any", which circuit compilation looks up
@@ -34,9 +35,13 @@ void load_file() {
   while (std::fgets(line, sizeof(line), f)) {
     char key[512];
     TuneEntry e{};
-    if (std::sscanf(line, "{\"key\": \"%511[^\"]\", \"exs\": %d, \"wg_per_cu\": %d, \"ms\": %lf}", key, &e.exs,
-                    &e.wg_per_cu, &e.ms) == 4)
+    int dense = 0;   // lines without the field: the fused path
+    const int got = std::sscanf(line, "{\"key\": \"%511[^\"]\", \"exs\": %d, \"wg_per_cu\": %d, \"ms\": %lf, \"dense\": %d}",
+                                key, &e.exs, &e.wg_per_cu, &e.ms, &dense);
+    if (got >= 4) {
+      e.dense = got == 5 ? (dense != 0) : 0;
       g_cache[key] = e;
+    }
   }
   std::fclose(f);
 }
@@ -46,7 +51,8 @@ void append_file(const std::string& key, const TuneEntry& e) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"exs\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}\n", key.c_str(), e.exs, e.wg_per_cu, e.ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"exs\": %d, \"wg_per_cu\": %d, \"ms\": %.6f, \"dense\": %d}\n", key.c_str(), e.exs,
+               e.wg_per_cu, e.ms, e.dense);
   std::fclose(f);
 }
 }  // namespace
@@ -76,7 +82,7 @@ const TuneEntry* tune_lookup(const qp_ctx* ctx, const qp_circuit* c) {
 }
 
 void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* points, const float* angles,
-                  const float* jac, int64_t P, const qp_maxwell_desc* ld, void* ws) {
+                  const float* jac, int64_t P, const qp_maxwell_desc* ld, void* ws, bool dense_ok) {
   const std::string key = pkey(tune_key(ctx, c), P);
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -85,6 +91,7 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
     if (it != g_cache.end()) {
       c->exs = it->second.exs;
       c->wg_per_cu = it->second.wg_per_cu;
+      c->use_dense = it->second.dense != 0 && c->hp.dense_ok;
       return;
     }
   }
@@ -118,10 +125,25 @@ void tune_circuit(qp_ctx* ctx, qp_circuit* c, const float* params, const float* 
       if (best_ms < best.ms) best = TuneEntry{exs, wg, best_ms};
     }
   }
+  if (dense_ok) {   // fusion width: the dense-block path keeps the fused path's launch shape
+    double best_ms = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, ctx->stream);
+      run_dense(ctx, c, kModeMaxwell, params, points, angles, jac, P, ld, nullptr, nullptr, nullptr, nullptr, nullptr,
+                nullptr, ws, 0);
+      hipEventRecord(e1, ctx->stream);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best_ms = std::min(best_ms, (double)ms);
+    }
+    if (best_ms < best.ms) { best.ms = best_ms; best.dense = 1; }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->exs = best.exs;
   c->wg_per_cu = best.wg_per_cu;
+  c->use_dense = best.dense != 0;
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string any = tune_key(ctx, c) + "/any";
   g_cache[key] = best;
