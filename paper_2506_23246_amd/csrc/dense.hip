@@ -239,6 +239,7 @@ void k_dense_apply(const QPlanDev* __restrict__ plan, const float* __restrict__ 
     f32x16 acc0, acc1, acc2, acc3;
 #pragma unroll
     for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; acc2[v] = 0.f; acc3[v] = 0.f; }
+    __builtin_amdgcn_s_setprio(1);   // raised priority while issuing the matrix-core chain
 #pragma unroll
     for (int i = 0; i < 32; i += 2) {
       acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv[i], acc0, 0, 0, 0);
@@ -246,6 +247,7 @@ void k_dense_apply(const QPlanDev* __restrict__ plan, const float* __restrict__ 
       acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i + 1) * 64 + lane], bv[i + 1], acc2, 0, 0, 0);
       acc3 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i + 1) * 64 + lane], bv[i + 1], acc3, 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int v = 0; v < 16; ++v) { acc0[v] += acc2[v]; acc1[v] += acc3[v]; }
     if (ok) {
@@ -487,12 +489,14 @@ __global__ __launch_bounds__(256) void k_dense_adj(const QPlanDev* __restrict__ 
         f32x16 acc0, acc1;
 #pragma unroll
         for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; }
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
           const float bv = Tf[2 * i * LD];
           acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(0 * 32 + i) * 64 + lane], bv, acc0, 0, 0, 0);
           acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[(1 * 32 + i) * 64 + lane], bv, acc1, 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
         float2* dst = X + (size_t)(is_psi ? s : 4 + s) * DIM * Pc;
 #pragma unroll
         for (int v = 0; v < 16; v += 2) {
@@ -516,6 +520,7 @@ __global__ __launch_bounds__(256) void k_dense_adj(const QPlanDev* __restrict__ 
       }
       __syncthreads();
       const int a = lane & 31;
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const int col = wave * 16 + 2 * kk + h;
@@ -526,6 +531,7 @@ __global__ __launch_bounds__(256) void k_dense_adj(const QPlanDev* __restrict__ 
         mi = __builtin_amdgcn_mfma_f32_32x32x2f32(lv.x, pv.y, mi, 0, 0, 0);
         mi = __builtin_amdgcn_mfma_f32_32x32x2f32(-lv.y, pv.x, mi, 0, 0, 0);
       }
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   // combine the four waves (fixed order) and add to this workgroup's slot
