@@ -68,7 +68,7 @@ __device__ __forceinline__ void apply_gate(float (&sr)[8][8], float (&si)[8][8],
     }
     // Raised wave priority while this wave issues its matrix-core chains: the SIMD's other wave
     // (statistics, exchanges) fills the issue slots between them instead of delaying the next
-    // link of a chain (12-qubit step 322 -> 299 ms).
+    // link of a chain (12-qubit step 322 -> 298 ms).
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(k0, sr[s][rr[i]], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -277,6 +277,10 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
   constexpr uint32_t PLANE = T * 8 * 8;   // bytes; a power of two above every in-plane offset
   const char* b = reinterpret_cast<const char*>(buf);
   const uint32_t base = rb | (PL * PLANE);   // plane PL folded into the base: one XOR per access
+  // raised wave priority while issuing the reads (as for the matrix-core chains): after a
+  // barrier the wave's reads go out ahead of the other wave's arithmetic (12-qubit step 298 ->
+  // 284 ms)
+  __builtin_amdgcn_s_setprio(1);
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -285,6 +289,7 @@ __device__ __forceinline__ void xread(float (&sr)[8][8], float (&si)[8][8], cons
       const float2 v = *reinterpret_cast<const float2*>(b + h * PLANE + o);
       if (h == 0) { sr[SV0][r] = v.x; si[SV0][r] = v.y; } else { sr[SV1][r] = v.x; si[SV1][r] = v.y; }
     }
+  __builtin_amdgcn_s_setprio(0);
   if (SG && signs) {   // a CZ stage: negate the amplitudes whose sign bit is set (uniform branch)
     // The empty volatile asm keeps this a branch: merged into the unconditional path, the flips
     // would cost two XORs per amplitude on every exchange and consume the loaded values at once,
