@@ -136,10 +136,12 @@ hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* item
                         int npars, int* counter, float* mpart, float* lpart, int grid, int grid_lo, int grid_hi,
                         int grid_big, int max_cols, int max_cols_big, int count_needed, hipStream_t st,
                         hipStream_t aux, hipEvent_t ev_fork, hipEvent_t ev_join, hipEvent_t ev0, hipEvent_t ev1) {
+  hipError_t e = hipSuccess;
+  auto keep = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   hipLaunchKernelGGL(k_batch_gates, dim3(ngates > 0 ? (ngates + 127) / 128 : 1), dim3(128), 0, st,
                      circs, gates, ngates, counter);
   if (count_needed) hipLaunchKernelGGL(k_batch_counts, dim3(ncirc), dim3(256), 0, st, circs);
-  if (ev0) hipEventRecord(ev0, st);
+  if (ev0) keep(hipEventRecord(ev0, st));
   const BatchItem* seg_items[kNumSegs];
   for (int sg = 0, off = 0; sg < kNumSegs; off += nitems_seg[sg], ++sg) seg_items[sg] = items + off;
   const int n_low = nitems_seg[kSegLo] + nitems_seg[kSegLoPh];
@@ -151,24 +153,22 @@ hipError_t launch_batch(const BatchCirc* circs, int ncirc, const BatchItem* item
     const size_t dyn = sg % 3 == kSegBig ? batch_dyn_lds_bytes(512, max_cols_big) : batch_dyn_lds_bytes(256, max_cols);
     return launch_batch_seg(sg, g, dyn, s, circs, seg_items[sg], nitems_seg[sg], counter + sg, mpart, lpart);
   };
-  hipError_t e = hipSuccess;
-  auto keep = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   if (two) {
     // the low segments on st, the others one after the other on aux, at the same time
-    hipEventRecord(ev_fork, st);
-    hipStreamWaitEvent(aux, ev_fork, 0);
+    keep(hipEventRecord(ev_fork, st));
+    keep(hipStreamWaitEvent(aux, ev_fork, 0));
     keep(seg(kSegLo, st, grid_lo));
     keep(seg(kSegLoPh, st, grid_lo));
     keep(seg(kSegHi, aux, grid_hi));
     keep(seg(kSegHiPh, aux, grid_hi));
     keep(seg(kSegBig, aux, grid_big));
     keep(seg(kSegBigPh, aux, grid_big));
-    hipEventRecord(ev_join, aux);
-    hipStreamWaitEvent(st, ev_join, 0);
+    keep(hipEventRecord(ev_join, aux));
+    keep(hipStreamWaitEvent(st, ev_join, 0));
   } else {
     for (int sg = 0; sg < kNumSegs; ++sg) keep(seg(sg, st, sg % 3 == kSegBig ? grid_big : grid));
   }
-  if (ev1) hipEventRecord(ev1, st);
+  if (ev1) keep(hipEventRecord(ev1, st));
   hipLaunchKernelGGL(k_batch_reduce, dim3((ncols + 3) / 4), dim3(256), 0, st, circs, cols, ncols, mpart, lpart);
   if (npars > 0) hipLaunchKernelGGL(k_batch_grads, dim3((npars + 127) / 128), dim3(128), 0, st, circs, pars, npars);
   keep(hipGetLastError());

@@ -110,7 +110,7 @@ extern "C" qp_status qp_batch_compile(qp_ctx* ctx, int32_t count, const qp_circu
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   BatchLayout& L = b->layout;
   size_t off = 0;
-  L.counter = off; off = al(off + 3 * sizeof(int));
+  L.counter = off; off = al(off + kNumSegs * sizeof(int));   // one work counter per segment
   long long mp = 0;
   L.gtab_c.resize(count); L.counts_c.resize(count); L.m64_c.resize(count); L.mpart_c.resize(count);
   L.angles_c.assign(count, 0); L.jac_c.assign(count, 0);
