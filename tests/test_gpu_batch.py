@@ -298,3 +298,28 @@ def test_batch_rejects_angle_encoding(env):
     c = W.paper_context_circuit()
     with pytest.raises(L.QPError, match="angle-given encoding not batched"):
         Batch(ctx, [c], [16])
+
+
+@pytest.mark.parametrize("kind,loss_sum", [(W.LOSS_DIEL_INTUITIVE, False), (W.LOSS_VACUUM, True)])
+def test_batch_mixed_segments_other_losses(env, kind, loss_sum):
+    """The mixed batch under the intuitive dielectric loss, and under the vacuum loss with
+    QP_FLAG_LOSS_SUM (plain sums: the oracle's mean loss and gradient times the member's point
+    count), against the oracle member by member."""
+    import torch
+    from paper_2506_23246_amd import _lib as L
+    ctx, s = env
+    ws = _mixed_members()
+    loss = W.MaxwellDesc(kind, 4.0, 0.0)
+    b = _batch(ctx, ws)
+    with torch.cuda.stream(s):
+        arr, bufs = b.io([w.params for w in ws], [w.points for w in ws])
+        b.run(arr, loss, flags=L.QP_FLAG_LOSS_SUM if loss_sum else 0)
+    s.synchronize()
+    for i, w in enumerate(ws):
+        f, g, Lo, grad = O.maxwell_eval(w.circuit, w.params, w.points, loss)
+        scale = len(w.points) if loss_sum else 1.0
+        e = dict(f=rel(t2n(bufs[i]["out"]), f), g=rel(t2n(bufs[i]["tan"]), g),
+                 loss=rel(t2n(bufs[i]["loss"]), [Lo * scale]), grad=rel(t2n(bufs[i]["grad"]), grad * scale))
+        report(f"mixed batch kind={kind} sum={loss_sum} {w.name}", **e)
+        for k, v in e.items():
+            assert v < TOL, (w.name, k, v)
