@@ -538,9 +538,10 @@ def main():
         terms = r_tot["terms"].cpu().numpy()
         n_sets = 3 if w.loss.kind == W.LOSS_VACUUM else 2
         line["total_loss"] = {
-            "what": "L_phys + 10 L_IC + 10 L_sym + 10 L_energy: fused forward with tangents over the collocation "
-                    f"points, packed forward (no tangents) over their {n_sets - 1} mirror image set(s) and a "
-                    "4096-point IC plane, seeds, the same two adjoints",
+            "what": "L_phys + 10 L_IC + 10 L_sym + 10 L_energy: packed forward (no tangents) over the "
+                    f"{n_sets - 1} mirror image set(s) of the collocation points and a 4096-point IC plane, "
+                    "one fused pass over the collocation points (forward with tangents, residual, energy and "
+                    "symmetry seeds in the kernel, adjoint), the four terms, packed adjoint of the images",
             "points": P_total, "ic_points": 4096, "ms_per_step": round(t_tot * 1e3, 3),
             "collocation_evals_per_s": round(P_total / t_tot, 1),
             "relative_to_residual_only_step": round(t_tot / (ms_per_step / 1e3), 3),

@@ -226,10 +226,13 @@ qp_status qp_maxwell_fused(qp_ctx* ctx, const qp_circuit* c, const float* params
  *   L_energy mean over X of the squared local Poynting residual
  *            eps E dE/dt + Hx dHx/dt + Hy dHy/dt - (dE/dx Hy + E dHy/dx) + (dE/dy Hx + E dHx/dy)
  *            (eqs. Poynting_thm, Poynting_value_u, Poynting_value_S, energy_loss).
- * The mirror images couple points, so the call runs three stream-ordered phases over the set
- * [X; X_my; X_mx (vacuum); X_0]: forward (with tangents for X; the mirrored and initial-condition
- * points, whose terms use the fields alone, packed four to a thread group), per-point loss terms
- * and seeds, adjoint VJP (the same split).  points [P][3] (t, x, y) and ic_xy [P0][2] (x, y) are device buffers; out [P][m] and tan
+ * The mirror images couple points, so the call runs stream-ordered phases over the set
+ * [X; X_my; X_mx (vacuum); X_0]: the outputs of the mirrored and initial-condition points (whose
+ * terms use the fields alone; packed four to a thread group); one fused pass over X (forward
+ * with tangents, the residual, energy and symmetry seeds formed in the kernel from the point's
+ * fields and its images' outputs, adjoint); the four terms and the seeds of the mirrored and
+ * initial-condition points; their adjoint (packed).  points [P][3] (t, x, y) and ic_xy [P0][2]
+ * (x, y) are device buffers; out [P][m] and tan
  * [P][m][3] (of X, may be NULL); loss_terms: device double [5] = total, phys, IC, sym, energy;
  * d_params [K].  Point encodings only (cycled or random Fourier features): QP_EINVAL for the
  * angle-given encoding.  Flags: only QP_FLAG_GATES_FP32 (others: QP_EUNSUPPORTED).          */

@@ -378,7 +378,8 @@ qp_status qp::run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
 qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                         const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                         float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,
-                        float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override) {
+                        float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override,
+                        const float* f_mir, int n_mir, float w_sym, float w_energy) {
   hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
   const int n = c->hp.n;
@@ -399,7 +400,7 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
     if ((e = launch_rff(c->dplan, points, P, const_cast<float*>(ang), const_cast<float*>(jc), st)) != hipSuccess)
       return hipcheck(ctx, e, "rff angles");
   }
-  if (mode == kModeMaxwell && ld->kind == QP_LOSS_DIEL_SPLIT) {
+  if ((mode == kModeMaxwell || mode == kModeTotal) && ld->kind == QP_LOSS_DIEL_SPLIT) {
     if ((e = launch_count(points, P, ld->x_interface, counts, st)) != hipSuccess) return hipcheck(ctx, e, "count");
   }
   // packed modes: four points per thread group, so a tile covers four times the points
@@ -431,6 +432,10 @@ qp_status qp::run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float*
   a.mpart = reinterpret_cast<float*>(w + L.mpart);
   a.lpart = reinterpret_cast<float*>(w + L.lpart);
   a.n_mom = NM;
+  a.f_mir = f_mir;
+  a.n_mir = n_mir;
+  a.w_sym = w_sym;
+  a.w_energy = w_energy;
   a.d_angles = (mode == kModeMaxwell || mode == kModeVjp) ? d_angles : nullptr;
   a.d_jac = (mode == kModeMaxwell || mode == kModeVjp) ? d_jac : nullptr;
   if (mode_packed(mode)) { a.tan = nullptr; a.d_tan = nullptr; }
@@ -669,18 +674,25 @@ extern "C" qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float
   if (e != hipSuccess) return hipcheck(ctx, e, "total-loss points");
   if (kind == QP_LOSS_DIEL_SPLIT && (e = launch_count(points, P, d->phys.x_interface, counts, st)) != hipSuccess)
     return hipcheck(ctx, e, "count");
-  // Forward: the collocation points with their input tangents; the mirrored and initial-condition
-  // points (whose terms use the fields alone) by the packed kernel, four points per thread group.
+  // 1. The mirrored and initial-condition points (whose terms use the fields alone): outputs by the
+  //    packed forward kernel, four points per thread group.
   const int64_t P_rest = L.P_ext - P;
   const int m = c->hp.m;
   qp_status s = QP_OK;
-  if (P > 0 && (s = run_fused(ctx, c, kModeFwd, params, ext, nullptr, nullptr, P, nullptr, fo, fg, nullptr, nullptr,
-                              nullptr, nullptr, nullptr, nullptr, fws, gflags, 0, 0)) != QP_OK)
-    return s;
   if (P_rest > 0 && (s = run_fused(ctx, c, kModeFwdPk, params, ext + 3 * P, nullptr, nullptr, P_rest, nullptr,
                                    fo + (size_t)m * P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                    fws, gflags, 0, 0)) != QP_OK)
     return s;
+  // 2. The collocation points in one pass: forward with input tangents, the seeds of the residual,
+  //    energy and symmetry terms formed in the kernel from the point's own fields and its mirror
+  //    images' outputs, then the adjoint (their share of the gradient goes to d_params).
+  if ((P > 0 || P_rest == 0) &&
+      (s = run_fused(ctx, c, kModeTotal, params, ext, nullptr, nullptr, P, &d->phys, fo, fg, nullptr, nullptr, nullptr,
+                     c->hp.K > 0 ? d_params : nullptr, nullptr, nullptr, fws, gflags, 0, 0, fo + (size_t)m * P,
+                     L.with_mx ? 2 : 1, d->w_sym, d->w_energy)) != QP_OK)
+    return s;
+  // 3. The four terms, and the seeds of the mirrored and initial-condition points (the kernel also
+  //    writes the collocation points' seeds, which step 2 formed itself and nothing reads).
   TotalSeedArgs a{};
   a.out = fo; a.tan = fg; a.points = points; a.ic_xy = ic_xy;
   a.P = P; a.P0 = P0; a.ic_base = L.ic_base; a.m = c->hp.m; a.with_mx = L.with_mx;
@@ -695,14 +707,11 @@ extern "C" qp_status qp_total_loss(qp_ctx* ctx, const qp_circuit* c, const float
   if (tan && P > 0 && (e = hipMemcpyAsync(tan, fg, sizeof(float) * 3 * c->hp.m * P, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hipcheck(ctx, e, "copy tangents");
   if (c->hp.K == 0) return QP_OK;
-  // Adjoint: the same split; with both parts, the packed part's gradient goes to a scratch vector
-  // and is added (each part reduced over its workgroups in FP64, rounded once, then summed).
+  // 4. The adjoint of the mirrored and initial-condition points (packed kernel); with collocation
+  //    points as well, their gradient goes to a scratch vector and is added (each part reduced over
+  //    its workgroups in FP64, rounded once, then summed).
   const bool two = P > 0 && P_rest > 0;
   float* dtmp = reinterpret_cast<float*>(w + L.dtmp);
-  if ((P > 0 || P_rest == 0) &&
-      (s = run_fused(ctx, c, kModeVjp, params, ext, nullptr, nullptr, P, nullptr, nullptr, nullptr, dout, dtan, nullptr,
-                     d_params, nullptr, nullptr, fws, gflags, 0, 0)) != QP_OK)
-    return s;
   if (P_rest > 0 &&
       (s = run_fused(ctx, c, kModeVjpPk, params, ext + 3 * P, nullptr, nullptr, P_rest, nullptr, nullptr, nullptr,
                      dout + (size_t)m * P, nullptr, nullptr, two ? dtmp : d_params, nullptr, nullptr, fws, gflags, 0,

@@ -47,7 +47,8 @@ int n_moments(const qp_circuit* c);   // phase-stage moments of the fused adjoin
 qp_status run_fused(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                     const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                     float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params,
-                    float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override);
+                    float* d_angles, float* d_jac, void* ws, uint32_t flags, int exs_override, int grid_override,
+                    const float* f_mir = nullptr, int n_mir = 0, float w_sym = 0.f, float w_energy = 0.f);
 qp_status run_dense(qp_ctx* ctx, const qp_circuit* c, int mode, const float* params, const float* points,
                     const float* angles, const float* jac, int64_t P, const qp_maxwell_desc* ld, float* out,
                     float* tan, const float* d_out, const float* d_tan, double* loss, float* d_params, void* ws,

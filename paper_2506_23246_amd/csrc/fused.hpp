@@ -32,6 +32,9 @@ struct FusedArgs {
   float* d_angles;        // [P][n] dL/d angles (angle-given encoding) or null
   float* d_jac;           // [P][n][3] dL/d Jacobian or null
   int n_mom;              // phase-stage moments per workgroup partial (after the F * kGS statistics)
+  const float* f_mir;     // kModeTotal: outputs of the mirror images [n_mir][P][m] (y-mirror first)
+  int n_mir;              // kModeTotal: 1 (y-mirror) or 2 (and x-mirror)
+  float w_sym, w_energy;  // kModeTotal: weights of the symmetry and energy terms
 };
 
 int fused_threads(int n);

@@ -908,7 +908,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
   const uint32_t pbase = (uint32_t)ps * DIM;
   // loss weights: 1/P for the mean over all points, 1/N_vac and 1/N_diel for the split loss
   float w_all = 1.f, w_vac = 1.f, w_diel = 1.f;
-  if (MODE == kModeMaxwell && !a.loss_sum) {
+  if ((MODE == kModeMaxwell || MODE == kModeTotal) && !a.loss_sum) {
     w_all = a.P > 0 ? 1.f / (float)a.P : 0.f;
     if (a.loss_kind == QP_LOSS_DIEL_SPLIT) {
       const int nv = a.counts[0], nd = a.counts[1];
@@ -1154,7 +1154,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
     float Wv[kMaxOut][3], Vv[kMaxOut];
 #pragma unroll
     for (int i = 0; i < kMaxOut; ++i) { Vv[i] = 0.f; Wv[i][0] = Wv[i][1] = Wv[i][2] = 0.f; }
-    if (MODE == kModeMaxwell) {
+    if (MODE == kModeMaxwell || MODE == kModeTotal) {
       if (valid) {
         const float gEt = acc[1], gEx = acc[2], gEy = acc[3];
         const float gXt = acc[5], gXy = acc[7];
@@ -1176,6 +1176,26 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, int tile, float2*
         Wv[0][0] = A;  Wv[2][1] = -A * ie;  Wv[1][2] = A * ie;
         Wv[1][0] = Bq; Wv[0][2] += Bq;
         Wv[2][0] = C;  Wv[0][1] += -C;
+        if constexpr (MODE == kModeTotal) {
+          // the energy term, mean square of the local Poynting residual e (eq. energy_loss), and
+          // this point's share of the symmetry term (eq. 2D_symLoss) against its mirror images
+          const float E = acc[0], Hx = acc[4], Hy = acc[8];
+          const float e = eps * E * gEt + Hx * gXt + Hy * gYt - (gEx * Hy + E * gYx) + (gEy * Hx + E * gXy);
+          const float k = a.w_energy * 2.f * e * w;
+          Vv[0] += k * (eps * gEt - gYx + gXy);
+          Vv[1] += k * (gXt + gEy);
+          Vv[2] += k * (gYt - gEx);
+          Wv[0][0] += k * eps * E; Wv[0][1] += -k * Hy; Wv[0][2] += k * Hx;
+          Wv[1][0] += k * Hx;      Wv[1][2] += k * E;
+          Wv[2][0] += k * Hy;      Wv[2][1] += -k * E;
+          const float ks = a.w_sym * 2.f * w;
+          for (int j = 0; j < a.n_mir; ++j) {   // parities: y-mirror (+, -, +), x-mirror (+, +, -)
+            const float* fm = a.f_mir + ((long long)j * a.P + pt) * m;
+            Vv[0] += ks * (E - fm[0]);
+            Vv[1] += ks * (j == 0 ? Hx + fm[1] : Hx - fm[1]);
+            Vv[2] += ks * (j == 0 ? Hy - fm[2] : Hy + fm[2]);
+          }
+        }
       }
     } else if (PK) {   // output seeds of the four slots' points: slot 0 in Vv, slot c + 1 in Wv[.][c]
       if (a.d_out) {
@@ -1442,6 +1462,11 @@ hipError_t launch_fused_n(int mode, const FusedArgs& a, int grid, int exs, bool 
   if (mode == kModeFwd) {
     if (exs == 2) return launch_one<N, 2, kModeFwd, true>(a, grid, lds, st);
     return signs ? launch_one<N, 4, kModeFwd, true>(a, grid, lds, st) : launch_one<N, 4, kModeFwd, false>(a, grid, lds, st);
+  }
+  if (mode == kModeTotal) {
+    if (exs == 2) return launch_one<N, 2, kModeTotal, true>(a, grid, lds, st);
+    return signs ? launch_one<N, 4, kModeTotal, true>(a, grid, lds, st)
+                 : launch_one<N, 4, kModeTotal, false>(a, grid, lds, st);
   }
   if (mode == kModeMaxwell) {
     if (exs == 2) return launch_one<N, 2, kModeMaxwell, true>(a, grid, lds, st);

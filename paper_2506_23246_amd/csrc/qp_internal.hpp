@@ -131,7 +131,9 @@ QP_HD inline constexpr int phase_terms(int n) { return n + n * (n - 1) / 2; }
 // Fused-kernel modes.  The packed modes carry no input tangents: the four statevector slots of a
 // thread group hold four consecutive points (forward: outputs only; VJP: output seeds only, the
 // adjoint slots holding each point's lambda), so a point costs a quarter of a tangent-carrying one.
-enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2, kModeFwdPk = 3, kModeVjpPk = 4 };
+// kModeTotal: the Maxwell step of the paper's total loss over the collocation points (residual,
+// energy and symmetry seeds formed in the kernel; the mirror images' outputs come from memory).
+enum Mode : int { kModeFwd = 0, kModeMaxwell = 1, kModeVjp = 2, kModeFwdPk = 3, kModeVjpPk = 4, kModeTotal = 5 };
 QP_HD inline constexpr bool mode_packed(int mode) { return mode == kModeFwdPk || mode == kModeVjpPk; }
 QP_HD inline constexpr bool mode_fwd_only(int mode) { return mode == kModeFwd || mode == kModeFwdPk; }
 

@@ -1,15 +1,17 @@
 // The paper's total loss on the GPU (eq. 2D_lossTot): L_phys + w_ic L_IC + w_sym L_sym + w_energy L_energy.
 //
-// The symmetry term couples a collocation point with its mirror images, so the step runs in three
+// The symmetry term couples a collocation point with its mirror images, so the step runs in
 // stream-ordered phases over an extended point set [X; X_my; X_mx (vacuum only); X_0]:
-//   1. the fused forward kernels: outputs and input tangents of the collocation points X, outputs
-//      alone of the mirrored and initial-condition points (packed kernel, four points per group),
-//   2. k_total_seeds: per collocation point the residual, energy and symmetry terms and their
-//      seeds d L_tot / d(f, g) for the point and d L_tot / d f for its images, per
-//      initial-condition point the IC term and its seed d L_tot / d f; FP32 per-block partial
-//      sums of the four terms,
-//   3. the fused VJP kernels with those seeds (adjoint with uncompute; the packed kernel for the
-//      points seeded through f alone), then the FP64 reductions.
+//   1. the packed forward kernel: outputs of the mirrored and initial-condition points,
+//   2. one fused pass over the collocation points X (kModeTotal): forward with input tangents,
+//      the seeds d L_tot / d(f, g) of the residual, energy and symmetry terms formed in the kernel
+//      from the point's own fields and its images' outputs, adjoint with uncompute,
+//   3. k_total_seeds: the four terms (per collocation point the residual, energy and symmetry
+//      terms, per initial-condition point the IC term; FP32 per-block partial sums) and the seeds
+//      d L_tot / d f of the mirrored and initial-condition points (it also writes the collocation
+//      points' seeds, which phase 2 formed itself),
+//   4. the packed VJP kernel over the mirrored and initial-condition points, then the FP64
+//      reductions.
 // The loss terms are summed across blocks in FP64 in a fixed order (k_total_reduce).
 #include <hip/hip_runtime.h>
 
