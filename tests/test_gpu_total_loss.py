@@ -47,6 +47,29 @@ def test_total_loss_matches_oracle(ctx, k, P, P0):
     assert all(v < TOL for v in errs.values()), errs
 
 
+def test_total_loss_parameter_free_circuit(ctx):
+    """A circuit with no trainable gate (K = 0, entangler rings only): the collocation pass forms
+    no gradient; the four terms, outputs and tangents against the oracle."""
+    from paper_2506_23246_amd.api import Circuit
+    circ = W.Circuit(n=5, gates=W.ring(5, W.CNOT, 1) + W.ring(5, W.CZ, 2), n_params=0)
+    params = np.zeros(0, np.float32)
+    rng = np.random.default_rng(77)
+    pts = rng.uniform(-1, 1, (70, 3)).astype(np.float32)
+    xy = _ic(20, 78)
+    desc = W.TotalLossDesc(phys=W.MaxwellDesc(W.LOSS_VACUUM))
+    c = Circuit(ctx, circ)
+    r = c.total_loss(params, pts, xy, desc, outputs=True)
+    terms, _ = O.total_eval(circ, params, pts, xy, desc)
+    got = t2n(r["terms"])
+    ref = np.array([terms["total"], terms["phys"], terms["ic"], terms["sym"], terms["energy"]])
+    errs = {name: rel([got[i]], [ref[i]]) if ref[i] != 0 else abs(got[i])
+            for i, name in enumerate(["total", "phys", "ic", "sym", "energy"])}
+    f, g = O.simulate(circ, params, pts)
+    errs["f"], errs["g"] = rel(t2n(r["out"]), f), rel(t2n(r["tan"]), g)
+    report("total loss K=0", **errs)
+    assert all(v < TOL for v in errs.values()), errs
+
+
 def test_total_loss_full_size_terms_follow_from_outputs(ctx):
     """12 qubits x 8 layers at 262144 collocation points and a 4096-point IC plane: the four terms
     equal the oracle's loss function applied to the library's outputs and tangents of the four
